@@ -1,0 +1,259 @@
+"""ctypes binding of the CPU oracle (``gc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``, never by the product package.
+The oracle is a plain single-threaded C transcription of the method; it shares
+no code with the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, ERR_ARG, ERR_GRAPH, ERR_COLORING, ERR_OOM, ERR_NOT_CONVERGED = 0, 1, 2, 3, 4, 6
+FIRST_FIT, RANDOM_X = 0, 1
+PERM_REVERSE, PERM_NONINC, PERM_NONDEC, PERM_RANDOM = 0, 1, 2, 3
+FIXED_PRIORITY = 1
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("num_colors", ctypes.c_int32), ("max_color", ctypes.c_int32),
+                ("_pad", ctypes.c_int32), ("losers_total", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"rounds": self.rounds, "num_colors": self.num_colors, "max_color": self.max_color,
+                "losers_total": self.losers_total}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle (plain C, -O2, single-threaded) into liboracle.so."""
+    src = os.path.join(_HERE, "gc_oracle.c")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+    sig = {
+        "orc_mix64": (u64, [u64]),
+        "orc_fmix32": (u32, [u32]),
+        "orc_stream": (u32, [u64, u32, u32]),
+        "orc_prio": (u32, [u64, u32, u32]),
+        "orc_key": (u64, [u64, u32, u32]),
+        "orc_pick": (u32, [u64, u32, u32, u32]),
+        "orc_bounded": (u32, [u64, u32, u32, u32]),
+        "orc_graph_seed": (u64, [u64, u32]),
+        "orc_greedy_seq": (ctypes.c_int, [i32, i32p, i32p, i32p, i32p]),
+        "orc_count": (ctypes.c_int, [i32, i32p, i32p, i32p]),
+        "orc_validate": (ctypes.c_int, [i32, i32p, i32p, i32p, i64p, i64p]),
+        "orc_check_csr": (ctypes.c_int, [i32, i32p, i32p]),
+        "orc_init_color": (ctypes.c_int, [i32, i32p, i32p, i32, i32, u64, i32, u32, i32p,
+                                          ctypes.POINTER(Stats), i64p, i64p, i32]),
+        "orc_class_order": (i32, [i32, i64p, i32, u64, i32, i32p]),
+        "orc_recolor": (ctypes.c_int, [i32, i32p, i32p, i32, u64, i32, i32p, i32p, i32p, i32p,
+                                       ctypes.POINTER(Stats)]),
+        "orc_schedule_perm": (i32, [i32, i32, i32, i32]),
+        "orc_chromatic": (i32, [i32, i32p, i32p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _p64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, np.int32)
+    return rp, col
+
+
+# ---- hash ----
+def mix64(z):
+    return int(_load().orc_mix64(z & (2**64 - 1)))
+
+
+def fmix32(h):
+    return int(_load().orc_fmix32(h & 0xFFFFFFFF))
+
+
+def stream(seed, tag, r):
+    return int(_load().orc_stream(seed, tag, r))
+
+
+def prio(seed, r, v):
+    return int(_load().orc_prio(seed, r, v))
+
+
+def key(seed, r, v):
+    return int(_load().orc_key(seed, r, v))
+
+
+def pick(seed, r, v, X):
+    return int(_load().orc_pick(seed, r, v, X))
+
+
+def bounded(seed, p, i, m):
+    return int(_load().orc_bounded(seed, p, i, m))
+
+
+def graph_seed(base, g):
+    return int(_load().orc_graph_seed(base, g))
+
+
+# ---- algorithms ----
+def greedy_seq(g, order=None) -> np.ndarray:
+    """Algorithm 1 (sequential greedy First Fit) over `order` (natural when None)."""
+    rp, col = _csr(g)
+    c = np.zeros(max(g.n, 1), np.int32)
+    o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+    rc = _load().orc_greedy_seq(g.n, _p32(rp), _p32(col), None if o is None else _p32(o), _p32(c))
+    if rc:
+        raise RuntimeError(f"orc_greedy_seq: {rc}")
+    return c[:g.n]
+
+
+def count(colors) -> tuple[int, int]:
+    c = np.ascontiguousarray(colors, dtype=np.int32)
+    num, mx = ctypes.c_int32(), ctypes.c_int32()
+    rc = _load().orc_count(c.size, _p32(c) if c.size else _p32(np.zeros(1, np.int32)), ctypes.byref(num),
+                           ctypes.byref(mx))
+    if rc:
+        raise RuntimeError(f"orc_count: {rc}")
+    return num.value, mx.value
+
+
+def validate(g, colors) -> tuple[int, int]:
+    rp, col = _csr(g)
+    c = np.ascontiguousarray(colors, dtype=np.int32)
+    if c.size == 0:
+        c = np.zeros(1, np.int32)
+    cf, un = ctypes.c_int64(), ctypes.c_int64()
+    _load().orc_validate(g.n, _p32(rp), _p32(col), _p32(c), ctypes.byref(cf), ctypes.byref(un))
+    return cf.value, un.value
+
+
+def check_csr(g) -> int:
+    rp, col = _csr(g)
+    return int(_load().orc_check_csr(g.n, _p32(rp), _p32(col)))
+
+
+class InitResult:
+    def __init__(self, status, colors, stats, w_sizes, w_degsum):
+        self.status = status
+        self.colors = colors
+        self.stats = stats
+        self.w_sizes = w_sizes
+        self.w_degsum = w_degsum
+
+    @property
+    def rounds(self):
+        return self.stats["rounds"]
+
+
+def init_color(g, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0, w_cap=None) -> InitResult:
+    """Speculative round-synchronous initial coloring (section 2.2 framework)."""
+    rp, col = _csr(g)
+    c = np.zeros(max(g.n, 1), np.int32)
+    cap = (g.n + 2) if w_cap is None else w_cap
+    ws = np.zeros(max(cap, 1), np.int64)
+    wd = np.zeros(max(cap, 1), np.int64)
+    st = Stats()
+    rc = _load().orc_init_color(g.n, _p32(rp), _p32(col), select, X, seed, max_rounds, flags, _p32(c),
+                                ctypes.byref(st), _p64(ws), _p64(wd), cap)
+    if rc not in (OK, ERR_NOT_CONVERGED):
+        raise RuntimeError(f"orc_init_color: {rc}")
+    r = min(st.rounds, cap)
+    return InitResult(rc, c[:g.n], st.as_dict(), ws[:r].copy(), wd[:r].copy())
+
+
+class RecolorResult:
+    def __init__(self, status, colors, stats, pi):
+        self.status = status
+        self.colors = colors
+        self.stats = stats
+        self.pi = pi
+
+
+def class_order(sizes_by_color, perm, seed=1, pass_=0) -> np.ndarray:
+    """Class permutation pi for sizes_by_color[c] (index 0 ignored)."""
+    s = np.ascontiguousarray(sizes_by_color, dtype=np.int64)
+    maxc = s.size - 1
+    pi = np.zeros(max(maxc, 1), np.int32)
+    k = _load().orc_class_order(maxc, _p64(s), perm, seed, pass_, _p32(pi))
+    return pi[:k].copy()
+
+
+def recolor(g, colors, perm=PERM_REVERSE, seed=1, pass_=0) -> RecolorResult:
+    """One Culberson recoloring pass over the color classes in order pi."""
+    rp, col = _csr(g)
+    c_old = np.ascontiguousarray(colors, dtype=np.int32)
+    if c_old.size == 0:
+        c_old = np.zeros(1, np.int32)
+    c_new = np.zeros(max(g.n, 1), np.int32)
+    maxc = int(c_old[:g.n].max()) if g.n > 0 else 0
+    pi = np.zeros(max(maxc, 1), np.int32)
+    k = ctypes.c_int32()
+    st = Stats()
+    rc = _load().orc_recolor(g.n, _p32(rp), _p32(col), perm, seed, pass_, _p32(c_old), _p32(c_new), _p32(pi),
+                             ctypes.byref(k), ctypes.byref(st))
+    if rc:
+        return RecolorResult(rc, None, None, None)
+    return RecolorResult(rc, c_new[:g.n], st.as_dict(), pi[:k.value].copy())
+
+
+def schedule_perm(kind, base, x, t) -> int:
+    return int(_load().orc_schedule_perm(kind, base, x, t))
+
+
+def chromatic(g) -> int:
+    rp, col = _csr(g)
+    return int(_load().orc_chromatic(g.n, _p32(rp), _p32(col)))
+
+
+def run_pipeline(g, select, X, seed, perm_schedule, max_rounds=0):
+    """Initial coloring followed by one recoloring pass per entry of perm_schedule.
+
+    Returns (init_result, [recolor_result, ...]); pass p uses class order
+    perm_schedule[p] and pass index p."""
+    ini = init_color(g, select, X, seed, max_rounds)
+    out = []
+    c = ini.colors
+    for p, perm in enumerate(perm_schedule):
+        r = recolor(g, c, perm, seed, p)
+        if r.status:
+            raise RuntimeError(f"orc_recolor: {r.status}")
+        out.append(r)
+        c = r.colors
+    return ini, out
