@@ -1,0 +1,230 @@
+/*
+ * gc.h - C ABI of libgc.so: speculative distance-1 graph coloring with
+ * iterated recoloring on AMD MI355X (gfx950), after Sariyuce, Saule and
+ * Catalyurek, "On Distributed Graph Coloring with Iterative Recoloring".
+ *
+ * Problem (paper, section 1): a distance-1 coloring maps every vertex to a
+ * positive integer so that the two ends of every edge differ.  Here colors
+ * are int32, 1-based; 0 means "not colored".
+ *
+ * Graphs are int32 CSR in device memory: row_ptr[n+1] (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n] = nnz) and col_idx[nnz] with ids in [0, n).
+ * The CSR must be symmetric (every entry (u, w) has a matching (w, u)) with
+ * no self-loops; duplicate entries and the order inside a row do not change
+ * any result.  gc_check_csr verifies these preconditions; the other calls do
+ * not, but every kernel clamps row ranges to [0, nnz] and ignores neighbor ids
+ * outside [0, n), so a malformed graph gives wrong colors, never an
+ * out-of-bounds access.
+ *
+ * Ownership: every graph and color pointer is a DEVICE pointer owned by the
+ * caller, which keeps it alive until the work queued on `stream` is done.
+ * The library keeps no pointer after a call returns.  A gc_ctx owns all
+ * device workspace (sized at creation) and must not be used by two host
+ * threads at once; use one context per concurrent stream.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Calls enqueue their kernels on it.  Calls whose results are host
+ * values (gc_validate, gc_count_colors, gc_check_csr, and any call given a
+ * non-NULL gc_stats) synchronize that stream before returning.
+ *
+ * Errors: every call returns a gc_status; nothing aborts and no C++
+ * exception crosses the ABI.  gc_ctx_last_error gives a message for the last
+ * failure on a context.
+ */
+#ifndef GC_H
+#define GC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gc_status {
+    GC_OK = 0,
+    GC_ERR_ARG = 1,            /* bad argument (NULL pointer, size above the context's capacity, ...) */
+    GC_ERR_GRAPH = 2,          /* gc_check_csr: the CSR breaks a precondition */
+    GC_ERR_COLORING = 3,       /* gc_recolor: input coloring has a color <= 0 or above the capacity */
+    GC_ERR_OOM = 4,            /* device or host allocation failed */
+    GC_ERR_DEVICE = 5,         /* a HIP runtime call failed, or a kernel's bounded wait ran out */
+    GC_ERR_NOT_CONVERGED = 6   /* gc_init_color stopped at max_rounds with vertices still uncolored */
+} gc_status;
+
+/* Color selection of the initial coloring. */
+typedef enum gc_select {
+    GC_FIRST_FIT = 0,  /* smallest permissible color (section 2.1, First Fit) */
+    GC_RANDOM_X = 1    /* uniform among the first X permissible colors (section 3.2, Random-X Fit) */
+} gc_select;
+
+/* Order in which a recoloring pass visits the color classes (section 3). */
+typedef enum gc_perm {
+    GC_PERM_REVERSE = 0,  /* RV: decreasing color */
+    GC_PERM_NONINC = 1,   /* NI: non-increasing class size, ties by increasing color */
+    GC_PERM_NONDEC = 2,   /* ND: non-decreasing class size, ties by increasing color */
+    GC_PERM_RANDOM = 3    /* RAND: Knuth shuffle of the increasing color list */
+} gc_perm;
+
+/* gc_init_color flags */
+#define GC_FLAG_FIXED_PRIORITY 1u /* one random total order for all rounds (round 0's keys) */
+
+/* Largest X accepted by GC_RANDOM_X. */
+#define GC_MAX_X 1024
+
+typedef struct gc_ctx gc_ctx;
+
+typedef struct gc_csr {
+    int32_t n;                /* vertices */
+    int32_t reserved;         /* set to 0 */
+    int64_t nnz;              /* adjacency entries (2 x undirected edges); must be < 2^31 */
+    const int32_t *row_ptr;   /* device, n + 1 */
+    const int32_t *col_idx;   /* device, nnz */
+} gc_csr;
+
+/*
+ * Statistics of one call (host struct).  round_sizes / round_degsum are
+ * optional host arrays of round_cap entries: |W_r| (vertices colored
+ * tentatively in round r) and the sum of their degrees.
+ */
+typedef struct gc_stats {
+    int32_t rounds;        /* init: rounds run (1 = no conflict; 0 iff n = 0); recolor: 0 */
+    int32_t num_colors;    /* distinct colors in the output */
+    int32_t max_color;     /* largest color in the output */
+    int32_t k_classes;     /* recolor: non-empty classes of the input coloring; init: 0 */
+    int64_t losers_total;  /* init: sum over rounds of |W_r|, minus n */
+    int64_t *round_sizes;  /* host, round_cap entries, or NULL */
+    int64_t *round_degsum; /* host, round_cap entries, or NULL */
+    int32_t round_cap;
+    int32_t reserved;
+} gc_stats;
+
+/* Tuning knobs.  No knob changes any result, only the speed. */
+typedef struct gc_tuning {
+    int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
+    int32_t deg_small;     /* rows with degree <= deg_small: one lane per vertex */
+    int32_t deg_wave;      /* rows with degree > deg_wave: one wavefront per vertex; in between, lane groups */
+    int32_t group;         /* lanes per vertex for the middle bin (power of two, 2..64) */
+    int32_t grid_per_cu;   /* workgroups per compute unit for persistent kernels */
+    int32_t reserved[3];
+} gc_tuning;
+
+const char *gc_status_string(gc_status s);
+
+/*
+ * Create a context on HIP device `device` able to color graphs with up to
+ * max_n vertices and max_nnz adjacency entries.  Allocates every workspace
+ * buffer once (roughly 40 bytes per vertex).  *out is NULL on failure.
+ */
+gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, gc_ctx **out);
+void gc_ctx_destroy(gc_ctx *ctx);
+const char *gc_ctx_last_error(const gc_ctx *ctx);
+gc_status gc_ctx_get_tuning(const gc_ctx *ctx, gc_tuning *t);
+gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t);
+
+/*
+ * Check the CSR preconditions on the device: row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz, ids in [0, n), no self-loops, symmetric with multiplicity
+ * (checked by per-entry reverse search, so rows must be sorted for it to be
+ * fast; unsorted rows are still checked correctly).  Returns GC_OK or
+ * GC_ERR_GRAPH.  Synchronizes the stream.
+ */
+gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream);
+
+/*
+ * Speculative initial coloring (section 2.2 framework, run as one superstep
+ * per round over every uncolored vertex).  Round r: every vertex v of the
+ * uncolored set W_r takes a tentative color from the colors its neighbors
+ * held at the start of the round: the (j+1)-th smallest positive color not
+ * among them, j = 0 for First Fit and j = hash(seed, v, r) mapped to [0, X)
+ * for Random-X Fit (section 3.2).  Then v loses if a neighbor in W_r has the
+ * same tentative color and a larger priority key (a hash of seed, vertex and
+ * round; the random total order of section 2.2), losers form W_{r+1}, winners
+ * keep their colors.  Repeats until no vertex loses.
+ *
+ * colors (device, n, output) receives the coloring.  max_rounds = 0 means no
+ * limit (the process always ends within n rounds); with a limit, the call
+ * returns GC_ERR_NOT_CONVERGED after that many rounds, with the vertices
+ * still uncolored at <= 0.  X must be in [1, GC_MAX_X] for GC_RANDOM_X and is
+ * ignored for GC_FIRST_FIT.
+ */
+gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                        int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream);
+
+/*
+ * One iterated-greedy recoloring pass (section 2.1, Culberson's Iterated
+ * Greedy; section 3, synchronous recoloring RC).  The classes of colors_in
+ * are visited in the order `perm` picks; every vertex of the current class
+ * takes the smallest positive color not held by a neighbor recolored earlier
+ * in this pass.  The result never has more colors than the input.
+ *
+ * colors_in (device, n): a proper coloring with colors in [1, n + GC_MAX_X];
+ * colors_out (device, n) may equal colors_in (in place).  `pass` is the pass
+ * index that seeds GC_PERM_RANDOM (with `seed`).  An input color outside the
+ * range gives GC_ERR_COLORING when st != NULL (checked at the synchronization
+ * the stats need); without stats such input leaves colors_out unspecified.
+ */
+gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                     const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
+
+/*
+ * conflict_edges: adjacency entries (u, w) with u < w and colors[u] ==
+ * colors[w] > 0 (each undirected edge once); uncolored: vertices with
+ * colors[v] <= 0.  Host outputs; synchronizes.  Either pointer may be NULL.
+ */
+gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
+                      int64_t *uncolored, void *stream);
+
+/*
+ * num_colors: distinct positive values in colors[0..n); max_color: the
+ * largest (0 if none).  Host outputs; synchronizes.
+ */
+gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors, int32_t *max_color,
+                          void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched coloring: many independent graphs in one persistent launch.
+ *
+ * Packed CSR: graph g has n_g = vtx_off[g+1] - vtx_off[g] vertices and
+ * nnz_g = edge_off[g+1] - edge_off[g] entries; its local row_ptr (n_g + 1
+ * entries, values in [0, nnz_g]) is at row_ptr + vtx_off[g] + g, its local
+ * col_idx (ids in [0, n_g)) at col_idx + edge_off[g], and its colors at
+ * colors + vtx_off[g].  Offsets are int64 (the packed arrays may exceed 2^31
+ * entries); each graph must have n_g <= 2^31 - 1 and nnz_g < 2^31.
+ */
+typedef struct gc_batch_csr {
+    int32_t num_graphs;
+    int32_t reserved;
+    const int64_t *vtx_off;   /* device, G + 1 */
+    const int64_t *edge_off;  /* device, G + 1 */
+    const int32_t *row_ptr;   /* device, vtx_off[G] + G */
+    const int32_t *col_idx;   /* device, edge_off[G] */
+} gc_batch_csr;
+
+/* Per-graph result of gc_batch_color (device array of G entries). */
+typedef struct gc_graph_stats {
+    int32_t rounds;          /* initial-coloring rounds */
+    int32_t colors_init;     /* distinct colors after the initial coloring */
+    int32_t colors_final;    /* colors after the last pass */
+    int32_t status;          /* gc_status of this graph (GC_ERR_NOT_CONVERGED if max_rounds hit) */
+} gc_graph_stats;
+
+/*
+ * Color every graph of the batch: initial coloring with seed_g, then `passes`
+ * recoloring passes with class order `perm` (pass index p = 0..passes-1).
+ * seed_g = mix64(base_seed + 0x9E3779B97F4A7C15 * (4 << 32 | g)) (SplitMix64
+ * output function), so that gc_init_color / gc_recolor called on graph g
+ * alone with seed_g give the same colors bit for bit.  max_vertices_per_graph
+ * bounds n_g (the caller knows it; it sizes the workspace).  per_graph may be
+ * NULL.  Asynchronous on `stream`.
+ */
+gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+                         int32_t passes, uint64_t base_seed, int32_t max_rounds, int32_t max_vertices_per_graph,
+                         int32_t *colors, gc_graph_stats *per_graph, void *stream);
+
+/* seed_g of graph g in a batch (host helper, same formula as above). */
+uint64_t gc_batch_graph_seed(uint64_t base_seed, int32_t g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GC_H */

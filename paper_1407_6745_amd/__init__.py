@@ -1,0 +1,339 @@
+"""Python binding of libgc (speculative graph coloring with iterated
+recoloring on MI355X).  Argument marshalling only: every step of the method
+runs in the HIP kernels of ``libgc.so``; torch provides device memory and
+streams.  The binding refuses to run without the built library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgc.so")
+
+OK, ERR_ARG, ERR_GRAPH, ERR_COLORING, ERR_OOM, ERR_DEVICE, ERR_NOT_CONVERGED = 0, 1, 2, 3, 4, 5, 6
+FIRST_FIT, RANDOM_X = 0, 1
+PERM_REVERSE, PERM_NONINC, PERM_NONDEC, PERM_RANDOM = 0, 1, 2, 3
+PERM_NAMES = {"RV": PERM_REVERSE, "NI": PERM_NONINC, "ND": PERM_NONDEC, "RAND": PERM_RANDOM}
+FLAG_FIXED_PRIORITY = 1
+MAX_X = 1024
+
+
+class GCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class CSRArgs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class StatsArgs(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("num_colors", ctypes.c_int32), ("max_color", ctypes.c_int32),
+                ("k_classes", ctypes.c_int32), ("losers_total", ctypes.c_int64),
+                ("round_sizes", ctypes.POINTER(ctypes.c_int64)), ("round_degsum", ctypes.POINTER(ctypes.c_int64)),
+                ("round_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("deg_small", ctypes.c_int32), ("deg_wave", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class BatchArgs(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32), ("vtx_off", ctypes.c_void_p),
+                ("edge_off", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+# name -> (restype, argtypes); every symbol the C header declares
+_SIGS = {
+    "gc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gc_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
+    "gc_ctx_destroy": (None, [ctypes.c_void_p]),
+    "gc_ctx_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gc_ctx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "gc_ctx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "gc_check_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_void_p]),
+    "gc_init_color": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p,
+                                     ctypes.POINTER(StatsArgs), ctypes.c_void_p]),
+    "gc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
+                                  ctypes.c_void_p]),
+    "gc_validate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "gc_count_colors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "gc_batch_color": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchArgs), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gc_batch_graph_seed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32]),
+}
+
+
+def lib():
+    """The loaded libgc.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+        return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().gc_status_string(s).decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns a gc_ctx (device workspace) for graphs up to max_n / max_nnz."""
+
+    def __init__(self, max_n: int, max_nnz: int = 0, device: int | None = None):
+        torch = _torch()
+        self.device = torch.cuda.current_device() if device is None else device
+        self.max_n = int(max_n)
+        self.max_nnz = int(max_nnz)
+        h = ctypes.c_void_p()
+        rc = lib().gc_ctx_create(self.device, self.max_n, self.max_nnz, ctypes.byref(h))
+        if rc:
+            raise GCError(rc, f"gc_ctx_create(max_n={max_n}): {status_string(rc)}")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().gc_ctx_last_error(self.handle).decode()
+
+    def check(self, rc, what):
+        if rc not in (OK,):
+            raise GCError(rc, f"{what}: {status_string(rc)}: {self.last_error()}")
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        self.check(lib().gc_ctx_get_tuning(self.handle, ctypes.byref(t)), "gc_ctx_get_tuning")
+        return {"block": t.block, "deg_small": t.deg_small, "deg_wave": t.deg_wave, "group": t.group,
+                "grid_per_cu": t.grid_per_cu}
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self.check(lib().gc_ctx_get_tuning(self.handle, ctypes.byref(t)), "gc_ctx_get_tuning")
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self.check(lib().gc_ctx_set_tuning(self.handle, ctypes.byref(t)), "gc_ctx_set_tuning")
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def default_context(n: int, nnz: int = 0) -> Context:
+    """Per-device context, regrown when a larger graph arrives."""
+    torch = _torch()
+    dev = torch.cuda.current_device()
+    c = _default_ctx.get(dev)
+    if c is None or c.max_n < n or c.max_nnz < nnz:
+        if c is not None:
+            torch.cuda.synchronize()
+            c.close()
+        c = Context(max(n, 1024), max(nnz, 1024), dev)
+        _default_ctx[dev] = c
+    return c
+
+
+def _check_i32_dev(t, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous torch.int32 CUDA (HIP) tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+
+
+def _csr_args(row_ptr, col_idx) -> CSRArgs:
+    _check_i32_dev(row_ptr, "row_ptr")
+    _check_i32_dev(col_idx, "col_idx")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr needs n + 1 >= 1 entries")
+    return CSRArgs(n, 0, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+
+
+def _stats_dict(st: StatsArgs, sizes=None, degsum=None) -> dict:
+    d = {"rounds": st.rounds, "num_colors": st.num_colors, "max_color": st.max_color, "k_classes": st.k_classes,
+         "losers_total": st.losers_total}
+    if sizes is not None:
+        r = min(st.rounds, len(sizes))
+        d["round_sizes"] = sizes[:r].tolist()
+        d["round_degsum"] = degsum[:r].tolist()
+    return d
+
+
+def init_color(row_ptr, col_idx, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0, out=None, stats=True,
+               round_cap=4096, ctx: Context | None = None, stream=None, allow_not_converged=False):
+    """Speculative initial coloring; returns (colors int32 tensor, stats dict or None)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.int32, device=row_ptr.device)
+    _check_i32_dev(out, "out", g.n)
+    st = None
+    sizes = degsum = None
+    if stats:
+        sizes = np.zeros(round_cap, np.int64)
+        degsum = np.zeros(round_cap, np.int64)
+        st = StatsArgs()
+        st.round_sizes = sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.round_degsum = degsum.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        st.round_cap = round_cap
+    rc = lib().gc_init_color(ctx.handle, ctypes.byref(g), select, X, seed, max_rounds, flags,
+                             out.data_ptr() if g.n else None, ctypes.byref(st) if st is not None else None,
+                             _stream_ptr(stream))
+    if not (rc == ERR_NOT_CONVERGED and allow_not_converged):
+        ctx.check(rc, "gc_init_color")
+    d = _stats_dict(st, sizes, degsum) if st is not None else None
+    if d is not None:
+        d["status"] = rc
+    return out, d
+
+
+def recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,
+            ctx: Context | None = None, stream=None):
+    """One recoloring pass; `out` may be `colors` (in place).  Returns (colors, stats or None)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty_like(colors)
+    _check_i32_dev(out, "out", g.n)
+    st = StatsArgs() if stats else None
+    rc = lib().gc_recolor(ctx.handle, ctypes.byref(g), perm, seed, pass_, colors.data_ptr() if g.n else None,
+                          out.data_ptr() if g.n else None, ctypes.byref(st) if st is not None else None,
+                          _stream_ptr(stream))
+    ctx.check(rc, "gc_recolor")
+    return out, (_stats_dict(st) if st is not None else None)
+
+
+def validate(row_ptr, col_idx, colors, ctx: Context | None = None, stream=None):
+    """(conflicting edges, uncolored vertices)."""
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    cf, un = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().gc_validate(ctx.handle, ctypes.byref(g), colors.data_ptr() if g.n else None, ctypes.byref(cf),
+                           ctypes.byref(un), _stream_ptr(stream))
+    ctx.check(rc, "gc_validate")
+    return cf.value, un.value
+
+
+def count_colors(colors, ctx: Context | None = None, stream=None):
+    """(distinct positive colors, max color)."""
+    _check_i32_dev(colors, "colors")
+    n = colors.numel()
+    ctx = ctx or default_context(n)
+    num, mx = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().gc_count_colors(ctx.handle, n, colors.data_ptr() if n else None, ctypes.byref(num), ctypes.byref(mx),
+                               _stream_ptr(stream))
+    ctx.check(rc, "gc_count_colors")
+    return num.value, mx.value
+
+
+def check_csr(row_ptr, col_idx, ctx: Context | None = None, stream=None) -> int:
+    """GC_OK (0) or GC_ERR_GRAPH (2)."""
+    g = _csr_args(row_ptr, col_idx)
+    ctx = ctx or default_context(g.n, g.nnz)
+    rc = lib().gc_check_csr(ctx.handle, ctypes.byref(g), _stream_ptr(stream))
+    if rc not in (OK, ERR_GRAPH):
+        ctx.check(rc, "gc_check_csr")
+    return rc
+
+
+def batch_graph_seed(base_seed: int, g: int) -> int:
+    return int(lib().gc_batch_graph_seed(base_seed, g))
+
+
+GRAPH_STATS_FIELDS = ("rounds", "colors_init", "colors_final", "status")
+
+
+def batch_color(vtx_off, edge_off, row_ptr, col_idx, select=RANDOM_X, X=4, perm=PERM_REVERSE, passes=5, base_seed=1,
+                max_rounds=0, max_vertices_per_graph=None, out=None, per_graph=None, ctx: Context | None = None,
+                stream=None):
+    """Color every graph of a packed batch in one persistent launch (asynchronous).
+
+    Returns (colors, per_graph int32 tensor of shape (G, 4): rounds, colors_init, colors_final, status)."""
+    torch = _torch()
+    for t, nm in ((vtx_off, "vtx_off"), (edge_off, "edge_off")):
+        if t.dtype != torch.int64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous torch.int64 CUDA tensor")
+    _check_i32_dev(row_ptr, "row_ptr")
+    _check_i32_dev(col_idx, "col_idx")
+    G = vtx_off.numel() - 1
+    total_v = row_ptr.numel() - G
+    if max_vertices_per_graph is None:
+        max_vertices_per_graph = int((vtx_off[1:] - vtx_off[:-1]).max().item()) if G > 0 else 0
+    ctx = ctx or default_context(max(max_vertices_per_graph, 1))
+    if out is None:
+        out = torch.empty(max(total_v, 0), dtype=torch.int32, device=row_ptr.device)
+    if per_graph is None:
+        per_graph = torch.empty((max(G, 0), 4), dtype=torch.int32, device=row_ptr.device)
+    b = BatchArgs(G, 0, vtx_off.data_ptr(), edge_off.data_ptr(), row_ptr.data_ptr(),
+                  col_idx.data_ptr() if col_idx.numel() else None)
+    rc = lib().gc_batch_color(ctx.handle, ctypes.byref(b), select, X, perm, passes, base_seed, max_rounds,
+                              int(max_vertices_per_graph), out.data_ptr() if out.numel() else None,
+                              per_graph.data_ptr() if G > 0 else None, _stream_ptr(stream))
+    ctx.check(rc, "gc_batch_color")
+    return out, per_graph
+
+
+def schedule_perm(kind: int, base: int, x: int, t: int) -> int:
+    """Class order of iteration t (1-based) under a hybrid schedule:
+    kind 0 = `base` every time; 1 = ND-RAND%x; 2 = ND-RAND%2^i (RAND at t = 2, 4, 8, ...)."""
+    if kind == 1:
+        return PERM_RANDOM if x > 0 and t % x == 0 else PERM_NONDEC
+    if kind == 2:
+        return PERM_RANDOM if t >= 2 and (t & (t - 1)) == 0 else PERM_NONDEC
+    return base
+
+
+def color(row_ptr, col_idx, select=RANDOM_X, X=4, seed=1, perms=(PERM_REVERSE,), ctx=None, stream=None, stats=True):
+    """Initial coloring followed by one recoloring pass per entry of `perms` (pass p uses index p)."""
+    c, s0 = init_color(row_ptr, col_idx, select, X, seed, ctx=ctx, stream=stream, stats=stats)
+    hist = [s0]
+    for p, perm in enumerate(perms):
+        c, sp = recolor(row_ptr, col_idx, c, perm, seed, p, out=c, ctx=ctx, stream=stream, stats=stats)
+        hist.append(sp)
+    return c, hist

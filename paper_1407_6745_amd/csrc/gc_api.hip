@@ -1,0 +1,402 @@
+// gc_api.hip - context management, status strings, and the checking /
+// counting entry points of the C ABI (validate, count colors, CSR check).
+#include "gc_internal.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+extern "C" const char *gc_status_string(gc_status s) {
+    switch (s) {
+        case GC_OK: return "ok";
+        case GC_ERR_ARG: return "invalid argument";
+        case GC_ERR_GRAPH: return "graph breaks a CSR precondition";
+        case GC_ERR_COLORING: return "input coloring out of range";
+        case GC_ERR_OOM: return "out of memory";
+        case GC_ERR_DEVICE: return "HIP device error";
+        case GC_ERR_NOT_CONVERGED: return "max_rounds reached before every vertex was colored";
+    }
+    return "unknown status";
+}
+
+gc_status gc_fail(gc_ctx *ctx, gc_status s, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return s;
+}
+
+extern "C" const char *gc_ctx_last_error(const gc_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int gc_grid(const gc_ctx *ctx, int64_t work, int block) {
+    int64_t want = (work + block - 1) / block;
+    int64_t cap = (int64_t)ctx->num_cu * (ctx->tune.grid_per_cu > 0 ? ctx->tune.grid_per_cu : 8);
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    return (int)want;
+}
+
+gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
+    if (!ctx) return GC_ERR_ARG;
+    if (!g) return gc_fail(ctx, GC_ERR_ARG, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0) return gc_fail(ctx, GC_ERR_ARG, "negative size");
+    if (g->n > ctx->max_n) return gc_fail(ctx, GC_ERR_ARG, "n = %d above the context capacity %lld", g->n, (long long)ctx->max_n);
+    if (g->nnz >= 2147483647LL) return gc_fail(ctx, GC_ERR_ARG, "nnz must be < 2^31");
+    if (g->n > 0 && !g->row_ptr) return gc_fail(ctx, GC_ERR_ARG, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return gc_fail(ctx, GC_ERR_ARG, "col_idx is NULL");
+    return GC_OK;
+}
+
+static void free_all(gc_ctx *c) {
+    void *ptrs[] = {c->wl[0], c->wl[1], c->list, c->hist, c->rank, c->pi, c->off, c->cursor,
+                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+}
+
+extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, gc_ctx **out) {
+    if (!out) return GC_ERR_ARG;
+    *out = nullptr;
+    if (max_n < 0 || max_n > 2147483647LL - 4096 || max_nnz < 0) return GC_ERR_ARG;
+    gc_ctx *ctx = (gc_ctx *)calloc(1, sizeof(gc_ctx));
+    if (!ctx) return GC_ERR_OOM;
+    ctx->device = device;
+    ctx->max_n = max_n;
+    ctx->max_nnz = max_nnz;
+    ctx->ccap = (int32_t)(max_n + GC_MAX_X + 64);
+    ctx->tune.block = 256;
+    ctx->tune.deg_small = 8;
+    ctx->tune.deg_wave = 512;
+    ctx->tune.group = 8;
+    ctx->tune.grid_per_cu = 8;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
+    ctx->num_cu = prop.multiProcessorCount;
+    size_t N = (size_t)max_n + 64;
+    size_t CC = (size_t)ctx->ccap + 64;
+    ctx->bitmap_bits = (int64_t)((CC + 63) / 64 * 64);
+    struct { void **p; size_t bytes; } allocs[] = {
+        {(void **)&ctx->wl[0], N * 4},       {(void **)&ctx->wl[1], N * 4},
+        {(void **)&ctx->list, (N + CC * 64) * 4},
+        {(void **)&ctx->hist, CC * 4},       {(void **)&ctx->rank, CC * 4},
+        {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (CC + 1) * 4},
+        {(void **)&ctx->cursor, CC * 4},     {(void **)&ctx->keys, CC * 8},
+        {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
+        {(void **)&ctx->round_stats, 2 * N * 8},
+        {(void **)&ctx->scal, S_COUNT * 8},
+    };
+    for (auto &a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) { free_all(ctx); free(ctx); return GC_ERR_OOM; }
+    }
+    if (hipHostMalloc((void **)&ctx->hscal, S_COUNT * 8, hipHostMallocDefault) != hipSuccess) {
+        free_all(ctx); free(ctx); return GC_ERR_OOM;
+    }
+    // buffers that must be zero between calls
+    if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
+        hipMemset(ctx->scal, 0, S_COUNT * 8) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        free_all(ctx); free(ctx); return GC_ERR_DEVICE;
+    }
+    *out = ctx;
+    return GC_OK;
+}
+
+extern "C" void gc_ctx_destroy(gc_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_all(ctx);
+    free(ctx);
+}
+
+extern "C" gc_status gc_ctx_get_tuning(const gc_ctx *ctx, gc_tuning *t) {
+    if (!ctx || !t) return GC_ERR_ARG;
+    *t = ctx->tune;
+    return GC_OK;
+}
+
+extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
+    if (!ctx || !t) return GC_ERR_ARG;
+    if (t->block < 64 || t->block > 1024 || t->block % 64) return gc_fail(ctx, GC_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (t->group < 2 || t->group > 64 || (t->group & (t->group - 1))) return gc_fail(ctx, GC_ERR_ARG, "group must be a power of two in [2, 64]");
+    if (t->deg_small < 0 || t->deg_wave < t->deg_small) return gc_fail(ctx, GC_ERR_ARG, "need 0 <= deg_small <= deg_wave");
+    if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
+    ctx->tune = *t;
+    return GC_OK;
+}
+
+gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s) {
+    GC_HIP(hipMemcpyAsync(ctx->hscal, ctx->scal, S_COUNT * 8, hipMemcpyDeviceToHost, s));
+    GC_HIP(hipStreamSynchronize(s));
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validate: conflicting edges and uncolored vertices
+// ---------------------------------------------------------------------------
+
+__global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                           const int32_t *__restrict__ C, unsigned long long *scal) {
+    unsigned long long conf = 0, unc = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int32_t cu = C[u];
+        if (cu <= 0) { unc++; continue; }
+        int32_t e0, e1;
+        row_range(rp, (int32_t)u, nnz, e0, e1);
+        for (int32_t e = e0; e < e1; e++) {
+            int32_t w = col[e];
+            if ((uint32_t)w < (uint32_t)n && w > u && C[w] == cu) conf++;
+        }
+    }
+    conf = wave_sum_u64(conf);
+    unc = wave_sum_u64(unc);
+    if (__lane_id() == 0) {
+        if (conf) atomicAdd(&scal[S_CONFLICTS], conf);
+        if (unc) atomicAdd(&scal[S_UNCOLORED], unc);
+    }
+}
+
+extern "C" gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
+                                 int64_t *uncolored, void *stream) {
+    gc_status st = gc_check_graph_args(ctx, g);
+    if (st) return st;
+    if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_CONFLICTS, 0, 2 * 8, s));
+    if (g->n > 0) {
+        int block = 256;
+        k_validate<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->scal);
+        GC_LAUNCHED();
+    }
+    st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    if (conflict_edges) *conflict_edges = (int64_t)ctx->hscal[S_CONFLICTS];
+    if (uncolored) *uncolored = (int64_t)ctx->hscal[S_UNCOLORED];
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// count colors: max / min reduction, then a bitmap of present colors
+// (workgroup-private in LDS for small colors) and a popcount
+// ---------------------------------------------------------------------------
+
+__global__ void k_minmax(int32_t n, const int32_t *__restrict__ C, unsigned long long *scal) {
+    int32_t mx = 0, mn = 0x7fffffff;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t c = C[i];
+        mx = max(mx, c);
+        mn = min(mn, c);
+    }
+    mx = wave_max_i32(mx);
+    mn = wave_min_i32(mn);
+    if (__lane_id() == 0) {
+        atomicMax((int *)&scal[S_MAXC], mx);
+        atomicMin((int *)&scal[S_MINC], mn);
+    }
+}
+
+#define BITMAP_LDS_WORDS 2048  // colors 1..65536 tracked in LDS
+
+__global__ void k_bitmap(int32_t n, const int32_t *__restrict__ C, uint32_t *bitmap, int64_t bitmap_bits) {
+    __shared__ uint32_t lb[BITMAP_LDS_WORDS];
+    for (int i = threadIdx.x; i < BITMAP_LDS_WORDS; i += blockDim.x) lb[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t c = C[i];
+        if (c <= 0) continue;
+        uint32_t b = (uint32_t)c - 1u;
+        if (b < BITMAP_LDS_WORDS * 32u) {
+            if (!(lb[b >> 5] & (1u << (b & 31)))) atomicOr(&lb[b >> 5], 1u << (b & 31));
+        } else if ((int64_t)b < bitmap_bits) {
+            atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < BITMAP_LDS_WORDS; i += blockDim.x) {
+        uint32_t w = lb[i];
+        if (w && (int64_t)i * 32 < bitmap_bits) atomicOr(&bitmap[i], w);
+    }
+}
+
+// popcount of bitmap words covering colors 1..maxc, clearing them for the next call
+__global__ void k_popcount_clear(uint32_t *bitmap, int64_t bitmap_bits, unsigned long long *scal) {
+    int64_t maxc = (int64_t)(int32_t)scal[S_MAXC];
+    if (maxc > bitmap_bits) maxc = bitmap_bits;
+    int64_t words = (maxc + 31) / 32;
+    unsigned long long cnt = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) {
+        uint32_t w = bitmap[i];
+        if (w) {
+            cnt += __popc(w);
+            bitmap[i] = 0;
+        }
+    }
+    cnt = wave_sum_u64(cnt);
+    if (__lane_id() == 0 && cnt) atomicAdd(&scal[S_NUMC], cnt);
+}
+
+__global__ void k_init_minmax(unsigned long long *scal) {
+    if (threadIdx.x == 0) {
+        scal[S_MAXC] = 0;
+        scal[S_MINC] = 0x7fffffff;
+        scal[S_NUMC] = 0;
+    }
+}
+
+// Queues the count of distinct colors / max / min into ctx->scal (no sync).
+// Colors above the bitmap capacity are not counted as distinct (the caller
+// handles that case); the bitmap is left all zero.
+gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax) {
+    if (reset_minmax) {
+        k_init_minmax<<<1, 64, 0, s>>>(ctx->scal);
+        GC_LAUNCHED();
+    }
+    if (n <= 0) return GC_OK;
+    int block = 256;
+    k_minmax<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->scal);
+    GC_LAUNCHED();
+    k_bitmap<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->bitmap, ctx->bitmap_bits);
+    GC_LAUNCHED();
+    k_popcount_clear<<<gc_grid(ctx, ctx->bitmap_bits / 32, block), block, 0, s>>>(ctx->bitmap, ctx->bitmap_bits, ctx->scal);
+    GC_LAUNCHED();
+    return GC_OK;
+}
+
+extern "C" gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors,
+                                     int32_t *max_color, void *stream) {
+    if (!ctx) return GC_ERR_ARG;
+    if (n < 0 || n > ctx->max_n) return gc_fail(ctx, GC_ERR_ARG, "n out of range");
+    if (n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    gc_status st = gc_count_device(ctx, n, colors, s, true);
+    if (st) return st;
+    st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    int64_t maxc = (int64_t)(int32_t)ctx->hscal[S_MAXC];
+    if (maxc > ctx->bitmap_bits) {
+        // some color lies above the bitmap: grow it to cover every int32 color seen, count again
+        int64_t bits = (maxc + 64) / 64 * 64;
+        uint32_t *nb = nullptr;
+        GC_HIP(hipStreamSynchronize(s));
+        if (hipMalloc((void **)&nb, (size_t)bits / 8) != hipSuccess) return gc_fail(ctx, GC_ERR_OOM, "bitmap of %lld bits", (long long)bits);
+        GC_HIP(hipMemsetAsync(nb, 0, (size_t)bits / 8, s));
+        GC_HIP(hipStreamSynchronize(s));
+        GC_HIP(hipFree(ctx->bitmap));
+        ctx->bitmap = nb;
+        ctx->bitmap_bits = bits;
+        st = gc_count_device(ctx, n, colors, s, true);
+        if (st) return st;
+        st = gc_sync_scalars(ctx, s);
+        if (st) return st;
+    }
+    if (num_colors) *num_colors = (int32_t)ctx->hscal[S_NUMC];
+    if (max_color) *max_color = (int32_t)ctx->hscal[S_MAXC];
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CSR precondition check
+// ---------------------------------------------------------------------------
+
+__global__ void k_check_rows(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, unsigned long long *scal) {
+    unsigned long long bad = 0, unsorted = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        int32_t a = rp[v], b = rp[v + 1];
+        if (a < 0 || b < a || b > nnz) bad++;
+        if (v == 0 && a != 0) bad++;
+        if (v == n - 1 && (int64_t)b != nnz) bad++;
+    }
+    bad = wave_sum_u64(bad);
+    if (__lane_id() == 0 && bad) atomicAdd(&scal[S_GRAPHERR], bad);
+    (void)unsorted;
+}
+
+__global__ void k_check_sorted(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t n,
+                               unsigned long long *scal) {
+    unsigned long long uns = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        for (int32_t e = rp[v] + 1; e < rp[v + 1]; e++)
+            if (col[e - 1] > col[e]) { uns++; break; }
+    }
+    uns = wave_sum_u64(uns);
+    if (__lane_id() == 0 && uns) atomicAdd(&scal[S_DONE], uns);
+}
+
+// count of x in the sorted (or, if !sorted, arbitrary) range col[a..b)
+__device__ inline int32_t count_in_row(const int32_t *__restrict__ col, int32_t a, int32_t b, int32_t x, bool sorted) {
+    if (!sorted) {
+        int32_t c = 0;
+        for (int32_t e = a; e < b; e++) c += col[e] == x;
+        return c;
+    }
+    int32_t lo = a, hi = b;
+    while (lo < hi) { int32_t m = lo + ((hi - lo) >> 1); if (col[m] < x) lo = m + 1; else hi = m; }
+    int32_t first = lo;
+    hi = b;
+    while (lo < hi) { int32_t m = lo + ((hi - lo) >> 1); if (col[m] <= x) lo = m + 1; else hi = m; }
+    return lo - first;
+}
+
+__global__ void k_check_entries(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int32_t n,
+                                unsigned long long *scal) {
+    bool sorted = scal[S_DONE] == 0;
+    unsigned long long bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        int32_t a = rp[v], b = rp[v + 1];
+        for (int32_t e = a; e < b; e++) {
+            int32_t w = col[e];
+            if ((uint32_t)w >= (uint32_t)n || w == v) { bad++; continue; }
+            // multiplicity of w in row v (count each run once, at its first entry when sorted)
+            if (sorted && e > a && col[e - 1] == w) continue;
+            int32_t fwd = count_in_row(col, a, b, w, sorted);
+            int32_t back = count_in_row(col, rp[w], rp[w + 1], (int32_t)v, sorted);
+            if (fwd != back) bad++;
+        }
+    }
+    bad = wave_sum_u64(bad);
+    if (__lane_id() == 0 && bad) atomicAdd(&scal[S_GRAPHERR], bad);
+}
+
+extern "C" gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream) {
+    gc_status st = gc_check_graph_args(ctx, g);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_GRAPHERR, 0, 8, s));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_DONE, 0, 8, s));
+    if (g->n == 0) return g->nnz == 0 ? GC_OK : gc_fail(ctx, GC_ERR_GRAPH, "n = 0 with nnz > 0");
+    int block = 256;
+    k_check_rows<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
+    GC_LAUNCHED();
+    st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    if (ctx->hscal[S_GRAPHERR]) return gc_fail(ctx, GC_ERR_GRAPH, "row_ptr is not a valid offset array for nnz = %lld", (long long)g->nnz);
+    k_check_sorted<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal);
+    GC_LAUNCHED();
+    k_check_entries<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal);
+    GC_LAUNCHED();
+    st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    if (ctx->hscal[S_GRAPHERR])
+        return gc_fail(ctx, GC_ERR_GRAPH, "%llu adjacency entries out of range, self-loops or without a matching reverse entry",
+                       (unsigned long long)ctx->hscal[S_GRAPHERR]);
+    return GC_OK;
+}
+
+extern "C" uint64_t gc_batch_graph_seed(uint64_t base_seed, int32_t g) {
+    return gc_mix64(base_seed + GC_GOLDEN * (((uint64_t)GC_TAG_GRAPH << 32) | (uint32_t)g));
+}

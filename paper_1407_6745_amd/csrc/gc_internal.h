@@ -1,0 +1,309 @@
+// gc_internal.h - shared internals of libgc (HIP, gfx950): context layout,
+// device helpers (hash, wavefront primitives, first-fit selection).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "../../include/gc.h"
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+// Device scalar slots (int64 each) in ctx->scal.
+enum {
+    S_WCOUNT0 = 0,   // worklist length, buffer 0
+    S_WCOUNT1 = 1,   // worklist length, buffer 1
+    S_MAXC = 2,      // max color seen
+    S_MINC = 3,      // min color seen
+    S_ERR = 4,       // error flags (bit 0: color out of range, bit 1: wait limit)
+    S_CONFLICTS = 5,
+    S_UNCOLORED = 6,
+    S_K = 7,         // number of non-empty classes
+    S_NUMC = 8,      // distinct colors
+    S_GRAPHERR = 9,  // csr check failures
+    S_TICKET = 10,   // work ticket of persistent kernels
+    S_DONE = 11,
+    S_COUNT = 64
+};
+
+struct gc_ctx {
+    int device;
+    int num_cu;
+    int64_t max_n;
+    int64_t max_nnz;
+    int32_t ccap;            // largest color any buffer indexed by color can hold
+    gc_tuning tune;
+    // device workspace
+    int32_t *wl[2];          // init worklists (max_n)
+    int32_t *list;           // recolor: vertices grouped by class rank (max_n + padding)
+    int32_t *hist;           // class sizes by color (ccap + 2), all zero between calls
+    int32_t *rank;           // rank of a color in the class order (ccap + 2)
+    int32_t *pi;             // class order (ccap + 2)
+    int32_t *off;            // list offsets per rank (ccap + 3)
+    int32_t *cursor;         // scatter cursors per rank (ccap + 2)
+    uint64_t *keys;          // sort keys (ccap + 2)
+    uint32_t *bitmap;        // distinct-color bitmap, all zero between calls
+    int64_t bitmap_bits;
+    int64_t *round_stats;    // 2 * (max_n + 2): |W_r|, degree sum of W_r
+    unsigned long long *scal;  // S_COUNT device scalars
+    unsigned long long *hscal; // pinned host mirror
+    int32_t *bws;            // batched coloring: per-workgroup workspace (grown on demand)
+    int64_t bws_bytes;
+    char err[512];
+};
+
+// Records a message and returns the status.
+gc_status gc_fail(gc_ctx *ctx, gc_status s, const char *fmt, ...);
+
+#define GC_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return gc_fail(ctx, GC_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GC_LAUNCHED()                                                                  \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return gc_fail(ctx, GC_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// Common argument checks for a single-graph call.
+gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g);
+
+// Host-side grid size for grid-stride kernels over `work` items.
+int gc_grid(const gc_ctx *ctx, int64_t work, int block);
+
+// Launch helpers shared between files (defined in gc_api.hip).
+gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax);
+gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// hash: counter-based randomness of the method (written from the published
+// definitions of the SplitMix64 output function and the MurmurHash3 32-bit
+// finalizer)
+// ---------------------------------------------------------------------------
+
+#define GC_GOLDEN 0x9E3779B97F4A7C15ULL
+enum { GC_TAG_PRIO = 1, GC_TAG_COLOR = 2, GC_TAG_PERM = 3, GC_TAG_GRAPH = 4 };
+
+__host__ __device__ inline uint64_t gc_mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ULL;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return z;
+}
+
+__host__ __device__ inline uint32_t gc_fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6BU;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35U;
+    h ^= h >> 16;
+    return h;
+}
+
+// Per-round (or per-pass) stream value: the top 32 bits of
+// mix64(seed + golden * (tag << 32 | counter)).  Uniform over a launch, so the
+// host computes it once and passes it to the kernels.
+inline uint32_t gc_stream_value(uint64_t seed, uint32_t tag, uint32_t counter) {
+    return (uint32_t)(gc_mix64(seed + GC_GOLDEN * (((uint64_t)tag << 32) | counter)) >> 32);
+}
+
+// priority of v for a round with stream value s (larger wins; a bijection of v)
+__device__ inline uint32_t gc_prio(uint32_t s, int32_t v) { return gc_fmix32(s ^ (uint32_t)v); }
+
+// Random-X offset in [0, X): multiply-shift of the vertex hash
+__device__ inline uint32_t gc_pick(uint32_t s, int32_t v, uint32_t X) {
+    return (uint32_t)(((uint64_t)gc_fmix32(s ^ (uint32_t)v) * X) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// wavefront helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+__device__ inline int32_t wave_max_i32(int32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ inline int32_t wave_min_i32(int32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ inline uint64_t wave_or_u64(uint64_t x) {
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+    return x;
+}
+
+// Appends v (where pred holds) to wl, one atomic per wavefront.  Every lane of
+// the wavefront must call it (converged).
+__device__ inline void wave_push(int32_t *wl, unsigned long long *count, bool pred, int32_t v) {
+    unsigned long long b = __ballot(pred);
+    if (b == 0) return;
+    int lane = __lane_id();
+    int leader = __ffsll((long long)b) - 1;
+    unsigned int base = 0;
+    if (lane == leader) base = (unsigned int)atomicAdd(count, (unsigned long long)__popcll(b));
+    base = __shfl(base, leader);
+    if (pred) wl[base + __popcll(b & ((1ull << lane) - 1))] = v;
+}
+
+// row range of v clamped to [0, nnz]
+__device__ inline void row_range(const int32_t *__restrict__ rp, int32_t v, int64_t nnz, int32_t &e0, int32_t &e1) {
+    int64_t a = rp[v], b = rp[v + 1];
+    a = a < 0 ? 0 : (a > nnz ? nnz : a);
+    b = b < a ? a : (b > nnz ? nnz : b);
+    e0 = (int32_t)a;
+    e1 = (int32_t)b;
+}
+
+// Position (0-based) of the (j+1)-th set bit of x; x must have more than j set bits.
+__device__ inline uint32_t nth_set_bit(uint64_t x, uint32_t j) {
+    for (uint32_t i = 0; i < j; i++) x &= x - 1;
+    return (uint32_t)(__ffsll((long long)x) - 1);
+}
+
+// (j+1)-th smallest positive color absent from {C[w] > 0 : w in col[e0..e1)},
+// one lane per vertex, 64 colors per window.
+__device__ inline int32_t select_color_lane(const int32_t *__restrict__ col, int32_t e0, int32_t e1,
+                                            const int32_t *C, int32_t n, uint32_t j) {
+    uint32_t base = 0;
+    for (;;) {
+        uint64_t mask = 0;
+        for (int32_t e = e0; e < e1; e++) {
+            int32_t w = col[e];
+            if ((uint32_t)w < (uint32_t)n) {
+                uint32_t d = (uint32_t)C[w] - base - 1u;  // colors <= base (incl. <= 0) wrap to >= 64
+                if (d < 64u) mask |= 1ull << d;
+            }
+        }
+        uint64_t fr = ~mask;
+        uint32_t cnt = (uint32_t)__popcll(fr);
+        if (j < cnt) return (int32_t)(base + 1u + nth_set_bit(fr, j));
+        j -= cnt;
+        base += 64u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workgroup-level routines (blockDim.x a multiple of 64, at most 1024)
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of x across the workgroup; *total = sum.  lds: >= 17 ints.
+// Every thread of the workgroup must call it.
+__device__ inline int32_t block_exclusive_scan(int32_t x, int32_t *total, int32_t *lds) {
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int32_t incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) lds[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int w = 0; w < nw; w++) { int32_t t = lds[w]; lds[w] = acc; acc += t; }
+        lds[16] = acc;
+    }
+    __syncthreads();
+    int32_t ex = incl - x + lds[wid];
+    *total = lds[16];
+    __syncthreads();
+    return ex;
+}
+
+__device__ inline int32_t block_max_i32(int32_t x, int32_t *lds) {
+    x = wave_max_i32(x);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (__lane_id() == 0) lds[wid] = x;
+    __syncthreads();
+    int32_t m = lds[0];
+    for (int w = 1; w < nw; w++) m = max(m, lds[w]);
+    __syncthreads();
+    return m;
+}
+
+// Class order of one recoloring pass, computed by one workgroup (section 3:
+// RV, NI, ND and RAND permutations of the color classes).
+//   hist[c]  : class sizes for c in [1, maxc]; cleared on return;
+//   cls      : scratch, receives the increasing list of non-empty colors;
+//   pi[s]    : color visited at step s, s < k;
+//   rank[c]  : s such that pi[s] = c (for present colors);
+//   off[s]   : first slot of rank s in the grouped list (off[k] = total);
+//   cursor[s]: copy of off[s] (scatter cursors).
+// Arrays may live in LDS or global memory.  Returns k (same in every thread).
+// s_perm is the pass's stream value for the RAND shuffle.
+__device__ inline int32_t block_class_order(int32_t maxc, int32_t perm, uint32_t s_perm, int32_t *hist, int32_t *cls,
+                                            int32_t *pi, int32_t *rank, int32_t *off, int32_t *cursor, int32_t *lds) {
+    // compact the non-empty classes in increasing color order
+    int32_t k = 0;
+    for (int32_t base = 1; base <= maxc; base += blockDim.x) {
+        int32_t c = base + (int32_t)threadIdx.x;
+        int32_t f = (c <= maxc && hist[c] > 0) ? 1 : 0;
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(f, &tot, lds);
+        if (f) cls[k + ex] = c;
+        k += tot;
+    }
+    __syncthreads();
+    if (perm == GC_PERM_REVERSE) {
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) pi[i] = cls[k - 1 - i];
+    } else if (perm == GC_PERM_NONINC || perm == GC_PERM_NONDEC) {
+        // position of class i = number of classes ordered before it by (size, color)
+        const bool noninc = perm == GC_PERM_NONINC;
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) {
+            int32_t ci = cls[i];
+            int32_t si = hist[ci];
+            int32_t r = 0;
+            for (int32_t j = 0; j < k; j++) {
+                int32_t cj = cls[j];
+                int32_t sj = hist[cj];
+                r += noninc ? (sj > si || (sj == si && cj < ci)) : (sj < si || (sj == si && cj < ci));
+            }
+            pi[r] = ci;
+        }
+    } else {
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) pi[i] = cls[i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // Knuth shuffle from the top index down: swap i with a uniform index in [0, i]
+            for (int32_t i = k - 1; i >= 1; i--) {
+                uint32_t j = (uint32_t)(((uint64_t)gc_fmix32(s_perm ^ (uint32_t)i) * (uint32_t)(i + 1)) >> 32);
+                int32_t t = pi[i];
+                pi[i] = pi[j];
+                pi[j] = t;
+            }
+        }
+    }
+    __syncthreads();
+    int32_t acc = 0;
+    for (int32_t base = 0; base < k; base += blockDim.x) {
+        int32_t s = base + (int32_t)threadIdx.x;
+        int32_t sz = 0;
+        if (s < k) {
+            int32_t c = pi[s];
+            rank[c] = s;
+            sz = hist[c];
+        }
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(sz, &tot, lds);
+        if (s < k) { off[s] = acc + ex; cursor[s] = acc + ex; }
+        acc += tot;
+    }
+    if (threadIdx.x == 0) off[k] = acc;
+    __syncthreads();
+    for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    return k;
+}

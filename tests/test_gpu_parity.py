@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element (integer work: bit-exact), on seeded inputs of every family at
+sizes that span several workgroups and a ragged tail, plus edge cases."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_6745_amd as m
+
+    m.lib()
+    return m
+
+
+def dev(g):
+    d = torch.device("cuda:0")
+    return torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(d), torch.from_numpy(np.ascontiguousarray(g.col)).to(d)
+
+
+GRAPHS = {
+    "er": lambda: gen.er(3001, 15007, 3),
+    "mesh": lambda: gen.mesh27(13),
+    "grid": lambda: gen.grid5(61, 37),
+    "rmat": lambda: gen.rmat(12, 16, seed=5),
+    "rgg": lambda: gen.rgg(2500, 0.05, 7),
+    "complete": lambda: gen.complete(40),
+    "star": lambda: gen.star(700),
+    "crown": lambda: gen.crown(30),
+    "path": lambda: gen.path(1000),
+    "empty": lambda: gen.empty(777),
+    "single": lambda: gen.empty(1),
+}
+
+
+def _init_equal(gc, g, sel, X, seed, flags=0):
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, sel, X, seed, flags=flags)
+    ref = oracle.init_color(g, sel, X, seed, flags=flags)
+    got = c.cpu().numpy()
+    assert np.array_equal(got, ref.colors), f"{g.name}: {int((got != ref.colors).sum())} vertex colors differ"
+    assert st["rounds"] == ref.stats["rounds"]
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    assert st["losers_total"] == ref.stats["losers_total"]
+    assert (st["num_colors"], st["max_color"]) == (ref.stats["num_colors"], ref.stats["max_color"])
+    return c, ref
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_init_parity(gc, name):
+    g = GRAPHS[name]()
+    for sel, X in ((gc.FIRST_FIT, 1), (gc.RANDOM_X, 1), (gc.RANDOM_X, 4), (gc.RANDOM_X, 10)):
+        for seed in (1, 77):
+            _init_equal(gc, g, sel, X, seed)
+
+
+def test_init_fixed_priority(gc):
+    g = GRAPHS["rmat"]()
+    _init_equal(gc, g, gc.FIRST_FIT, 1, 3, flags=gc.FLAG_FIXED_PRIORITY)
+    _init_equal(gc, g, gc.RANDOM_X, 5, 3, flags=gc.FLAG_FIXED_PRIORITY)
+
+
+@pytest.mark.parametrize("name", ["er", "mesh", "grid", "rmat", "rgg", "complete", "crown", "path", "single"])
+def test_recolor_parity(gc, name):
+    g = GRAPHS[name]()
+    rp, col = dev(g)
+    c, ref = _init_equal(gc, g, gc.RANDOM_X, 5, 11)
+    rc = ref.colors
+    for p in range(8):
+        perm = (gc.PERM_REVERSE, gc.PERM_NONINC, gc.PERM_NONDEC, gc.PERM_RANDOM)[p % 4]
+        inplace = p % 2 == 1
+        out = c if inplace else None
+        c2, st = gc.recolor(rp, col, c, perm, 11, p, out=out)
+        r = oracle.recolor(g, rc, perm, 11, p)
+        got = c2.cpu().numpy()
+        assert np.array_equal(got, r.colors), f"{name} pass {p} perm {perm}: {int((got != r.colors).sum())} differ"
+        assert st["k_classes"] == len(r.pi)
+        assert (st["num_colors"], st["max_color"]) == (r.stats["num_colors"], r.stats["max_color"])
+        c, rc = c2, r.colors
+
+
+def test_validate_count_parity(gc):
+    rng = np.random.default_rng(1)
+    for name in ("er", "rmat", "mesh"):
+        g = GRAPHS[name]()
+        rp, col = dev(g)
+        base = oracle.greedy_seq(g)
+        for trial in range(4):
+            c = base.copy()
+            idx = rng.integers(0, g.n, 20)
+            c[idx] = rng.integers(-2, 6, 20)  # plant conflicts and uncolored vertices
+            ct = torch.from_numpy(c).cuda()
+            assert gc.validate(rp, col, ct) == oracle.validate(g, c)
+            assert gc.count_colors(ct) == oracle.count(c)
+
+
+def test_count_large_colors(gc):
+    c = np.array([5, 2_000_000_000, 5, 7, -3, 0, 2_000_000_000, 123456789], np.int32)
+    assert gc.count_colors(torch.from_numpy(c).cuda()) == oracle.count(c)
+
+
+def test_check_csr(gc):
+    g = GRAPHS["rmat"]()
+    rp, col = dev(g)
+    assert gc.check_csr(rp, col) == gc.OK
+    g2 = gen.shuffle_rows(g, 3)  # unsorted rows are still valid
+    assert gc.check_csr(*dev(g2)) == gc.OK
+    bad = g.col.copy()
+    e = int(g.row_ptr[5])
+    bad[e] = 5 if g.row_ptr[6] > e else bad[e]  # self-loop
+    assert gc.check_csr(rp, torch.from_numpy(bad).cuda()) == gc.ERR_GRAPH
+    asym = gen.CSR(3, np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32))
+    assert gc.check_csr(*dev(asym)) == gc.ERR_GRAPH
+    oob = g.col.copy()
+    oob[0] = g.n + 3
+    assert gc.check_csr(rp, torch.from_numpy(oob).cuda()) == gc.ERR_GRAPH
+
+
+def test_not_converged(gc):
+    g = gen.complete(30)
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, gc.FIRST_FIT, 1, 4, max_rounds=7, allow_not_converged=True)
+    ref = oracle.init_color(g, oracle.FIRST_FIT, 1, 4, max_rounds=7)
+    assert st["status"] == gc.ERR_NOT_CONVERGED and ref.status == oracle.ERR_NOT_CONVERGED
+    assert st["rounds"] == 7
+    got = c.cpu().numpy()
+    assert np.array_equal(got > 0, ref.colors > 0)
+    assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
+    with pytest.raises(gc.GCError):
+        gc.init_color(rp, col, gc.FIRST_FIT, 1, 4, max_rounds=7)
+
+
+def test_empty_graph_and_bad_args(gc):
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    col = torch.zeros(0, dtype=torch.int32, device="cuda")
+    c, st = gc.init_color(rp, col)
+    assert c.numel() == 0 and st["rounds"] == 0 and st["num_colors"] == 0
+    c2, st2 = gc.recolor(rp, col, c)
+    assert st2["num_colors"] == 0
+    g = GRAPHS["er"]()
+    rpg, colg = dev(g)
+    with pytest.raises(gc.GCError) as e:
+        gc.init_color(rpg, colg, gc.RANDOM_X, 0)
+    assert e.value.status == gc.ERR_ARG
+    with pytest.raises(gc.GCError) as e:
+        gc.recolor(rpg, colg, torch.zeros(g.n, dtype=torch.int32, device="cuda"))
+    assert e.value.status == gc.ERR_COLORING
+    with pytest.raises(TypeError):
+        gc.init_color(rpg.long(), colg)
+
+
+def test_many_small_random_graphs(gc):
+    rng = np.random.default_rng(123)
+    for t in range(60):
+        n = int(rng.integers(1, 200))
+        m = int(rng.integers(0, min(n * (n - 1) // 2, 6 * n) + 1))
+        g = gen.er(n, m, int(rng.integers(1, 10**9))) if n >= 2 else gen.empty(n)
+        sel = int(rng.integers(0, 2))
+        X = int(rng.integers(1, 12))
+        seed = int(rng.integers(1, 2**63))
+        c, ref = _init_equal(gc, g, sel, X, seed)
+        if g.n:
+            rp, col = dev(g)
+            perm = int(rng.integers(0, 4))
+            c2, _ = gc.recolor(rp, col, c, perm, seed, t)
+            assert np.array_equal(c2.cpu().numpy(), oracle.recolor(g, ref.colors, perm, seed, t).colors)
