@@ -100,11 +100,15 @@ typedef struct gc_stats {
 /* Tuning knobs.  No knob changes any result, only the speed. */
 typedef struct gc_tuning {
     int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
-    int32_t deg_small;     /* rows with degree <= deg_small: one lane per vertex */
-    int32_t deg_wave;      /* rows with degree > deg_wave: one wavefront per vertex; in between, lane groups */
-    int32_t group;         /* lanes per vertex for the middle bin (power of two, 2..64) */
-    int32_t grid_per_cu;   /* workgroups per compute unit for persistent kernels */
-    int32_t reserved[3];
+    int32_t deg_wave;      /* recoloring: rows with degree > deg_wave get a whole wavefront per vertex */
+    int32_t group;         /* recoloring: lanes per vertex for the other rows (power of two, 1..64) */
+    int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
+    int32_t walk_mode;     /* recoloring class walk: 0 = one persistent launch, waits per dependency;
+                              1 = one launch per class (host reads the class count) */
+    int32_t xcd_chunks;    /* persistent walk: consecutive work chunks kept on one XCD (0 = round robin) */
+    int32_t check_resident;/* persistent walk: verify at start that every workgroup is resident (diagnostic;
+                              a failed check makes the call return GC_ERR_DEVICE when it synchronizes) */
+    int32_t reserved;
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);
@@ -119,6 +123,30 @@ void gc_ctx_destroy(gc_ctx *ctx);
 const char *gc_ctx_last_error(const gc_ctx *ctx);
 gc_status gc_ctx_get_tuning(const gc_ctx *ctx, gc_tuning *t);
 gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t);
+
+/*
+ * Launch facts of a context (host values): info[0] = compute units,
+ * info[1] = workgroups of the persistent recoloring walk for the current
+ * group size (0 until first used), info[2] = its workgroups per compute unit.
+ * Fills min(cap, 3) entries.
+ */
+gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap);
+
+/*
+ * Kernel timing (profiling aid).  When enabled, the library records a pair of
+ * HIP events on the launch stream around every kernel it launches and sums
+ * the elapsed times per kernel kind.  gc_ctx_get_timing synchronizes the
+ * device, fills launches[kind] and ms[kind] for kind < min(cap,
+ * GC_KERNEL_KINDS) and returns GC_OK.  Enabling (or re-enabling) clears the
+ * sums.  Timing adds event records between launches and should stay off
+ * outside measurements.
+ */
+enum {
+    GC_K_ROUND0 = 0, GC_K_ASSIGN = 1, GC_K_DETECT = 2, GC_K_HIST = 3, GC_K_ORDER = 4, GC_K_SCATTER = 5,
+    GC_K_WALK = 6, GC_K_COUNT = 7, GC_K_BATCH = 8, GC_K_OTHER = 9, GC_KERNEL_KINDS = 10
+};
+gc_status gc_ctx_set_timing(gc_ctx *ctx, int enable);
+gc_status gc_ctx_get_timing(gc_ctx *ctx, int64_t *launches, double *ms, int cap);
 
 /*
  * Check the CSR preconditions on the device: row_ptr[0] = 0, non-decreasing,

@@ -41,8 +41,11 @@ class StatsArgs(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("deg_small", ctypes.c_int32), ("deg_wave", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("block", ctypes.c_int32), ("deg_wave", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32), ("walk_mode", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
+                ("check_resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident")
 
 
 class BatchArgs(ctypes.Structure):
@@ -76,7 +79,13 @@ _SIGS = {
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_batch_graph_seed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32]),
+    "gc_ctx_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "gc_ctx_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "gc_ctx_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
 }
+
+KERNEL_KINDS = ("round0", "assign", "detect", "hist", "order", "scatter", "walk", "count", "batch", "other")
 
 
 def lib():
@@ -146,8 +155,24 @@ class Context:
     def tuning(self) -> dict:
         t = Tuning()
         self.check(lib().gc_ctx_get_tuning(self.handle, ctypes.byref(t)), "gc_ctx_get_tuning")
-        return {"block": t.block, "deg_small": t.deg_small, "deg_wave": t.deg_wave, "group": t.group,
-                "grid_per_cu": t.grid_per_cu}
+        return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+    def set_timing(self, enable: bool):
+        """Turn per-kernel HIP-event timing on (clearing the sums) or off."""
+        self.check(lib().gc_ctx_set_timing(self.handle, 1 if enable else 0), "gc_ctx_set_timing")
+
+    def timing(self) -> dict:
+        """{kind: (launches, total ms)} since timing was enabled (synchronizes the device)."""
+        n = len(KERNEL_KINDS)
+        la = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        self.check(lib().gc_ctx_get_timing(self.handle, la, ms, n), "gc_ctx_get_timing")
+        return {k: (int(la[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def info(self) -> dict:
+        a = (ctypes.c_int64 * 3)()
+        self.check(lib().gc_ctx_get_info(self.handle, a, 3), "gc_ctx_get_info")
+        return {"num_cu": a[0], "walk_blocks": a[1], "walk_blocks_per_cu": a[2]}
 
     def set_tuning(self, **kw):
         t = Tuning()

@@ -50,8 +50,8 @@ gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
 }
 
 static void free_all(gc_ctx *c) {
-    void *ptrs[] = {c->wl[0], c->wl[1], c->list, c->hist, c->rank, c->pi, c->off, c->cursor,
-                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws};
+    void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
+                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -68,10 +68,11 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->max_nnz = max_nnz;
     ctx->ccap = (int32_t)(max_n + GC_MAX_X + 64);
     ctx->tune.block = 256;
-    ctx->tune.deg_small = 8;
-    ctx->tune.deg_wave = 512;
-    ctx->tune.group = 8;
+    ctx->tune.deg_wave = 256;
+    ctx->tune.group = 4;
     ctx->tune.grid_per_cu = 8;
+    ctx->tune.walk_mode = 0;
+    ctx->tune.xcd_chunks = 0;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -83,10 +84,14 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->bitmap_bits = (int64_t)((CC + 63) / 64 * 64);
     struct { void **p; size_t bytes; } allocs[] = {
         {(void **)&ctx->wl[0], N * 4},       {(void **)&ctx->wl[1], N * 4},
+        {(void **)&ctx->wl[2], N * 4},       {(void **)&ctx->wl[3], N * 4},
         {(void **)&ctx->list, (N + CC * 64) * 4},
+        {(void **)&ctx->rows, (N + 64) * 8},
         {(void **)&ctx->hist, CC * 4},       {(void **)&ctx->rank, CC * 4},
-        {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (CC + 1) * 4},
-        {(void **)&ctx->cursor, CC * 4},     {(void **)&ctx->keys, CC * 8},
+        {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (2 * CC + 4) * 4},
+        {(void **)&ctx->coff, (2 * CC + 4) * 4},
+        {(void **)&ctx->histw, CC * 4},
+        {(void **)&ctx->cursor, (2 * CC + 4) * 4}, {(void **)&ctx->keys, CC * 8},
         {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
         {(void **)&ctx->round_stats, 2 * N * 8},
         {(void **)&ctx->scal, S_COUNT * 8},
@@ -98,7 +103,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         free_all(ctx); free(ctx); return GC_ERR_OOM;
     }
     // buffers that must be zero between calls
-    if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
+    if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->histw, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
         hipMemset(ctx->scal, 0, S_COUNT * 8) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx); free(ctx); return GC_ERR_DEVICE;
     }
@@ -106,10 +111,98 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     return GC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+
+#define TIMER_PAIRS 4096
+
+struct gc_timer {
+    hipEvent_t ev[2 * TIMER_PAIRS];
+    int kind[TIMER_PAIRS];
+    int pending;
+    int open;  // index of the pair whose begin event was recorded last, or -1
+    int64_t launches[GC_KERNEL_KINDS];
+    double ms[GC_KERNEL_KINDS];
+};
+
+static void timer_flush(gc_timer *t) {
+    for (int i = 0; i < t->pending; i++) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t->ev[2 * i + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, t->ev[2 * i], t->ev[2 * i + 1]) == hipSuccess) {
+            t->ms[t->kind[i]] += ms;
+            t->launches[t->kind[i]]++;
+        }
+    }
+    t->pending = 0;
+}
+
+static void timer_free(gc_timer *t) {
+    if (!t) return;
+    for (int i = 0; i < 2 * TIMER_PAIRS; i++)
+        if (t->ev[i]) (void)hipEventDestroy(t->ev[i]);
+    free(t);
+}
+
+void gc_time_begin(gc_ctx *ctx, int kind, hipStream_t s) {
+    gc_timer *t = ctx->timer;
+    if (!t) return;
+    if (t->pending == TIMER_PAIRS) timer_flush(t);
+    t->kind[t->pending] = kind;
+    (void)hipEventRecord(t->ev[2 * t->pending], s);
+    t->open = t->pending;
+}
+
+void gc_time_end(gc_ctx *ctx, int kind, hipStream_t s) {
+    gc_timer *t = ctx->timer;
+    if (!t || t->open < 0 || t->kind[t->open] != kind) return;
+    (void)hipEventRecord(t->ev[2 * t->open + 1], s);
+    t->pending = t->open + 1;
+    t->open = -1;
+}
+
+extern "C" gc_status gc_ctx_set_timing(gc_ctx *ctx, int enable) {
+    if (!ctx) return GC_ERR_ARG;
+    GC_HIP(hipSetDevice(ctx->device));
+    if (ctx->timer) {
+        (void)hipDeviceSynchronize();
+        timer_free(ctx->timer);
+        ctx->timer = nullptr;
+    }
+    if (!enable) return GC_OK;
+    gc_timer *t = (gc_timer *)calloc(1, sizeof(gc_timer));
+    if (!t) return gc_fail(ctx, GC_ERR_OOM, "timer");
+    for (int i = 0; i < 2 * TIMER_PAIRS; i++) {
+        if (hipEventCreate(&t->ev[i]) != hipSuccess) {
+            timer_free(t);
+            return gc_fail(ctx, GC_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    t->open = -1;
+    ctx->timer = t;
+    return GC_OK;
+}
+
+extern "C" gc_status gc_ctx_get_timing(gc_ctx *ctx, int64_t *launches, double *ms, int cap) {
+    if (!ctx || cap < 0 || (cap > 0 && (!launches || !ms))) return GC_ERR_ARG;
+    GC_HIP(hipSetDevice(ctx->device));
+    for (int i = 0; i < cap && i < GC_KERNEL_KINDS; i++) { launches[i] = 0; ms[i] = 0.0; }
+    if (!ctx->timer) return GC_OK;
+    GC_HIP(hipDeviceSynchronize());
+    timer_flush(ctx->timer);
+    for (int i = 0; i < cap && i < GC_KERNEL_KINDS; i++) {
+        launches[i] = ctx->timer->launches[i];
+        ms[i] = ctx->timer->ms[i];
+    }
+    return GC_OK;
+}
+
 extern "C" void gc_ctx_destroy(gc_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    timer_free(ctx->timer);
     free_all(ctx);
     free(ctx);
 }
@@ -123,10 +216,20 @@ extern "C" gc_status gc_ctx_get_tuning(const gc_ctx *ctx, gc_tuning *t) {
 extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (!ctx || !t) return GC_ERR_ARG;
     if (t->block < 64 || t->block > 1024 || t->block % 64) return gc_fail(ctx, GC_ERR_ARG, "block must be a multiple of 64 in [64, 1024]");
-    if (t->group < 2 || t->group > 64 || (t->group & (t->group - 1))) return gc_fail(ctx, GC_ERR_ARG, "group must be a power of two in [2, 64]");
-    if (t->deg_small < 0 || t->deg_wave < t->deg_small) return gc_fail(ctx, GC_ERR_ARG, "need 0 <= deg_small <= deg_wave");
+    if (t->group < 1 || t->group > 64 || (t->group & (t->group - 1))) return gc_fail(ctx, GC_ERR_ARG, "group must be a power of two in [1, 64]");
+    if (t->deg_wave < 0) return gc_fail(ctx, GC_ERR_ARG, "deg_wave must be >= 0");
+    if (t->walk_mode < 0 || t->walk_mode > 1) return gc_fail(ctx, GC_ERR_ARG, "walk_mode must be 0 or 1");
+    if (t->xcd_chunks < 0) return gc_fail(ctx, GC_ERR_ARG, "xcd_chunks must be >= 0");
+    if (t->check_resident < 0 || t->check_resident > 1) return gc_fail(ctx, GC_ERR_ARG, "check_resident must be 0 or 1");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
     ctx->tune = *t;
+    return GC_OK;
+}
+
+extern "C" gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap) {
+    if (!ctx || cap < 0 || (cap > 0 && !info)) return GC_ERR_ARG;
+    const int64_t v[3] = {ctx->num_cu, ctx->walk_blocks, ctx->num_cu ? ctx->walk_blocks / ctx->num_cu : 0};
+    for (int i = 0; i < cap && i < 3; i++) info[i] = v[i];
     return GC_OK;
 }
 
@@ -172,7 +275,7 @@ extern "C" gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *co
     GC_HIP(hipMemsetAsync(ctx->scal + S_CONFLICTS, 0, 2 * 8, s));
     if (g->n > 0) {
         int block = 256;
-        k_validate<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->scal);
+        GC_TIMED(GC_K_OTHER, s, k_validate<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->scal));
         GC_LAUNCHED();
     }
     st = gc_sync_scalars(ctx, s);
@@ -258,16 +361,16 @@ __global__ void k_init_minmax(unsigned long long *scal) {
 // handles that case); the bitmap is left all zero.
 gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax) {
     if (reset_minmax) {
-        k_init_minmax<<<1, 64, 0, s>>>(ctx->scal);
+        GC_TIMED(GC_K_COUNT, s, k_init_minmax<<<1, 64, 0, s>>>(ctx->scal));
         GC_LAUNCHED();
     }
     if (n <= 0) return GC_OK;
     int block = 256;
-    k_minmax<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->scal);
+    GC_TIMED(GC_K_COUNT, s, k_minmax<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->scal));
     GC_LAUNCHED();
-    k_bitmap<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->bitmap, ctx->bitmap_bits);
+    GC_TIMED(GC_K_COUNT, s, k_bitmap<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->bitmap, ctx->bitmap_bits));
     GC_LAUNCHED();
-    k_popcount_clear<<<gc_grid(ctx, ctx->bitmap_bits / 32, block), block, 0, s>>>(ctx->bitmap, ctx->bitmap_bits, ctx->scal);
+    GC_TIMED(GC_K_COUNT, s, k_popcount_clear<<<gc_grid(ctx, ctx->bitmap_bits / 32, block), block, 0, s>>>(ctx->bitmap, ctx->bitmap_bits, ctx->scal));
     GC_LAUNCHED();
     return GC_OK;
 }
@@ -380,14 +483,14 @@ extern "C" gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream) {
     GC_HIP(hipMemsetAsync(ctx->scal + S_DONE, 0, 8, s));
     if (g->n == 0) return g->nnz == 0 ? GC_OK : gc_fail(ctx, GC_ERR_GRAPH, "n = 0 with nnz > 0");
     int block = 256;
-    k_check_rows<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
+    GC_TIMED(GC_K_OTHER, s, k_check_rows<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal));
     GC_LAUNCHED();
     st = gc_sync_scalars(ctx, s);
     if (st) return st;
     if (ctx->hscal[S_GRAPHERR]) return gc_fail(ctx, GC_ERR_GRAPH, "row_ptr is not a valid offset array for nnz = %lld", (long long)g->nnz);
-    k_check_sorted<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal);
+    GC_TIMED(GC_K_OTHER, s, k_check_sorted<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal));
     GC_LAUNCHED();
-    k_check_entries<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal);
+    GC_TIMED(GC_K_OTHER, s, k_check_entries<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->n, ctx->scal));
     GC_LAUNCHED();
     st = gc_sync_scalars(ctx, s);
     if (st) return st;

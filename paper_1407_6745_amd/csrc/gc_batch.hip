@@ -169,6 +169,7 @@ __device__ int32_t block_pass(const int32_t *rp, const int32_t *col, int64_t nnz
     }
     __syncthreads();
     const int32_t k = block_class_order(maxc, perm, s_perm, hist, cls, pi, rank, off, cursor, lds);
+    for (int32_t c = threadIdx.x; c <= maxc; c += BT) hist[c] = 0;
     for (int32_t v = threadIdx.x; v < n; v += BT) {
         int32_t c = C[v];
         if (c < 1) continue;
@@ -281,9 +282,9 @@ extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t 
         ctx->bws_bytes = need;
     }
     GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
-    k_batch<<<grid, BT, 0, s>>>(b->num_graphs, b->vtx_off, b->edge_off, b->row_ptr, b->col_idx, select == GC_RANDOM_X,
+    GC_TIMED(GC_K_BATCH, s, k_batch<<<grid, BT, 0, s>>>(b->num_graphs, b->vtx_off, b->edge_off, b->row_ptr, b->col_idx, select == GC_RANDOM_X,
                                 (uint32_t)X, perm, passes, base_seed, max_rounds, V, colors, per_graph, ctx->bws, slice,
-                                ctx->scal + S_TICKET);
+                                ctx->scal + S_TICKET));
     GC_LAUNCHED();
     return GC_OK;
 }

@@ -5,8 +5,7 @@
 // In-place encoding of the colors array C during the rounds:
 //   C[v] > 0   committed color (final);
 //   C[v] < 0   v is in the current round's set W_r with tentative color -C[v]
-//              (or lost the previous round and waits for a new one);
-//   C[v] = 0   never written (only before round 0).
+//              (or lost the previous round and waits for a new one).
 // Readers of the assign step treat every value <= 0 as "no color", which is
 // exactly the start-of-round snapshot: a value only becomes positive in the
 // detect step.  The detect step compares |C[w]| with v's tentative color: a
@@ -14,87 +13,220 @@
 // committed before the round), whether w has already flipped its own sign to
 // commit or not.  Losers keep -T until the next assign overwrites it, so every
 // detect read of the round sees every tentative color.
+//
+// Work layout: every vertex is handled by a group of G lanes (rows up to
+// deg_wave long) or by a whole wavefront (longer rows).  Each round keeps two
+// worklists (group bin, wavefront bin); losers are appended through LDS queues
+// (one global atomic per flush).
 #include "gc_internal.h"
 
 #include <vector>
 
-// Round 0: every vertex is uncolored and no neighbor holds a color, so the
-// tentative color of any vertex is a pure function of its id: 1 + j(v).
-// Detect directly from the hash; no color is read.
-template <bool RANDX>
-__global__ void k_round0(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                         int32_t *__restrict__ C, int32_t *__restrict__ wl_out, unsigned long long *wcount_out,
-                         uint32_t s_prio, uint32_t s_color, uint32_t X) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool lose = false;
-        if (i < n) {
-            int32_t v = (int32_t)i;
-            int32_t e0, e1;
-            row_range(rp, v, nnz, e0, e1);
-            uint32_t tv = RANDX ? gc_pick(s_color, v, X) : 0u;
-            uint32_t pv = gc_prio(s_prio, v);
-            for (int32_t e = e0; e < e1; e++) {
-                int32_t w = col[e];
-                if ((uint32_t)w >= (uint32_t)n) continue;
-                uint32_t tw = RANDX ? gc_pick(s_color, w, X) : 0u;
-                if (tw == tv && gc_prio(s_prio, w) > pv) { lose = true; break; }
-            }
-            int32_t t = (int32_t)tv + 1;
-            C[v] = lose ? -t : t;
-        }
-        wave_push(wl_out, wcount_out, lose, (int32_t)i);
-    }
+#define INIT_BLOCK 256
+
+// Tentative color of w in round 0: 1 + its Random-X offset (no color is held yet).
+__device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, bool randx) {
+    return randx ? (int32_t)gc_pick(s_color, w, X) + 1 : 1;
 }
 
-// Assign step of round r >= 1 over the worklist: tentative color into C[v] as -T.
-__global__ void k_assign(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                         int32_t *C, const int32_t *__restrict__ wl, const unsigned long long *__restrict__ wcount,
-                         uint32_t s_color, uint32_t X, int randx, int64_t *round_stats_r) {
+// Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
+// G lanes, result uniform over the group.  ROUND0: neighbor colors come from
+// the hash; otherwise |C[w]|.
+template <int G, bool ROUND0>
+__device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
+                                   const int32_t *C, int32_t n, uint32_t s_prio, uint32_t s_color, uint32_t X,
+                                   bool randx) {
+    const int l = __lane_id() & (G - 1);
+    bool lose = false;
+    for (int32_t eb = e0 + l; eb < e1; eb += G * GC_UNROLL) {
+        int32_t w[GC_UNROLL], t[GC_UNROLL];
+#pragma unroll
+        for (int u = 0; u < GC_UNROLL; u++) {
+            const int32_t e = eb + u * G;
+            const int32_t wl = col[e < e1 ? e : eb];
+            w[u] = e < e1 ? wl : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < GC_UNROLL; u++) {
+            const bool ok = (uint32_t)w[u] < (uint32_t)n;
+            if (ROUND0) {
+                t[u] = ok ? round0_color(s_color, w[u], X, randx) : 0;
+            } else {
+                const int32_t cl = C[ok ? w[u] : 0];
+                t[u] = ok ? abs(cl) : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GC_UNROLL; u++)
+            if (t[u] == tv && gc_prio(s_prio, w[u]) > pv) lose = true;
+    }
+    return group_any<G>(lose);
+}
+
+// LDS state of a kernel that appends to two worklists.
+struct InitQueues {
+    int32_t buf[2][GC_QCAP];
+    int32_t cnt[2];
+    int32_t base[2];
+};
+
+__device__ inline void queues_init(InitQueues &q) {
+    if (threadIdx.x == 0) { q.cnt[0] = 0; q.cnt[1] = 0; }
+    __syncthreads();
+}
+
+__device__ inline void queues_flush(InitQueues &q, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
+                                    unsigned long long *c_hub, bool force) {
+    __syncthreads();
+    bq_flush(q.buf[0], &q.cnt[0], &q.base[0], wl_lo, c_lo, force);
+    bq_flush(q.buf[1], &q.cnt[1], &q.base[1], wl_hub, c_hub, force);
+}
+
+// Round 0, by vertex id (in_list == NULL) or over a list of long rows.  By
+// vertex id, rows longer than deg_wave are not processed but appended to the
+// second queue (they get their own launch, one wavefront each).  Writes
+// C[v] = +T (kept) or -T (lost) and appends losers by bin.
+template <int G>
+__global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       int64_t nnz, int32_t n, int32_t *C, int32_t deg_wave,
+                                                       const int32_t *__restrict__ in_list,
+                                                       const unsigned long long *__restrict__ in_count,
+                                                       int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
+                                                       unsigned long long *c_hub, uint32_t s_prio, uint32_t s_color,
+                                                       uint32_t X, int randx) {
+    __shared__ InitQueues q;
+    queues_init(q);
+    const int64_t cnt = in_list ? (int64_t)*in_count : (int64_t)n;
+    const int vpi = INIT_BLOCK / G;  // vertices per block iteration
+    const int gi = threadIdx.x / G;
+    for (int64_t base = (int64_t)blockIdx.x * vpi; base < cnt; base += (int64_t)gridDim.x * vpi) {
+        const int64_t i = base + gi;
+        int32_t v = -1, e0 = 0, e1 = 0;
+        bool forward = false;
+        if (i < cnt) {
+            v = in_list ? in_list[i] : (int32_t)i;
+            row_range(rp, v, nnz, e0, e1);
+            if (!in_list && e1 - e0 > deg_wave) forward = true;
+        }
+        const bool hub = e1 - e0 > deg_wave;
+        if (forward) e1 = e0;
+        const int32_t tv = v >= 0 ? round0_color(s_color, v, X, randx != 0) : 0;
+        const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
+        const bool lose = group_loses<G, true>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0);
+        const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
+        if (leader && !forward) C[v] = lose ? -tv : tv;
+        bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
+        bq_push(q.buf[1], &q.cnt[1], leader && (forward || (lose && hub)), v);
+        queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
+    }
+    queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, true);
+}
+
+// Assign step of round r >= 1: C[v] = -T for every v of the list.
+template <int G>
+__global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       int64_t nnz, int32_t n, int32_t *C,
+                                                       const int32_t *__restrict__ wl,
+                                                       const unsigned long long *__restrict__ wcount, uint32_t s_color,
+                                                       uint32_t X, int randx, unsigned long long *degsum) {
+    __shared__ unsigned long long sdeg;
+    if (threadIdx.x == 0) sdeg = 0;
+    __syncthreads();
     const int64_t cnt = (int64_t)*wcount;
+    const int vpi = INIT_BLOCK / G;
+    const int gi = threadIdx.x / G;
     unsigned long long degs = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-        int32_t v = wl[i];
-        int32_t e0, e1;
-        row_range(rp, v, nnz, e0, e1);
-        degs += (unsigned long long)(e1 - e0);
-        uint32_t j = randx ? gc_pick(s_color, v, X) : 0u;
-        C[v] = -select_color_lane(col, e0, e1, C, n, j);
+    for (int64_t base = (int64_t)blockIdx.x * vpi; base < cnt; base += (int64_t)gridDim.x * vpi) {
+        const int64_t i = base + gi;
+        int32_t v = -1, e0 = 0, e1 = 0;
+        if (i < cnt) {
+            v = wl[i];
+            row_range(rp, v, nnz, e0, e1);
+        }
+        const uint32_t j = (v >= 0 && randx) ? gc_pick(s_color, v, X) : 0u;
+        const int32_t t = group_select<G>(col, e0, e1, C, n, j);
+        if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
+            C[v] = -t;
+            degs += (unsigned long long)(e1 - e0);
+        }
     }
     degs = wave_sum_u64(degs);
-    if (__lane_id() == 0 && degs) atomicAdd((unsigned long long *)&round_stats_r[1], degs);
+    if (__lane_id() == 0 && degs) atomicAdd(&sdeg, degs);
+    __syncthreads();
+    if (threadIdx.x == 0 && sdeg) atomicAdd(degsum, sdeg);
 }
 
 // Detect step of round r >= 1: v loses when a neighbor has the same tentative
-// color and a larger priority; winners commit (flip the sign), losers go to wl_out.
-__global__ void k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                         int32_t *C, const int32_t *__restrict__ wl, const unsigned long long *__restrict__ wcount,
-                         int32_t *__restrict__ wl_out, unsigned long long *wcount_out, uint32_t s_prio) {
+// color and a larger priority; winners commit (flip the sign), losers go to
+// the next worklist of their bin.
+template <int G>
+__global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       int64_t nnz, int32_t n, int32_t *C, int32_t deg_wave,
+                                                       const int32_t *__restrict__ wl,
+                                                       const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
+                                                       unsigned long long *c_lo, int32_t *wl_hub,
+                                                       unsigned long long *c_hub, uint32_t s_prio) {
+    __shared__ InitQueues q;
+    queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cnt; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool lose = false;
-        int32_t v = 0;
+    const int vpi = INIT_BLOCK / G;
+    const int gi = threadIdx.x / G;
+    for (int64_t base = (int64_t)blockIdx.x * vpi; base < cnt; base += (int64_t)gridDim.x * vpi) {
+        const int64_t i = base + gi;
+        int32_t v = -1, e0 = 0, e1 = 0, t = 0;
         if (i < cnt) {
             v = wl[i];
-            int32_t t = -C[v];
-            int32_t e0, e1;
             row_range(rp, v, nnz, e0, e1);
-            uint32_t pv = gc_prio(s_prio, v);
-            for (int32_t e = e0; e < e1; e++) {
-                int32_t w = col[e];
-                if ((uint32_t)w >= (uint32_t)n) continue;
-                int32_t cw = C[w];
-                if ((cw == t || cw == -t) && gc_prio(s_prio, w) > pv) { lose = true; break; }
-            }
-            if (!lose) C[v] = t;
+            t = -C[v];
         }
-        wave_push(wl_out, wcount_out, lose, v);
+        const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
+        const bool lose = group_loses<G, false>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false);
+        const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
+        if (leader && !lose) C[v] = t;
+        const bool hub = e1 - e0 > deg_wave;
+        bq_push(q.buf[0], &q.cnt[0], leader && lose && !hub, v);
+        bq_push(q.buf[1], &q.cnt[1], leader && lose && hub, v);
+        queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
     }
+    queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, true);
 }
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <int G>
+static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *in_list,
+                          const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
+                          int32_t *wl_hub, unsigned long long *c_hub, uint32_t sp, uint32_t sc, uint32_t X, int randx) {
+    k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, in_list, in_count, wl_lo,
+                                            c_lo, wl_hub, c_hub, sp, sc, X, randx);
+}
+
+template <int G>
+static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
+                          const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum) {
+    k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum);
+}
+
+template <int G>
+static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
+                          const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
+                          unsigned long long *c_hub, uint32_t sp) {
+    k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
+                                            c_hub, sp);
+}
+
+#define GC_DISPATCH_G(G, CALL)                           \
+    switch (G) {                                         \
+        case 1: { constexpr int GG = 1; CALL; } break;   \
+        case 2: { constexpr int GG = 2; CALL; } break;   \
+        case 4: { constexpr int GG = 4; CALL; } break;   \
+        case 8: { constexpr int GG = 8; CALL; } break;   \
+        case 16: { constexpr int GG = 16; CALL; } break; \
+        case 32: { constexpr int GG = 32; CALL; } break; \
+        default: { constexpr int GG = 64; CALL; } break; \
+    }
 
 extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
                                    int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
@@ -105,54 +237,82 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     if (max_rounds < 0) return gc_fail(ctx, GC_ERR_ARG, "max_rounds must be >= 0");
     if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
     if (select == GC_FIRST_FIT) X = 1;
-    const bool randx = select == GC_RANDOM_X;
+    const int randx = select == GC_RANDOM_X ? 1 : 0;
     hipStream_t s = (hipStream_t)stream;
     GC_HIP(hipSetDevice(ctx->device));
     const int32_t n = g->n;
     if (n == 0) {
-        if (st) {
-            st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0;
-        }
+        if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
         return GC_OK;
     }
     auto prio_stream = [&](int32_t r) {
         return gc_stream_value(seed, GC_TAG_PRIO, (flags & GC_FLAG_FIXED_PRIORITY) ? 0u : (uint32_t)r);
     };
-    const int block = 256;
-    std::vector<int64_t> sizes;
+    const int G = ctx->tune.group;
+    const int32_t deg_wave = ctx->tune.deg_wave;
+    const int cap = ctx->num_cu * ctx->tune.grid_per_cu;
+    auto grid_for = [&](int64_t items, int gsz) {
+        int64_t per = INIT_BLOCK / gsz;
+        int64_t want = (items + per - 1) / per;
+        return (int)(want < 1 ? 1 : (want > cap ? cap : want));
+    };
+    // Worklists wl[2 * buf + bin] (bin 0: lane groups, bin 1: wavefronts),
+    // counts in scal[S_WL + 2 * buf + bin]; scal[S_WL + 4] holds the degree
+    // sum of the current round.  Round 0 uses wl[3] for the long rows it
+    // forwards to its second launch.
+    unsigned long long *cnt = ctx->scal + S_WL;
+    std::vector<int64_t> sizes, degsum;
     sizes.push_back(n);
-    std::vector<int64_t> degsum;
     degsum.push_back(g->nnz);
-    GC_HIP(hipMemsetAsync(ctx->scal + S_WCOUNT0, 0, 2 * 8, s));
-    if (randx)
-        k_round0<true><<<gc_grid(ctx, n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[0],
-                                                              ctx->scal + S_WCOUNT0, prio_stream(0),
-                                                              gc_stream_value(seed, GC_TAG_COLOR, 0), (uint32_t)X);
-    else
-        k_round0<false><<<gc_grid(ctx, n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[0],
-                                                               ctx->scal + S_WCOUNT0, prio_stream(0), 0u, 1u);
+    GC_HIP(hipMemsetAsync(cnt, 0, 5 * 8, s));
+    const uint32_t sp0 = prio_stream(0), sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
+    GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, nullptr, nullptr,
+                                                                ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0, sc0,
+                                                                (uint32_t)X, randx)));
+    GC_LAUNCHED();
+    GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
+                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx));
     GC_LAUNCHED();
     int32_t r = 1, cur = 0;
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
         if (ss) return ss;
-        int64_t cnt = (int64_t)ctx->hscal[S_WCOUNT0 + cur];
-        if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_COUNT - 1]);
-        if (cnt == 0) break;
+        const int64_t nlo = (int64_t)ctx->hscal[S_WL + 2 * cur], nhub = (int64_t)ctx->hscal[S_WL + 2 * cur + 1];
+        if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4]);
+        const int64_t tot = nlo + nhub;
+        if (tot == 0) break;
         if (max_rounds > 0 && r == max_rounds) { status = GC_ERR_NOT_CONVERGED; break; }
         if (r > n) return gc_fail(ctx, GC_ERR_DEVICE, "no progress after %d rounds", r);  // each round commits >= 1 vertex
-        sizes.push_back(cnt);
-        int nxt = cur ^ 1;
-        GC_HIP(hipMemsetAsync(ctx->scal + S_WCOUNT0 + nxt, 0, 8, s));
-        GC_HIP(hipMemsetAsync(ctx->scal + S_COUNT - 2, 0, 16, s));
-        int grid = gc_grid(ctx, cnt, block);
-        k_assign<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[cur], ctx->scal + S_WCOUNT0 + cur,
-                                        gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r), (uint32_t)X, randx ? 1 : 0,
-                                        (int64_t *)(ctx->scal + S_COUNT - 2));
-        GC_LAUNCHED();
-        k_detect<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[cur], ctx->scal + S_WCOUNT0 + cur,
-                                        ctx->wl[nxt], ctx->scal + S_WCOUNT0 + nxt, prio_stream(r));
-        GC_LAUNCHED();
+        sizes.push_back(tot);
+        const int nxt = cur ^ 1;
+        int32_t *lo_in = ctx->wl[2 * cur], *hub_in = ctx->wl[2 * cur + 1];
+        int32_t *lo_out = ctx->wl[2 * nxt], *hub_out = ctx->wl[2 * nxt + 1];
+        unsigned long long *c_lo_in = cnt + 2 * cur, *c_hub_in = cnt + 2 * cur + 1;
+        unsigned long long *c_lo_out = cnt + 2 * nxt, *c_hub_out = cnt + 2 * nxt + 1;
+        GC_HIP(hipMemsetAsync(c_lo_out, 0, 2 * 8, s));
+        GC_HIP(hipMemsetAsync(cnt + 4, 0, 8, s));
+        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r), sp = prio_stream(r);
+        if (nlo) {
+            GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
+                                                                        sc, (uint32_t)X, randx, cnt + 4)));
+            GC_LAUNCHED();
+        }
+        if (nhub) {
+            GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
+                                                       randx, cnt + 4));
+            GC_LAUNCHED();
+        }
+        if (nlo) {
+            GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
+                                                                        c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
+                                                                        sp)));
+            GC_LAUNCHED();
+        }
+        if (nhub) {
+            GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
+                                                       c_lo_out, hub_out, c_hub_out, sp));
+            GC_LAUNCHED();
+        }
         cur = nxt;
         r++;
     }

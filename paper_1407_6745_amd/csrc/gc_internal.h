@@ -7,7 +7,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
-#include "../../include/gc.h"
+#include "gc.h"
 
 // ---------------------------------------------------------------------------
 // context
@@ -27,6 +27,7 @@ enum {
     S_GRAPHERR = 9,  // csr check failures
     S_TICKET = 10,   // work ticket of persistent kernels
     S_DONE = 11,
+    S_WL = 16,       // initial coloring: 4 worklist counts + the round's degree sum (16..20)
     S_COUNT = 64
 };
 
@@ -38,19 +39,25 @@ struct gc_ctx {
     int32_t ccap;            // largest color any buffer indexed by color can hold
     gc_tuning tune;
     // device workspace
-    int32_t *wl[2];          // init worklists (max_n)
+    int32_t *wl[4];          // init worklists (max_n each): [2 * buffer + bin]
     int32_t *list;           // recolor: vertices grouped by class rank (max_n + padding)
+    int2 *rows;              // recolor: row range of list[i] (same layout)
     int32_t *hist;           // class sizes by color (ccap + 2), all zero between calls
+    int32_t *histw;          // per color: vertices in the wavefront-per-vertex degree bin; zero between calls
+    int32_t *coff;           // recolor: work-chunk offsets per (rank, bin) segment (2 * ccap + 4)
+    int walk_blocks;         // co-resident workgroups of the persistent walk (0 = not computed)
+    int walk_blocks_group;   // group size the count was computed for
     int32_t *rank;           // rank of a color in the class order (ccap + 2)
     int32_t *pi;             // class order (ccap + 2)
-    int32_t *off;            // list offsets per rank (ccap + 3)
-    int32_t *cursor;         // scatter cursors per rank (ccap + 2)
+    int32_t *off;            // list offsets per (rank, bin) segment (2 * ccap + 4)
+    int32_t *cursor;         // scatter cursors per segment (2 * ccap + 4)
     uint64_t *keys;          // sort keys (ccap + 2)
     uint32_t *bitmap;        // distinct-color bitmap, all zero between calls
     int64_t bitmap_bits;
     int64_t *round_stats;    // 2 * (max_n + 2): |W_r|, degree sum of W_r
     unsigned long long *scal;  // S_COUNT device scalars
     unsigned long long *hscal; // pinned host mirror
+    struct gc_timer *timer;  // kernel timing (NULL when off)
     int32_t *bws;            // batched coloring: per-workgroup workspace (grown on demand)
     int64_t bws_bytes;
     char err[512];
@@ -71,6 +78,17 @@ gc_status gc_fail(gc_ctx *ctx, gc_status s, const char *fmt, ...);
         hipError_t e_ = hipGetLastError();                                             \
         if (e_ != hipSuccess)                                                          \
             return gc_fail(ctx, GC_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// Kernel timing: events around a launch (no-ops unless timing is enabled).
+void gc_time_begin(gc_ctx *ctx, int kind, hipStream_t s);
+void gc_time_end(gc_ctx *ctx, int kind, hipStream_t s);
+
+#define GC_TIMED(kind, stream, ...)        \
+    do {                                  \
+        gc_time_begin(ctx, kind, stream); \
+        __VA_ARGS__;                      \
+        gc_time_end(ctx, kind, stream);   \
     } while (0)
 
 // Common argument checks for a single-graph call.
@@ -236,12 +254,12 @@ __device__ inline int32_t block_max_i32(int32_t x, int32_t *lds) {
 
 // Class order of one recoloring pass, computed by one workgroup (section 3:
 // RV, NI, ND and RAND permutations of the color classes).
-//   hist[c]  : class sizes for c in [1, maxc]; cleared on return;
+//   hist[c]  : class sizes for c in [1, maxc] (left as they are);
 //   cls      : scratch, receives the increasing list of non-empty colors;
 //   pi[s]    : color visited at step s, s < k;
 //   rank[c]  : s such that pi[s] = c (for present colors);
 //   off[s]   : first slot of rank s in the grouped list (off[k] = total);
-//   cursor[s]: copy of off[s] (scatter cursors).
+//   cursor[s]: copy of off[s] (scatter cursors); off / cursor may be NULL.
 // Arrays may live in LDS or global memory.  Returns k (same in every thread).
 // s_perm is the pass's stream value for the RAND shuffle.
 __device__ inline int32_t block_class_order(int32_t maxc, int32_t perm, uint32_t s_perm, int32_t *hist, int32_t *cls,
@@ -298,12 +316,146 @@ __device__ inline int32_t block_class_order(int32_t maxc, int32_t perm, uint32_t
         }
         int32_t tot;
         int32_t ex = block_exclusive_scan(sz, &tot, lds);
-        if (s < k) { off[s] = acc + ex; cursor[s] = acc + ex; }
+        if (s < k && off) { off[s] = acc + ex; cursor[s] = acc + ex; }
         acc += tot;
     }
-    if (threadIdx.x == 0) off[k] = acc;
-    __syncthreads();
-    for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) hist[c] = 0;
+    if (threadIdx.x == 0 && off) off[k] = acc;
     __syncthreads();
     return k;
+}
+
+// ---------------------------------------------------------------------------
+// lane groups: G consecutive lanes (G a power of two dividing 64) work on one
+// vertex; neighbor lists are read U entries per lane at a time so that U
+// independent loads are in flight before the first wait.
+// ---------------------------------------------------------------------------
+
+#define GC_UNROLL 4
+
+template <int G>
+__device__ inline uint64_t group_or_u64(uint64_t x) {
+    for (int o = G >> 1; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+    return x;
+}
+
+// true in every lane of the group if pred holds in any lane of it (whole wave must call)
+template <int G>
+__device__ inline bool group_any(bool pred) {
+    unsigned long long b = __ballot(pred);
+    if (G == 64) return b != 0;
+    const unsigned long long gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+    return ((b >> (__lane_id() & ~(G - 1))) & gm) != 0;
+}
+
+// For every valid lane: counter[key] is raised by the number of valid lanes
+// holding that key (one LDS/global atomic per distinct key of the wave); the
+// lane gets the old value plus the number of lower lanes with the same key.
+__device__ inline int32_t wave_match_reserve(int32_t *counter, int32_t key, bool valid) {
+    unsigned long long pending = __ballot(valid);
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int32_t pos = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int32_t k = __shfl(key, leader);
+        const bool mine = valid && key == k;
+        const unsigned long long same = __ballot(mine);
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counter[k], (int32_t)__popcll(same));
+        base = __shfl(base, leader);
+        if (mine) pos = base + (int32_t)__popcll(same & below);
+        pending &= ~same;
+    }
+    return pos;
+}
+
+// Same contract as wave_match_reserve for keys in [0, 2^bits): lanes with
+// equal keys are found with `bits` ballots (no loop over distinct keys); the
+// lowest lane of each key does the atomic and every lane reads its base back
+// with one cross-lane read.  bits must be uniform over the wave.
+__device__ inline int32_t wave_match_reserve_bits(int32_t *counter, int32_t key, bool valid, int bits) {
+    unsigned long long same = __ballot(valid);
+    for (int b = 0; b < bits; b++) {
+        const bool bit = (key >> b) & 1;
+        const unsigned long long bb = __ballot(bit);
+        same &= bit ? bb : ~bb;
+    }
+    const int lane = __lane_id();
+    int leader = valid ? __ffsll((long long)same) - 1 : lane;
+    int32_t base = 0;
+    if (valid && leader == lane) base = atomicAdd(&counter[key], (int32_t)__popcll(same));
+    base = __shfl(base, leader);
+    return valid ? base + (int32_t)__popcll(same & ((1ull << lane) - 1ull)) : 0;
+}
+
+// number of bits needed for keys in [0, count)
+__device__ inline int key_bits(int32_t count) { return count <= 1 ? 0 : 32 - __clz(count - 1); }
+
+// Block-aggregated append queue: entries collect in an LDS buffer and go to
+// the global list in one copy per flush (one global atomic per flush).
+// Every loop iteration may add at most blockDim.x entries.
+#define GC_QCAP 2048
+
+__device__ inline void bq_push(int32_t *lbuf, int32_t *lcnt, bool pred, int32_t v) {
+    unsigned long long b = __ballot(pred);
+    if (b == 0) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)b) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(lcnt, (int32_t)__popcll(b));
+    base = __shfl(base, leader);
+    if (pred) lbuf[base + __popcll(b & ((1ull << lane) - 1ull))] = v;
+}
+
+// Call with every thread of the block, right after a __syncthreads().
+// Flushes when `force` or when the buffer could not take one more iteration.
+__device__ inline void bq_flush(int32_t *lbuf, int32_t *lcnt, int32_t *lbase, int32_t *gl, unsigned long long *gcount,
+                                bool force) {
+    const int32_t c = *lcnt;
+    if (c == 0 || (!force && c <= GC_QCAP - (int32_t)blockDim.x)) return;
+    if (threadIdx.x == 0) *lbase = (int32_t)atomicAdd(gcount, (unsigned long long)c);
+    __syncthreads();
+    const int32_t base = *lbase;
+    for (int32_t i = threadIdx.x; i < c; i += blockDim.x) gl[base + i] = lbuf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *lcnt = 0;
+    __syncthreads();
+}
+
+// (j+1)-th smallest positive color absent from {C[w] > 0 : w in row}, by a
+// group of G lanes (group-uniform result).  Colors <= 0 are "no color".
+template <int G>
+__device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+                                       int32_t n, uint32_t j) {
+    const int l = __lane_id() & (G - 1);
+    uint32_t base = 0;
+    for (;;) {
+        uint64_t mask = 0;
+        for (int32_t eb = e0 + l; eb < e1; eb += G * GC_UNROLL) {
+            int32_t w[GC_UNROLL], x[GC_UNROLL];
+#pragma unroll
+            for (int u = 0; u < GC_UNROLL; u++) {
+                const int32_t e = eb + u * G;
+                const int32_t wl = col[e < e1 ? e : eb];
+                w[u] = e < e1 ? wl : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < GC_UNROLL; u++) {
+                const bool ok = (uint32_t)w[u] < (uint32_t)n;
+                const int32_t xl = C[ok ? w[u] : 0];
+                x[u] = ok ? xl : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < GC_UNROLL; u++) {
+                uint32_t d = (uint32_t)x[u] - base - 1u;
+                if (d < 64u) mask |= 1ull << d;
+            }
+        }
+        mask = group_or_u64<G>(mask);
+        const uint64_t fr = ~mask;
+        const uint32_t cnt = (uint32_t)__popcll(fr);
+        if (j < cnt) return (int32_t)(base + 1u + nth_set_bit(fr, j));
+        j -= cnt;
+        base += 64u;
+    }
 }

@@ -174,3 +174,50 @@ def test_many_small_random_graphs(gc):
             perm = int(rng.integers(0, 4))
             c2, _ = gc.recolor(rp, col, c, perm, seed, t)
             assert np.array_equal(c2.cpu().numpy(), oracle.recolor(g, ref.colors, perm, seed, t).colors)
+
+
+TUNINGS = [
+    dict(group=1), dict(group=2), dict(group=4), dict(group=16), dict(group=32), dict(group=64),
+    dict(deg_wave=0), dict(deg_wave=4), dict(deg_wave=1 << 30),
+    dict(walk_mode=1), dict(walk_mode=1, deg_wave=3),
+    dict(xcd_chunks=1), dict(xcd_chunks=1, group=4, deg_wave=16),
+    dict(block=64, grid_per_cu=1), dict(block=1024, grid_per_cu=2),
+]
+
+
+@pytest.mark.parametrize("name", ["rmat", "mesh", "star", "complete"])
+def test_tuning_invariance(gc, name):
+    """No tuning knob changes any color (integer work: bit-exact)."""
+    g = GRAPHS[name]()
+    rp, col = dev(g)
+    ref = oracle.init_color(g, oracle.RANDOM_X, 4, 9)
+    passes = [(p, (gc.PERM_NONINC, gc.PERM_RANDOM, gc.PERM_REVERSE)[p % 3]) for p in range(3)]
+    refs = []
+    c = ref.colors
+    for p, perm in passes:
+        c = oracle.recolor(g, c, perm, 9, p).colors
+        refs.append(c)
+    for t in TUNINGS:
+        ctx = gc.Context(g.n, g.nnz)
+        ctx.set_tuning(**t)
+        cur, st = gc.init_color(rp, col, gc.RANDOM_X, 4, 9, ctx=ctx)
+        assert np.array_equal(cur.cpu().numpy(), ref.colors), t
+        for (p, perm), r in zip(passes, refs):
+            cur, _ = gc.recolor(rp, col, cur, perm, 9, p, out=cur, ctx=ctx)
+            assert np.array_equal(cur.cpu().numpy(), r), (t, p)
+        ctx.close()
+
+
+def test_recolor_without_stats_matches(gc):
+    """The asynchronous path (no stats, no host synchronisation) gives the same colors."""
+    g = GRAPHS["rmat"]()
+    rp, col = dev(g)
+    c0 = oracle.init_color(g, oracle.FIRST_FIT, 1, 2).colors
+    c = torch.from_numpy(c0.copy()).cuda()
+    exp = c0
+    for p in range(6):
+        c, st = gc.recolor(rp, col, c, gc.PERM_RANDOM, 2, p, out=c, stats=False)
+        assert st is None
+        exp = oracle.recolor(g, exp, oracle.PERM_RANDOM, 2, p).colors
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), exp)
