@@ -81,6 +81,9 @@ def _load():
     lib.gen_rgg_batch_fill.argtypes = [ctypes.c_int32, ctypes.c_uint64, i64p, f64p, i64p, i64p, i64p,
                                        i32p, i32p]
     lib.gen_rgg_batch_fill.restype = ctypes.c_int
+    lib.gen_rgg_batch_one.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_double]
+    lib.gen_rgg_batch_one.restype = P
     lib.gen_threads.argtypes = []
     lib.gen_threads.restype = ctypes.c_int
     _lib = lib
@@ -295,6 +298,23 @@ def rgg_batch(G: int, seed: int = 1, n_lo: int = 500, n_hi: int = 50000,
     if rc:
         raise RuntimeError(f"rgg batch fill failed: {rc}")
     return Batch(G, vtx_off, edge_off, row_ptr, col)
+
+
+def rgg_batch_graph(g: int, seed: int = 1, n_lo: int = 500, n_hi: int = 50000,
+                    d_lo: float = 8.0, d_hi: float = 40.0) -> CSR:
+    """Graph g of rgg_batch(G, seed, ...) on its own (for any G > g)."""
+    return _take(_load().gen_rgg_batch_one(g, seed, n_lo, n_hi, d_lo, d_hi), f"rgg_batch_{seed}_g{g}")
+
+
+def checksum(g: CSR) -> str:
+    """SHA-256 of the CSR bytes (n, row_ptr, col; little-endian int32)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    h.update(np.int64(g.n).tobytes())
+    h.update(np.ascontiguousarray(g.row_ptr, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(g.col, dtype="<i4").tobytes())
+    return h.hexdigest()
 
 
 def threads() -> int:

@@ -488,3 +488,39 @@ int gen_threads(void) {
     return 1;
 #endif
 }
+
+/* Graph gi of the batch alone (same parameters and points as in the packed batch). */
+gen_graph *gen_rgg_batch_one(int32_t gi, uint64_t seed, int32_t n_lo, int32_t n_hi, double d_lo, double d_hi) {
+    gen_graph *g = g_alloc();
+    if (!g) return NULL;
+    uint64_t base = g_base(seed, FAM_RGG_BATCH, 0);
+    uint64_t h = g_val(base, (uint64_t)gi);
+    int64_t n = n_lo + (int64_t)g_below((uint32_t)h, (uint32_t)(n_hi - n_lo + 1));
+    double d = d_lo + (d_hi - d_lo) * ((double)(uint32_t)(h >> 32) / 4294967296.0);
+    double r = sqrt(d / (M_PI * (double)n));
+    g->n = n;
+    int32_t *px = NULL, *py = NULL;
+    int64_t *deg = NULL, *rp = NULL;
+    px = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    py = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    deg = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    rp = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!px || !py || !deg || !rp) { g->status = 1; goto done; }
+    int64_t rint = (int64_t)floor(r * (double)RGG_SIDE);
+    rgg_points(g_base(seed, FAM_RGG_BATCH, (uint64_t)gi + 1), n, px, py);
+    if (rgg_scan(n, px, py, rint, deg, NULL, NULL)) { g->status = 1; goto done; }
+    rp[0] = 0;
+    for (int64_t i = 0; i < n; i++) rp[i + 1] = rp[i] + deg[i];
+    g->row_ptr = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    g->col = (int32_t *)malloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(int32_t));
+    if (!g->row_ptr || !g->col) { g->status = 1; goto done; }
+    if (rgg_scan(n, px, py, rint, NULL, rp, g->col)) { g->status = 1; goto done; }
+    for (int64_t i = 0; i <= n; i++) g->row_ptr[i] = (int32_t)rp[i];
+    g->nnz = rp[n];
+    int32_t md = 0;
+    for (int64_t i = 0; i < n; i++) if (deg[i] > md) md = (int32_t)deg[i];
+    g->max_deg = md;
+done:
+    free(px); free(py); free(deg); free(rp);
+    return g;
+}

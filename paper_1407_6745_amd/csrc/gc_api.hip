@@ -257,9 +257,10 @@ __global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__rest
             if ((uint32_t)w < (uint32_t)n && w > u && C[w] == cu) conf++;
         }
     }
-    conf = wave_sum_u64(conf);
-    unc = wave_sum_u64(unc);
-    if (__lane_id() == 0) {
+    __shared__ unsigned long long lds[16];
+    conf = block_sum_u64(conf, lds);
+    unc = block_sum_u64(unc, lds);
+    if (threadIdx.x == 0) {
         if (conf) atomicAdd(&scal[S_CONFLICTS], conf);
         if (unc) atomicAdd(&scal[S_UNCOLORED], unc);
     }
@@ -298,9 +299,10 @@ __global__ void k_minmax(int32_t n, const int32_t *__restrict__ C, unsigned long
         mx = max(mx, c);
         mn = min(mn, c);
     }
-    mx = wave_max_i32(mx);
-    mn = wave_min_i32(mn);
-    if (__lane_id() == 0) {
+    __shared__ int32_t lds[16];
+    mx = block_max_i32(mx, lds);
+    mn = block_min_i32(mn, lds);
+    if (threadIdx.x == 0) {
         atomicMax((int *)&scal[S_MAXC], mx);
         atomicMin((int *)&scal[S_MINC], mn);
     }
@@ -318,7 +320,7 @@ __global__ void k_bitmap(int32_t n, const int32_t *__restrict__ C, uint32_t *bit
         if (c <= 0) continue;
         uint32_t b = (uint32_t)c - 1u;
         if (b < BITMAP_LDS_WORDS * 32u) {
-            if (!(lb[b >> 5] & (1u << (b & 31)))) atomicOr(&lb[b >> 5], 1u << (b & 31));
+            if (!(lb[b >> 5] & (1u << (b & 31)))) atomicOr(&lb[b >> 5], 1u << (b & 31));  // set bits are only read
         } else if ((int64_t)b < bitmap_bits) {
             atomicOr(&bitmap[b >> 5], 1u << (b & 31));
         }
@@ -344,8 +346,9 @@ __global__ void k_popcount_clear(uint32_t *bitmap, int64_t bitmap_bits, unsigned
             bitmap[i] = 0;
         }
     }
-    cnt = wave_sum_u64(cnt);
-    if (__lane_id() == 0 && cnt) atomicAdd(&scal[S_NUMC], cnt);
+    __shared__ unsigned long long lds[16];
+    cnt = block_sum_u64(cnt, lds);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&scal[S_NUMC], cnt);
 }
 
 __global__ void k_init_minmax(unsigned long long *scal) {
@@ -366,9 +369,10 @@ gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStre
     }
     if (n <= 0) return GC_OK;
     int block = 256;
-    GC_TIMED(GC_K_COUNT, s, k_minmax<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->scal));
+    const int rgrid = gc_grid(ctx, n, block) < 2 * ctx->num_cu ? gc_grid(ctx, n, block) : 2 * ctx->num_cu;
+    GC_TIMED(GC_K_COUNT, s, k_minmax<<<rgrid, block, 0, s>>>(n, colors, ctx->scal));
     GC_LAUNCHED();
-    GC_TIMED(GC_K_COUNT, s, k_bitmap<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors, ctx->bitmap, ctx->bitmap_bits));
+    GC_TIMED(GC_K_COUNT, s, k_bitmap<<<rgrid, block, 0, s>>>(n, colors, ctx->bitmap, ctx->bitmap_bits));
     GC_LAUNCHED();
     GC_TIMED(GC_K_COUNT, s, k_popcount_clear<<<gc_grid(ctx, ctx->bitmap_bits / 32, block), block, 0, s>>>(ctx->bitmap, ctx->bitmap_bits, ctx->scal));
     GC_LAUNCHED();

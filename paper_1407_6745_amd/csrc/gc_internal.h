@@ -241,6 +241,29 @@ __device__ inline int32_t block_exclusive_scan(int32_t x, int32_t *total, int32_
     return ex;
 }
 
+// Sum over the workgroup (every thread must call; lds: >= 16 words of 8 bytes).
+__device__ inline unsigned long long block_sum_u64(unsigned long long x, unsigned long long *lds) {
+    x = wave_sum_u64(x);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (__lane_id() == 0) lds[wid] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < nw; w++) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ inline int32_t block_min_i32(int32_t x, int32_t *lds) {
+    x = wave_min_i32(x);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (__lane_id() == 0) lds[wid] = x;
+    __syncthreads();
+    int32_t m = lds[0];
+    for (int w = 1; w < nw; w++) m = min(m, lds[w]);
+    __syncthreads();
+    return m;
+}
+
 __device__ inline int32_t block_max_i32(int32_t x, int32_t *lds) {
     x = wave_max_i32(x);
     const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
