@@ -182,7 +182,12 @@ def cycle(n: int) -> CSR:
 
 
 def complete(n: int) -> CSR:
-    return from_pairs(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    """K_n: row i lists every other vertex in increasing order."""
+    if n < 2:
+        return CSR(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), f"pairs_{n}")
+    col = np.tile(np.arange(n, dtype=np.int32), (n, 1))[~np.eye(n, dtype=bool)]
+    rp = (np.arange(n + 1, dtype=np.int64) * (n - 1)).astype(np.int32)
+    return CSR(n, rp, np.ascontiguousarray(col), f"pairs_{n}")
 
 
 def star(n_leaves: int) -> CSR:

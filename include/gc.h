@@ -108,6 +108,10 @@ typedef struct gc_tuning {
     int32_t xcd_chunks;    /* persistent walk: consecutive work chunks kept on one XCD (0 = round robin) */
     int32_t check_resident;/* persistent walk: verify at start that every workgroup is resident (diagnostic;
                               a failed check makes the call return GC_ERR_DEVICE when it synchronizes) */
+    int32_t deg_split;     /* recoloring: rows longer than both deg_wave and deg_split (0 = never) are
+                              scanned by several wavefronts at once, split_len entries each (graphs whose
+                              longest row is under 64 use a walk without this path) */
+    int32_t split_len;     /* entries per wavefront for split rows (>= 64) */
     int32_t reserved;
 } gc_tuning;
 

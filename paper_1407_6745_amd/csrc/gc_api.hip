@@ -51,7 +51,8 @@ gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
 
 static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
-                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw};
+                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
+                    c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -73,6 +74,8 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.grid_per_cu = 8;
     ctx->tune.walk_mode = 0;
     ctx->tune.xcd_chunks = 0;
+    ctx->tune.deg_split = 4096;
+    ctx->tune.split_len = 1024;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -88,10 +91,12 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         {(void **)&ctx->list, (N + CC * 64) * 4},
         {(void **)&ctx->rows, (N + 64) * 8},
         {(void **)&ctx->hist, CC * 4},       {(void **)&ctx->rank, CC * 4},
-        {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (2 * CC + 4) * 4},
-        {(void **)&ctx->coff, (2 * CC + 4) * 4},
-        {(void **)&ctx->histw, CC * 4},
-        {(void **)&ctx->cursor, (2 * CC + 4) * 4}, {(void **)&ctx->keys, CC * 8},
+        {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (3 * CC + 4) * 4},
+        {(void **)&ctx->coff, (3 * CC + 4) * 4},
+        {(void **)&ctx->histw, CC * 4},      {(void **)&ctx->hist_s, CC * 4},
+        {(void **)&ctx->hist_sc, CC * 4},    {(void **)&ctx->sbase, (CC + 2) * 4},
+        {(void **)&ctx->hsub, N * 4},
+        {(void **)&ctx->cursor, (3 * CC + 4) * 4}, {(void **)&ctx->keys, CC * 8},
         {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
         {(void **)&ctx->round_stats, 2 * N * 8},
         {(void **)&ctx->scal, S_COUNT * 8},
@@ -103,7 +108,8 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         free_all(ctx); free(ctx); return GC_ERR_OOM;
     }
     // buffers that must be zero between calls
-    if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->histw, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
+    if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->histw, 0, CC * 4) != hipSuccess ||
+        hipMemset(ctx->hist_s, 0, CC * 4) != hipSuccess || hipMemset(ctx->hist_sc, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
         hipMemset(ctx->scal, 0, S_COUNT * 8) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx); free(ctx); return GC_ERR_DEVICE;
     }
@@ -221,6 +227,8 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->walk_mode < 0 || t->walk_mode > 1) return gc_fail(ctx, GC_ERR_ARG, "walk_mode must be 0 or 1");
     if (t->xcd_chunks < 0) return gc_fail(ctx, GC_ERR_ARG, "xcd_chunks must be >= 0");
     if (t->check_resident < 0 || t->check_resident > 1) return gc_fail(ctx, GC_ERR_ARG, "check_resident must be 0 or 1");
+    if (t->deg_split < 0) return gc_fail(ctx, GC_ERR_ARG, "deg_split must be >= 0");
+    if (t->split_len < 64) return gc_fail(ctx, GC_ERR_ARG, "split_len must be >= 64");
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
     ctx->tune = *t;
     return GC_OK;

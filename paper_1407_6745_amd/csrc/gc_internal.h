@@ -27,6 +27,7 @@ enum {
     S_GRAPHERR = 9,  // csr check failures
     S_TICKET = 10,   // work ticket of persistent kernels
     S_DONE = 11,
+    S_MAXDEG = 12,   // longest row of the graph
     S_WL = 16,       // initial coloring: 4 worklist counts + the round's degree sum (16..20)
     S_COUNT = 64
 };
@@ -44,13 +45,24 @@ struct gc_ctx {
     int2 *rows;              // recolor: row range of list[i] (same layout)
     int32_t *hist;           // class sizes by color (ccap + 2), all zero between calls
     int32_t *histw;          // per color: vertices in the wavefront-per-vertex degree bin; zero between calls
-    int32_t *coff;           // recolor: work-chunk offsets per (rank, bin) segment (2 * ccap + 4)
+    int32_t *coff;           // recolor: work-chunk offsets per (rank, bin) segment (3 * ccap + 4)
+    int32_t *hist_s;         // per color: vertices of the split bin; zero between calls
+    int32_t *hist_sc;        // per color: work chunks of those vertices; zero between calls
+    int32_t *sbase;          // per rank: first hub slot of the rank's split segment (ccap + 2)
+    int32_t *hsub;           // per list slot of a split row: its first chunk inside the segment (max_n + 64)
+    unsigned long long *hub_bits;  // per hub slot: HUB_WORDS color-mask words, zero between calls
+    int32_t *hub_cnt;        // per hub slot: finished chunks, zero between calls
+    int64_t hub_cap;         // hub slots allocated
     int walk_blocks;         // co-resident workgroups of the persistent walk (0 = not computed)
-    int walk_blocks_group;   // group size the count was computed for
+    int walk_blocks_group;   // walk variant (2 * group + full) the count was computed for
+    // longest row of the last graph seen by the recoloring (keyed by its arrays and sizes)
+    const void *deg_key_rp, *deg_key_col;
+    int64_t deg_key_n, deg_key_nnz;
+    int32_t deg_max;
     int32_t *rank;           // rank of a color in the class order (ccap + 2)
     int32_t *pi;             // class order (ccap + 2)
-    int32_t *off;            // list offsets per (rank, bin) segment (2 * ccap + 4)
-    int32_t *cursor;         // scatter cursors per segment (2 * ccap + 4)
+    int32_t *off;            // list offsets per (rank, bin) segment (3 * ccap + 4)
+    int32_t *cursor;         // scatter cursors per segment (3 * ccap + 4)
     uint64_t *keys;          // sort keys (ccap + 2)
     uint32_t *bitmap;        // distinct-color bitmap, all zero between calls
     int64_t bitmap_bits;
@@ -482,3 +494,61 @@ __device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t 
         base += 64u;
     }
 }
+
+// ---------------------------------------------------------------------------
+// multi-word color masks: bit d of word w marks color base + 64 * w + d + 1
+// (static word indices only, so the words stay in registers)
+// ---------------------------------------------------------------------------
+
+template <int NW>
+struct CMask {
+    uint64_t w[NW];
+    __device__ inline void clear() {
+#pragma unroll
+        for (int i = 0; i < NW; i++) w[i] = 0;
+    }
+    // marks color base + d + 1 when d < 64 * NW (d = color - base - 1, unsigned)
+    __device__ inline void set(uint32_t d) {
+        const uint32_t wi = d >> 6;
+        const uint64_t bit = 1ull << (d & 63u);
+#pragma unroll
+        for (int i = 0; i < NW; i++) w[i] |= (wi == (uint32_t)i) ? bit : 0ull;
+    }
+    template <int G>
+    __device__ inline void group_or() {
+#pragma unroll
+        for (int i = 0; i < NW; i++) w[i] = group_or_u64<G>(w[i]);
+    }
+    __device__ inline void group_or_rt(int gsz) {
+#pragma unroll
+        for (int i = 0; i < NW; i++)
+            for (int o = gsz >> 1; o > 0; o >>= 1) w[i] |= __shfl_xor(w[i], o);
+    }
+    // smallest unmarked position + 1 in [1, 64 * NW], or 0 if every bit is set
+    __device__ inline uint32_t first_free() const {
+        uint32_t r = 0;
+#pragma unroll
+        for (int i = NW - 1; i >= 0; i--)
+            if (~w[i]) r = 64u * i + (uint32_t)__ffsll((long long)~w[i]);
+        return r;
+    }
+    // position + 1 of the (j+1)-th unmarked bit, or 0 and j reduced by the free count
+    __device__ inline uint32_t nth_free(uint32_t &j) const {
+        uint32_t r = 0;
+        bool found = false;
+#pragma unroll
+        for (int i = 0; i < NW; i++) {
+            const uint64_t fr = ~w[i];
+            const uint32_t cnt = (uint32_t)__popcll(fr);
+            if (!found) {
+                if (j < cnt) {
+                    r = 64u * i + 1u + nth_set_bit(fr, j);
+                    found = true;
+                } else {
+                    j -= cnt;
+                }
+            }
+        }
+        return r;
+    }
+};

@@ -3,8 +3,8 @@
 // RV / NI / ND / RAND class permutations).
 //
 // Steps on the device:
-//   1. histogram of the input colors (workgroup-private in LDS), split by
-//      degree bin (bin 1 = rows longer than deg_wave), and the max color;
+//   1. histogram of the input colors (workgroup-private in LDS) split by
+//      degree bin, and the max color;
 //   2. class order (one workgroup): compacts the non-empty classes, orders
 //      them, gives every color its rank, and lays out the grouped vertex list
 //      as segments (rank, bin) with list offsets and work-chunk offsets;
@@ -13,20 +13,27 @@
 //   4. class walk: every vertex of rank s takes the smallest positive color
 //      not held by a neighbor of lower rank (those are recolored before it).
 //
+// Degree bins (per rank): bin 0 rows up to deg_wave entries, one group of G
+// lanes per vertex; bin 1 rows up to deg_split entries, one wavefront per
+// vertex; bin 2 longer rows, cut into split_len-entry sub-chunks scanned by
+// different wavefronts, whose partial color masks meet in a per-row global
+// bitmap; the wavefront that finishes last publishes the color.
+//
 // The walk runs as ONE persistent launch (every workgroup resident) without
-// grid barriers.
-// Work chunks never straddle two ranks and every wavefront takes its chunks
-// in increasing order, so a vertex only ever waits for vertices of earlier
-// chunks: a vertex of rank s reads each neighbor's word; a positive word is a
-// final color of a lower rank; a negative word names the neighbor's rank, and
-// only ranks below s are waited for (an agent-scope load loop, bounded).
-// With every workgroup co-resident the earliest
-// unfinished chunk can always proceed, so the walk cannot deadlock.  Final
-// colors are written with agent-scope stores so that waiting wavefronts on
-// other XCDs see them; a word only ever changes from negative to its final
-// positive value, so a plain (possibly L2-stale) load that sees a positive
-// value is exact, and a stale negative value of a lower rank just falls into
-// the coherent wait loop.
+// grid barriers.  Work chunks never straddle two segments and every
+// wavefront takes its chunks in increasing order, so a vertex only ever waits
+// for vertices of earlier chunks: a vertex of rank s reads each neighbor's
+// word; a positive word is a final color of a lower rank; a negative word
+// names the neighbor's rank, and only ranks below s are waited for (an
+// agent-scope load loop, bounded).  With every workgroup co-resident the
+// earliest unfinished chunk can always proceed, so the walk cannot deadlock
+// (a split row's color appears when its last sub-chunk ends, and all its
+// sub-chunks come before any chunk that waits for it).  Final colors are
+// written with agent-scope stores so that waiting wavefronts on other XCDs
+// see them; a word only ever changes from negative to its final positive
+// value, so a plain (possibly L2-stale) load that sees a positive value is
+// exact, and a stale negative value of a lower rank just falls into the
+// coherent wait loop.
 #include "gc_internal.h"
 
 #define HIST_LDS 4096       // colors below this use the workgroup-private histogram
@@ -36,10 +43,19 @@
 #define SCATTER_ITEMS 4
 #define WALK_BLOCK 256
 #define SPIN_LIMIT (1u << 20)
+#define NSEG_PER_RANK 3
+#define HUB_WORDS 64        // mask words per split row: colors 1..4096
+#define HUB_MAX_RANK (64 * HUB_WORDS - 1)  // higher ranks keep long rows in the wavefront bin
+
+// bin of a row of length d (a split row of a rank above HUB_MAX_RANK goes to bin 1 later)
+__device__ inline int row_bin(int32_t d, int32_t deg_wave, int32_t deg_split) {
+    return d <= deg_wave ? 0 : ((deg_split > 0 && d > deg_split) ? 2 : 1);
+}
 
 __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t *__restrict__ rp, int64_t nnz,
-                       int32_t deg_wave, int32_t ccap, int32_t *__restrict__ hist, int32_t *__restrict__ histw,
-                       unsigned long long *scal) {
+                       int32_t deg_wave, int32_t deg_split, int32_t split_len, int32_t ccap,
+                       int32_t *__restrict__ hist, int32_t *__restrict__ histw, int32_t *__restrict__ hist_s,
+                       int32_t *__restrict__ hist_sc, unsigned long long *scal) {
     __shared__ int32_t h[HIST_LDS], hw[HIST_LDS];
     __shared__ int32_t lds[32];
     for (int i = threadIdx.x; i < HIST_LDS; i += blockDim.x) { h[i] = 0; hw[i] = 0; }
@@ -49,8 +65,8 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         const int64_t v = base + threadIdx.x;
-        int32_t c = 0;
-        bool valid = false, wave = false;
+        int32_t c = 0, bin = 0, d = 0;
+        bool valid = false;
         if (v < n) {
             c = Cin[v];
             mx = max(mx, c);
@@ -59,15 +75,20 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
                 valid = true;
                 int32_t e0, e1;
                 row_range(rp, (int32_t)v, nnz, e0, e1);
-                wave = e1 - e0 > deg_wave;
+                d = e1 - e0;
+                bin = row_bin(d, deg_wave, deg_split);
             }
         }
         const bool in_lds = valid && c < HIST_LDS;
         (void)wave_match_reserve_bits(h, c, in_lds, HIST_BITS);
-        (void)wave_match_reserve_bits(hw, c, in_lds && wave, HIST_BITS);
+        (void)wave_match_reserve_bits(hw, c, in_lds && bin == 1, HIST_BITS);
         if (valid && !in_lds) {
             atomicAdd(&hist[c], 1);
-            if (wave) atomicAdd(&histw[c], 1);
+            if (bin == 1) atomicAdd(&histw[c], 1);
+        }
+        if (valid && bin == 2) {  // rare: long rows
+            atomicAdd(&hist_s[c], 1);
+            atomicAdd(&hist_sc[c], (d + split_len - 1) / split_len);
         }
     }
     const int32_t bmax = block_max_i32(mx, lds);  // synchronizes the block
@@ -81,33 +102,45 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXC], bmax);
 }
 
-// Class order and segment layout (one workgroup).  Segment 2s holds the
-// rank-s vertices of the lane-group bin, segment 2s+1 those of the
-// wavefront bin.  off[g] / coff[g]: first list slot / first work chunk of
-// segment g (off[2k] = n, coff[2k] = chunks); cursor[g] = off[g].  A chunk is
-// vpc vertices of a lane-group segment or one vertex of a wavefront segment.
+// Class order and segment layout (one workgroup).  Segment 3s + b holds the
+// rank-s vertices of bin b.  off[g] / coff[g]: first list slot / first work
+// chunk of segment g (off[3k] = n, coff[3k] = chunks); cursor[g] = off[g];
+// sbase[s]: first hub slot of segment 3s + 2.  A chunk is 64 / G vertices of
+// a bin-0 segment, one vertex of a bin-1 segment, split_len entries of a row
+// of a bin-2 segment.
 __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int32_t perm, uint32_t s_perm, int32_t vpc,
-                                                               int32_t *hist, int32_t *histw, int32_t *cls, int32_t *pi,
+                                                               int32_t *hist, int32_t *histw, int32_t *hist_s,
+                                                               int32_t *hist_sc, int32_t *cls, int32_t *pi,
                                                                int32_t *rank, int32_t *off, int32_t *coff,
-                                                               int32_t *cursor, unsigned long long *scal) {
+                                                               int32_t *cursor, int32_t *sbase,
+                                                               unsigned long long *scal) {
     __shared__ int32_t lds[32];
     int32_t maxc = (int32_t)scal[S_MAXC];
     if (maxc > ccap) maxc = ccap;
     const int32_t k = block_class_order(maxc, perm, s_perm, hist, cls, pi, rank, nullptr, nullptr, lds);
-    const int32_t nseg = 2 * k;
+    const int32_t nseg = NSEG_PER_RANK * k;
     int32_t acc = 0, cacc = 0;
     for (int32_t base = 0; base < nseg; base += blockDim.x) {
-        int32_t g = base + (int32_t)threadIdx.x;
+        const int32_t g = base + (int32_t)threadIdx.x;
         int32_t sz = 0, ch = 0;
         if (g < nseg) {
-            int32_t c = pi[g >> 1];
-            int32_t w = histw[c];
-            sz = (g & 1) ? w : hist[c] - w;
-            ch = (g & 1) ? sz : (sz + vpc - 1) / vpc;
+            const int32_t s = g / NSEG_PER_RANK, b = g % NSEG_PER_RANK;
+            const int32_t c = pi[s];
+            const bool split = s <= HUB_MAX_RANK;
+            if (b == 0) {
+                sz = hist[c] - histw[c] - hist_s[c];
+                ch = (sz + vpc - 1) / vpc;
+            } else if (b == 1) {
+                sz = histw[c] + (split ? 0 : hist_s[c]);
+                ch = sz;
+            } else if (split) {
+                sz = hist_s[c];
+                ch = hist_sc[c];
+            }
         }
         int32_t tot, ctot;
-        int32_t ex = block_exclusive_scan(sz, &tot, lds);
-        int32_t cex = block_exclusive_scan(ch, &ctot, lds);
+        const int32_t ex = block_exclusive_scan(sz, &tot, lds);
+        const int32_t cex = block_exclusive_scan(ch, &ctot, lds);
         if (g < nseg) {
             off[g] = acc + ex;
             cursor[g] = acc + ex;
@@ -115,6 +148,17 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
         }
         acc += tot;
         cacc += ctot;
+    }
+    // hub slot bases: prefix of the split-segment sizes over ranks
+    int32_t hacc = 0;
+    for (int32_t base = 0; base < k; base += blockDim.x) {
+        const int32_t s = base + (int32_t)threadIdx.x;
+        int32_t sz = 0;
+        if (s < k && s <= HUB_MAX_RANK) sz = hist_s[pi[s]];
+        int32_t tot;
+        const int32_t ex = block_exclusive_scan(sz, &tot, lds);
+        if (s < k) sbase[s] = hacc + ex;
+        hacc += tot;
     }
     if (threadIdx.x == 0) {
         off[nseg] = acc;
@@ -125,20 +169,23 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
     for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) {
         hist[c] = 0;
         histw[c] = 0;
+        hist_s[c] = 0;
+        hist_sc[c] = 0;
     }
 }
 
 // Counting-sort scatter into segments: one tile of SCATTER_ITEMS * blockDim
 // vertices per workgroup; segments below SCATTER_BINS reserve their list
-// range once per workgroup.  Writes Cout[v] = -(rank + 1).
+// range once per workgroup.  Writes Cout[v] = -(rank + 1) and the row range
+// next to each list entry.
 __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const int32_t *__restrict__ rp, int64_t nnz,
-                          int32_t deg_wave, int32_t ccap, const int32_t *__restrict__ rank, int32_t *__restrict__ cursor,
-                          int32_t *__restrict__ list, int2 *__restrict__ rows,
+                          int32_t deg_wave, int32_t deg_split, int32_t ccap, const int32_t *__restrict__ rank,
+                          int32_t *__restrict__ cursor, int32_t *__restrict__ list, int2 *__restrict__ rows,
                           const unsigned long long *__restrict__ scal) {
     __shared__ int32_t cnt[SCATTER_BINS];
     __shared__ int32_t basepos[SCATTER_BINS];
     const int32_t k = (int32_t)scal[S_K];
-    const int32_t nseg = 2 * k;
+    const int32_t nseg = NSEG_PER_RANK * k;
     const int32_t bins = nseg < SCATTER_BINS ? nseg : SCATTER_BINS;
     const int gbits = key_bits(bins);
     for (int i = threadIdx.x; i < bins; i += blockDim.x) cnt[i] = 0;
@@ -148,22 +195,25 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const in
     int2 rw[SCATTER_ITEMS];
 #pragma unroll
     for (int it = 0; it < SCATTER_ITEMS; it++) {
-        int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
+        const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
         sg[it] = -1;
         loc[it] = -1;
+        rw[it] = make_int2(0, 0);
         int32_t g = -1;
         if (v < n) {
-            int32_t c = Cin[v];
+            const int32_t c = Cin[v];
             if (c >= 1 && c <= ccap && k > 0) {
                 int32_t s = rank[c];
                 if ((uint32_t)s >= (uint32_t)k) s = k - 1;  // unreachable for a ranked color; keeps indices in bounds
                 int32_t e0, e1;
                 row_range(rp, (int32_t)v, nnz, e0, e1);
                 rw[it] = make_int2(e0, e1);
-                g = 2 * s + (e1 - e0 > deg_wave ? 1 : 0);
+                int b = row_bin(e1 - e0, deg_wave, deg_split);
+                if (b == 2 && s > HUB_MAX_RANK) b = 1;
+                g = NSEG_PER_RANK * s + b;
                 sg[it] = g;
                 if (g >= SCATTER_BINS) {
-                    int32_t p = atomicAdd(&cursor[g], 1);
+                    const int32_t p = atomicAdd(&cursor[g], 1);
                     list[p] = (int32_t)v;
                     rows[p] = rw[it];
                     Cout[v] = -(s + 1);
@@ -182,12 +232,28 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const in
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < SCATTER_ITEMS; it++) {
-        int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
+        const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
         if (loc[it] >= 0) {
             const int32_t p = basepos[sg[it]] + loc[it];
             list[p] = (int32_t)v;
             rows[p] = rw[it];
-            Cout[v] = -((sg[it] >> 1) + 1);
+            Cout[v] = -((sg[it] / NSEG_PER_RANK) + 1);
+        }
+    }
+}
+
+// For every split segment: the first chunk of each of its rows (prefix of
+// ceil(len / split_len) in list order).  One thread per rank.
+__global__ void k_split_prefix(const int32_t *__restrict__ off, const int2 *__restrict__ rows, int32_t split_len,
+                               int32_t *__restrict__ hsub, const unsigned long long *__restrict__ scal) {
+    const int32_t k = (int32_t)scal[S_K];
+    for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < k; s += gridDim.x * blockDim.x) {
+        const int32_t g = NSEG_PER_RANK * s + 2;
+        int32_t acc = 0;
+        for (int32_t p = off[g]; p < off[g + 1]; p++) {
+            hsub[p] = acc;
+            const int2 r = rows[p];
+            acc += (r.y - r.x + split_len - 1) / split_len;
         }
     }
 }
@@ -208,79 +274,191 @@ __device__ inline int32_t wait_positive(int32_t *p, unsigned long long *scal) {
     return 0;
 }
 
-
-// One work chunk as a wavefront sees it: segment (rank 2s / 2s+1 = bin), the
-// vertex of this lane's group (-1: none) and its row.
+// One work chunk as a wavefront sees it: segment, the vertex of this lane's
+// group (-1: none) and the part of its row this chunk scans; for a split row
+// also its hub slot and number of sub-chunks.
 struct WalkChunk {
-    int32_t seg, v, e0, e1;
+    int32_t seg, v, e0, e1, slot, nsub;
 };
 
-// Persistent dataflow class walk (one launch per pass).
-//
-// Chunk assignment.  With xcd != 0 (and a grid that is a multiple of 8) the
-// chunks of every segment are cut into 8 consecutive parts and part x goes to
-// the workgroups b with b % 8 == x, which the hardware places on XCD x: the
-// same region of the vertex order (for a mesh, the same slab) stays on one
-// XCD for every class, so the neighbor colors it gathers stay in that XCD's
-// L2.  Otherwise chunks go round robin over all wavefronts.  Either way every
-// wavefront takes its chunks in increasing global order (segments in order,
-// increasing position inside a segment), which the deadlock argument needs.
-//
-// Software pipeline (per wavefront): while chunk i gathers its neighbors'
-// colors (the only loads that depend on earlier classes), chunk i+1's first
-// U neighbor ids and chunk i+2's vertex and row are already being loaded, so
-// one memory round trip per chunk sits on the dependency path instead of
-// four.  Group size: G lanes per vertex in even (lane-group) segments, the
-// whole wavefront in odd (long-row) segments.
-#define WALK_TAB 1024  // segment tables of up to WALK_TAB segments (512 classes) live in LDS
-
-template <int G, bool LDS_TAB>
-__device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, int32_t nseg,
-                                          const int2 *__restrict__ rows, const int32_t *__restrict__ col, int64_t nnz,
-                                          int32_t n, int32_t *C, const int32_t *__restrict__ list,
-                                          unsigned long long *scal, int32_t xcd);
-
-template <int G>
-__global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict__ rows, const int32_t *__restrict__ col,
-                                                          int64_t nnz, int32_t n, int32_t *C,
-                                                          const int32_t *__restrict__ list, const int32_t *__restrict__ off,
-                                                          const int32_t *__restrict__ coff, unsigned long long *scal,
-                                                          int32_t xcd, int32_t check_resident) {
-    __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
-    if (check_resident) {
-        // start barrier, bounded: every workgroup checks in and waits for all
-        // others; a timeout means they were not all resident (error bit 4).
-        // check_resident == 2: residency probe only (short limit, no work).
-        const uint32_t limit = check_resident == 2 ? (1u << 14) : SPIN_LIMIT;
-        if (threadIdx.x == 0) {
-            atomicAdd(&scal[S_TICKET], 1ull);
-            uint32_t it = 0;
-            while (__hip_atomic_load(&scal[S_TICKET], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
-                if (++it > limit) { atomicOr(&scal[S_ERR], 4ull); break; }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __syncthreads();
-        if (check_resident == 2) return;
-    }
-    const int32_t k = (int32_t)scal[S_K];
-    const int32_t nseg = 2 * k;
-    if (nseg <= WALK_TAB) {
-        // segment tables in LDS: their reads are tracked apart from the vector
-        // loads in flight, so looking up the next chunk never drains the pipeline
-        for (int32_t i = threadIdx.x; i <= nseg; i += WALK_BLOCK) { t_off[i] = off[i]; t_coff[i] = coff[i]; }
-        __syncthreads();
-        walk_body<G, true>(t_off, t_coff, nseg, rows, col, nnz, n, C, list, scal, xcd);
-    } else {
-        walk_body<G, false>(off, coff, nseg, rows, col, nnz, n, C, list, scal, xcd);
+// Marks color x (> base) for First Fit: colors base+1 .. base+64 in the
+// register word m; with WIDE also colors base+65 .. base+64*(gw+1) in the
+// group's LDS words lw[gfirst + o].  Words <= 0 (ranks >= s, invalid ids)
+// fall outside both.
+template <bool WIDE>
+__device__ inline void mark(int32_t x, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw) {
+    const uint32_t d = (uint32_t)x - base - 1u;
+    m |= (d < 64u ? 1ull : 0ull) << (d & 63u);
+    if (WIDE) {
+        const uint32_t o = (d >> 6) - 1u;
+        if (o < (uint32_t)gw) atomicOr(&lw[gfirst + (int)o], 1ull << (d & 63u));
     }
 }
 
-template <int G, bool LDS_TAB>
+// Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
+// that are not final yet are waited for in one wavefront-uniform slow path;
+// the rest is branch-free.
+template <int U, bool WIDE>
+__device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t base, uint64_t &m,
+                              unsigned long long *lw, int gfirst, int gw, int32_t *C, unsigned long long *scal) {
+    bool need = false;
+#pragma unroll
+    for (int u = 0; u < U; u++) need |= xv[u] < 0 && -xv[u] - 1 < s;
+    if (__ballot(need)) {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (xv[u] < 0) xv[u] = (-xv[u] - 1 < s) ? wait_positive(&C[w[u]], scal) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) mark<WIDE>(xv[u], base, m, lw, gfirst, gw);
+}
+
+// Gathers the colors of the neighbor ids w (invalid ids read as 0).
+template <int U>
+__device__ inline void gather(const int32_t *w, int32_t *xv, const int32_t *C, int32_t n) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const bool ok = (uint32_t)w[u] < (uint32_t)n;
+        const int32_t xl = C[ok ? w[u] : 0];
+        xv[u] = ok ? xl : 0;
+    }
+}
+
+// Scans row entries [e, e1) with stride gsz (this lane's share), U at a time.
+template <int U, bool WIDE>
+__device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t *__restrict__ col, int32_t n,
+                                  int32_t s, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw,
+                                  int32_t *C, unsigned long long *scal) {
+    for (int32_t eb = e; __ballot(eb < e1); eb += U * gsz) {
+        int32_t ww[U], xx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int32_t eu = eb + u * gsz;
+            const bool ok = eu < e1;
+            const int32_t wl = col[ok ? eu : 0];
+            ww[u] = ok ? wl : -1;
+        }
+        gather<U>(ww, xx, C, n);
+        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, scal);
+    }
+}
+
+__device__ inline uint64_t group_or_rt(uint64_t m, int gsz) {
+    for (int o = gsz >> 1; o > 0; o >>= 1) m |= __shfl_xor(m, o);
+    return m;
+}
+
+// First Fit for bins 0 and 1.  Colors 1..64 are tracked in a register word;
+// with WIDE (ranks >= 64) each group also owns gsz LDS words (one per lane of
+// the group: this lane's word is lw[lane]) for colors 65 .. 64 * (gsz + 1).
+// Colors beyond (a free color is at most the row length + 1) rescan the row
+// in 64-color windows.  The first window takes the prefetched ids w.
+template <int U, bool WIDE>
+__device__ inline void finish_row(const WalkChunk &t, const int32_t *w, int gsz, const int32_t *__restrict__ col,
+                                  int32_t n, int32_t *C, unsigned long long *lw, unsigned long long *scal) {
+    const int32_t s = t.seg / NSEG_PER_RANK;
+    const int lane = __lane_id();
+    const int l = lane & (gsz - 1);
+    const int gfirst = lane - l;
+    if (WIDE) {
+        lw[lane] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    uint64_t m = 0;
+    int32_t xv[U];
+    gather<U>(w, xv, C, n);
+    absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, scal);
+    scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, scal);
+    m = group_or_rt(m, gsz);
+    uint32_t r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
+    uint32_t base = 0;
+    if (WIDE) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (r == 0) {
+            const uint64_t word = lw[lane];
+            const uint64_t gmask = gsz == 64 ? ~0ull : (((1ull << gsz) - 1ull) << gfirst);
+            const uint64_t fr = __ballot(~word != 0ull) & gmask;
+            if (fr) {
+                const int fl = __ffsll((long long)fr) - 1;
+                const uint64_t wf = __shfl(word, fl);
+                r = 64u * (uint32_t)(fl - gfirst + 1) + (uint32_t)__ffsll((long long)~wf);
+            } else {
+                base = 64u * (uint32_t)gsz;  // windows beyond the LDS words start above them
+            }
+        }
+    }
+    while (r == 0) {
+        base += 64u;
+        m = 0;
+        scan_range<U, false>(t.e0 + l, t.e1, gsz, col, n, s, base, m, lw, gfirst, 0, C, scal);
+        m = group_or_rt(m, gsz);
+        r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
+    }
+    if (t.v >= 0 && l == 0) __hip_atomic_store(&C[t.v], (int32_t)(base + r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One sub-chunk of a split row (bin 2, whole wavefront).  The colors of lower
+// ranks among its entries (colors 1..64 in a register word, 65..4096 in the
+// wavefront's LDS words) go into the row's global bitmap; the sub-chunk that
+// ends last reads the bitmap, publishes the color and clears the slot for the
+// next pass.
+template <int U>
+__device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const int32_t *__restrict__ col, int32_t n,
+                                    int32_t *C, unsigned long long *lw, unsigned long long *hub_bits, int32_t *hub_cnt,
+                                    unsigned long long *scal) {
+    const int32_t s = t.seg / NSEG_PER_RANK;
+    const int lane = __lane_id();
+    const int32_t words = (s >> 6) + 1;  // lower ranks hold colors 1..s: words 0 .. s / 64
+    unsigned long long *bits = hub_bits + (int64_t)t.slot * HUB_WORDS;
+    lw[lane] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint64_t m = 0;
+    int32_t xv[U];
+    gather<U>(w, xv, C, n);
+    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
+    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
+    m = group_or_rt(m, 64);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // word i of the row: register word for i = 0, LDS word i - 1 above
+    const uint64_t lword = lane >= 1 ? lw[lane - 1] : 0ull;
+    const uint64_t mine = lane == 0 ? m : lword;
+    if (lane < words && mine) atomicOr(&bits[lane], mine);
+    __threadfence();
+    int32_t done = 0;
+    if (lane == 0) done = atomicAdd(&hub_cnt[t.slot], 1) + 1;
+    done = __shfl(done, 0);
+    if (done == t.nsub) {
+        __threadfence();
+        // every sub-chunk's bits are in: first free color of the row
+        const uint64_t word = lane < words ? atomicOr(&bits[lane], 0ull) : ~0ull;
+        const uint64_t fr = __ballot(~word != 0ull);
+        uint32_t r = 64u * (uint32_t)words + 1u;  // unreachable: at most s colors are taken
+        if (fr) {
+            const int first = __ffsll((long long)fr) - 1;
+            const uint64_t wf = __shfl(word, first);
+            r = 64u * (uint32_t)first + (uint32_t)__ffsll((long long)~wf);
+        }
+        if (lane < words) atomicExch(&bits[lane], 0ull);
+        if (lane == 0) {
+            atomicExch(&hub_cnt[t.slot], 0);
+            __hip_atomic_store(&C[t.v], (int32_t)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+#define WALK_TAB 1536  // segment tables of up to WALK_TAB segments (512 classes) live in LDS
+
+template <int G, bool LDS_TAB, bool FULL>
 __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, int32_t nseg,
-                                          const int2 *__restrict__ rows, const int32_t *__restrict__ col, int64_t nnz,
+                                          const int2 *__restrict__ rows, const int32_t *__restrict__ col,
                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
-                                          unsigned long long *scal, int32_t xcd) {
+                                          const int32_t *__restrict__ hsub, const int32_t *__restrict__ sbase,
+                                          int32_t split_len, unsigned long long *hub_bits, int32_t *hub_cnt,
+                                          unsigned long long *scal, int32_t xcd, unsigned long long *lw) {
     constexpr int U = 32 / G > 4 ? 32 / G : 4;
     const int lane = __lane_id();
     const int wpb = WALK_BLOCK / 64;
@@ -304,25 +482,52 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             c = lo + (me + Wx - s0 % Wx) % Wx;  // rotate so that short segments do not all land on the first wavefronts
         }
     };
-    // stage A: vertex and row of the chunk under the cursor, then advance
+    // stage A: vertex and row part of the chunk under the cursor, then advance
     auto load_chunk = [&](WalkChunk &t) {
         t.seg = seg;
         t.v = -1;
         t.e0 = t.e1 = 0;
+        t.slot = 0;
+        t.nsub = 1;
         if (seg >= nseg) return;
         const int32_t lo = O[seg], hi2 = O[seg + 1];
         const int32_t j = (int32_t)(c - (uint32_t)CO[seg]);
-        const int32_t pos = (seg & 1) ? lo + j : lo + j * (64 / G) + (lane / G);
-        const bool ok = pos < hi2;
-        const int32_t p = ok ? pos : lo;  // lo < hi2: the segment is not empty
-        const int32_t vv = list[p];
-        const int2 r = rows[p];
-        if (ok) { t.v = vv; t.e0 = r.x; t.e1 = r.y; }
+        const int b = seg % NSEG_PER_RANK;
+        if (b == 2) {
+            // split row: the last list slot whose first chunk is <= j
+            int32_t a = lo, z = hi2 - 1;
+            while (a < z) {
+                const int32_t mid = (a + z + 1) >> 1;
+                if (hsub[mid] <= j) a = mid;
+                else z = mid - 1;
+            }
+            const int32_t sub = j - hsub[a];
+            const int2 r = rows[a];
+            const int32_t vv = list[a];
+            if (FULL) {
+                t.v = vv;
+                t.e0 = r.x + sub * split_len;
+                t.e1 = min(r.y, t.e0 + split_len);
+                t.slot = sbase[seg / NSEG_PER_RANK] + (a - lo);
+                t.nsub = (r.y - r.x + split_len - 1) / split_len;
+            } else if (sub == 0) {  // the first sub-chunk takes the whole row, the others are empty
+                t.v = vv;
+                t.e0 = r.x;
+                t.e1 = r.y;
+            }
+        } else {
+            const int32_t pos = b == 1 ? lo + j : lo + j * (64 / G) + (lane / G);
+            const bool ok = pos < hi2;
+            const int32_t p = ok ? pos : lo;  // lo < hi2: the segment is not empty
+            const int32_t vv = list[p];
+            const int2 r = rows[p];
+            if (ok) { t.v = vv; t.e0 = r.x; t.e1 = r.y; }
+        }
         advance();
     };
     // stage B: the first U neighbor ids of the chunk (unconditional loads at clamped indices)
     auto load_ids = [&](const WalkChunk &t, int32_t *w) {
-        const int gsz = (t.seg & 1) ? 64 : G;
+        const int gsz = (t.seg % NSEG_PER_RANK) ? 64 : G;
         const int32_t e = t.e0 + (lane & (gsz - 1));
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -332,85 +537,14 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             w[u] = ok ? wl : -1;
         }
     };
-    // neighbor color as First Fit needs it: final colors of lower ranks, 0 otherwise
-    auto color_of = [&](int32_t w, int32_t x0, int32_t s) -> int32_t {
-        if (x0 >= 0) return x0;
-        return (-x0 - 1 < s) ? wait_positive(&C[w], scal) : 0;
-    };
-    // Gathered words -> First Fit mask bits of colors 1..64.  Words of lower
-    // ranks that are not final yet are waited for in one wavefront-uniform
-    // slow path; otherwise the update is branch-free (values <= 0 wrap past 64).
-    auto absorb = [&](const int32_t *w, int32_t *xv, int32_t s, uint64_t &mask) {
-        bool need = false;
-#pragma unroll
-        for (int u = 0; u < U; u++) need |= xv[u] < 0 && -xv[u] - 1 < s;
-        if (__ballot(need)) {
-#pragma unroll
-            for (int u = 0; u < U; u++) xv[u] = color_of(w[u], xv[u], s);
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const uint32_t d = (uint32_t)xv[u] - 1u;
-            mask |= (d < 64u ? 1ull : 0ull) << (d & 63u);
-        }
-    };
     // stage C: gather, wait for lower ranks, First Fit, publish
     auto finish = [&](const WalkChunk &t, const int32_t *w) {
-        const int gsz = (t.seg & 1) ? 64 : G;
-        const int32_t s = t.seg >> 1;
-        const int l = lane & (gsz - 1);
-        int32_t xv[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const bool ok = (uint32_t)w[u] < (uint32_t)n;
-            const int32_t xl = C[ok ? w[u] : 0];
-            xv[u] = ok ? xl : 0;
-        }
-        uint64_t mask = 0;
-        absorb(w, xv, s, mask);
-        // rows longer than one batch
-        for (int32_t eb = t.e0 + l + U * gsz; __ballot(eb < t.e1); eb += U * gsz) {
-            int32_t ww[U], xx[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int32_t eu = eb + u * gsz;
-                const bool ok = eu < t.e1;
-                const int32_t wl = col[ok ? eu : t.e0];
-                ww[u] = ok ? wl : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const bool ok = (uint32_t)ww[u] < (uint32_t)n;
-                const int32_t xl = C[ok ? ww[u] : 0];
-                xx[u] = ok ? xl : 0;
-            }
-            absorb(ww, xx, s, mask);
-        }
-        for (int o = gsz >> 1; o > 0; o >>= 1) mask |= __shfl_xor(mask, o);
-        int32_t ans;
-        if (mask != ~0ull) {
-            ans = (int32_t)__ffsll((long long)~mask);
-        } else {
-            // colors 1..64 all taken: look further, 64 colors per scan (every
-            // lower-rank neighbor is final by now; a stale read just waits again)
-            uint32_t base = 64;
-            for (;;) {
-                uint64_t m2 = 0;
-                for (int32_t e = t.e0 + l; e < t.e1; e += gsz) {
-                    const int32_t w2 = col[e];
-                    if ((uint32_t)w2 >= (uint32_t)n) continue;
-                    const uint32_t d = (uint32_t)color_of(w2, C[w2], s) - base - 1u;
-                    if (d < 64u) m2 |= 1ull << d;
-                }
-                for (int o = gsz >> 1; o > 0; o >>= 1) m2 |= __shfl_xor(m2, o);
-                if (m2 != ~0ull) {
-                    ans = (int32_t)(base + (uint32_t)__ffsll((long long)~m2));
-                    break;
-                }
-                base += 64;
-            }
-        }
-        if (t.v >= 0 && l == 0) __hip_atomic_store(&C[t.v], ans, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int b = t.seg % NSEG_PER_RANK;
+        const int32_t s = t.seg / NSEG_PER_RANK;
+        if (!FULL) finish_row<U, false>(t, w, b ? 64 : G, col, n, C, lw, scal);
+        else if (b == 2) finish_split<U>(t, w, col, n, C, lw, hub_bits, hub_cnt, scal);
+        else if (s < 64) finish_row<U, false>(t, w, b ? 64 : G, col, n, C, lw, scal);
+        else finish_row<U, true>(t, w, b ? 64 : G, col, n, C, lw, scal);
     };
 
     advance();
@@ -430,10 +564,67 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     }
 }
 
+// Persistent dataflow class walk (one launch per pass).
+//
+// Chunk assignment.  With xcd != 0 (and a grid that is a multiple of 8) the
+// chunks of every segment are cut into 8 consecutive parts and part x goes to
+// the workgroups b with b % 8 == x, which the hardware places on XCD x: the
+// same region of the vertex order (for a mesh, the same slab) stays on one
+// XCD for every class, so the neighbor colors it gathers stay in that XCD's
+// L2.  Otherwise chunks go round robin over all wavefronts.  Either way every
+// wavefront takes its chunks in increasing global order (segments in order,
+// increasing position inside a segment), which the deadlock argument needs.
+//
+// Software pipeline (per wavefront): while chunk i gathers its neighbors'
+// colors (the only loads that depend on earlier classes), chunk i+1's first
+// U neighbor ids and chunk i+2's vertex and row are already being loaded.
+template <int G, bool FULL>
+__global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict__ rows, const int32_t *__restrict__ col,
+                                                          int32_t n, int32_t *C, const int32_t *__restrict__ list,
+                                                          const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ coff,
+                                                          const int32_t *__restrict__ hsub,
+                                                          const int32_t *__restrict__ sbase, int32_t split_len,
+                                                          unsigned long long *hub_bits, int32_t *hub_cnt,
+                                                          unsigned long long *scal, int32_t xcd, int32_t check_resident) {
+    __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
+    __shared__ unsigned long long lmask[WALK_BLOCK];  // per wavefront: 64 mask words for colors above 64
+    unsigned long long *lw = lmask + (threadIdx.x & ~63u);
+    if (check_resident) {
+        // start barrier, bounded: every workgroup checks in and waits for all
+        // others; a timeout means they were not all resident (error bit 4).
+        // check_resident == 2: residency probe only (short limit, no work).
+        const uint32_t limit = check_resident == 2 ? (1u << 14) : SPIN_LIMIT;
+        if (threadIdx.x == 0) {
+            atomicAdd(&scal[S_TICKET], 1ull);
+            uint32_t it = 0;
+            while (__hip_atomic_load(&scal[S_TICKET], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+                if (++it > limit) { atomicOr(&scal[S_ERR], 4ull); break; }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (check_resident == 2) return;
+    }
+    const int32_t k = (int32_t)scal[S_K];
+    const int32_t nseg = NSEG_PER_RANK * k;
+    if (nseg <= WALK_TAB) {
+        // segment tables in LDS: their reads are tracked apart from the vector
+        // loads in flight, so looking up the next chunk never drains the pipeline
+        for (int32_t i = threadIdx.x; i <= nseg; i += WALK_BLOCK) { t_off[i] = off[i]; t_coff[i] = coff[i]; }
+        __syncthreads();
+        walk_body<G, true, FULL>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt, scal,
+                           xcd, lw);
+    } else {
+        walk_body<G, false, FULL>(off, coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt, scal,
+                            xcd, lw);
+    }
+}
+
 // One launch per class (host loop): every vertex of rank s, one lane each.
 __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
                              int32_t *C, const int32_t *__restrict__ list, const int32_t *__restrict__ off, int32_t s) {
-    const int32_t a = off[2 * s], b = off[2 * s + 2];
+    const int32_t a = off[NSEG_PER_RANK * s], b = off[NSEG_PER_RANK * s + NSEG_PER_RANK];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += stride) {
         int32_t v = list[i];
@@ -443,25 +634,93 @@ __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__re
     }
 }
 
-typedef void (*walk_fn)(const int2 *, const int32_t *, int64_t, int32_t, int32_t *, const int32_t *, const int32_t *,
-                        const int32_t *, unsigned long long *, int32_t, int32_t);
+typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const int32_t *, const int32_t *,
+                        const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
+                        unsigned long long *, int32_t, int32_t);
 
-static walk_fn walk_kernel(int G) {
+template <bool FULL>
+static walk_fn walk_kernel_t(int G) {
     switch (G) {
-        case 1: return k_walk_flow<1>;
-        case 2: return k_walk_flow<2>;
-        case 4: return k_walk_flow<4>;
-        case 8: return k_walk_flow<8>;
-        case 16: return k_walk_flow<16>;
-        case 32: return k_walk_flow<32>;
-        default: return k_walk_flow<64>;
+        case 1: return k_walk_flow<1, FULL>;
+        case 2: return k_walk_flow<2, FULL>;
+        case 4: return k_walk_flow<4, FULL>;
+        case 8: return k_walk_flow<8, FULL>;
+        case 16: return k_walk_flow<16, FULL>;
+        case 32: return k_walk_flow<32, FULL>;
+        default: return k_walk_flow<64, FULL>;
     }
 }
 
-static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, hipStream_t s) {
+static walk_fn walk_kernel(int G, bool full) { return full ? walk_kernel_t<true>(G) : walk_kernel_t<false>(G); }
+
+__global__ void k_max_degree(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, unsigned long long *scal) {
+    __shared__ int32_t lds[32];
+    int32_t mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e0, e1;
+        row_range(rp, (int32_t)v, nnz, e0, e1);
+        mx = max(mx, e1 - e0);
+    }
+    const int32_t bm = block_max_i32(mx, lds);
+    if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXDEG], bm);
+}
+
+// Longest row of g, computed once per graph (keyed by its arrays and sizes;
+// it only picks the walk variant, every variant colors any graph correctly).
+static gc_status graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out) {
+    if (ctx->deg_key_rp == g->row_ptr && ctx->deg_key_col == g->col_idx && ctx->deg_key_n == g->n &&
+        ctx->deg_key_nnz == g->nnz) {
+        *out = ctx->deg_max;
+        return GC_OK;
+    }
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXDEG, 0, 8, s));
+    const int grid = gc_grid(ctx, g->n, 256) < 2 * ctx->num_cu ? gc_grid(ctx, g->n, 256) : 2 * ctx->num_cu;
+    k_max_degree<<<grid, 256, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
+    GC_LAUNCHED();
+    gc_status st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    ctx->deg_max = (int32_t)ctx->hscal[S_MAXDEG];
+    ctx->deg_key_rp = g->row_ptr;
+    ctx->deg_key_col = g->col_idx;
+    ctx->deg_key_n = g->n;
+    ctx->deg_key_nnz = g->nnz;
+    *out = ctx->deg_max;
+    return GC_OK;
+}
+
+// Hub slots for rows longer than deg_split: at most nnz / (deg_split + 1) rows.
+static gc_status ensure_hub_slots(gc_ctx *ctx, const gc_csr *g, int32_t deg_split, hipStream_t s) {
+    const int64_t need = g->nnz / ((int64_t)deg_split + 1) + 1;
+    if (need <= ctx->hub_cap) return GC_OK;
+    GC_HIP(hipStreamSynchronize(s));
+    if (ctx->hub_bits) { GC_HIP(hipFree(ctx->hub_bits)); ctx->hub_bits = nullptr; }
+    if (ctx->hub_cnt) { GC_HIP(hipFree(ctx->hub_cnt)); ctx->hub_cnt = nullptr; }
+    ctx->hub_cap = 0;
+    const int64_t cap = need + 64;
+    if (hipMalloc((void **)&ctx->hub_bits, (size_t)cap * HUB_WORDS * 8) != hipSuccess ||
+        hipMalloc((void **)&ctx->hub_cnt, (size_t)cap * 4) != hipSuccess)
+        return gc_fail(ctx, GC_ERR_OOM, "hub slots (%lld)", (long long)cap);
+    GC_HIP(hipMemsetAsync(ctx->hub_bits, 0, (size_t)cap * HUB_WORDS * 8, s));
+    GC_HIP(hipMemsetAsync(ctx->hub_cnt, 0, (size_t)cap * 4, s));
+    ctx->hub_cap = cap;
+    return GC_OK;
+}
+
+// full: the variant with split rows and LDS mask words (rows of 64 or more
+// entries); the narrow one keeps only a 64-color register window (further
+// windows rescan the row) and lets the first sub-chunk of a split row scan the
+// whole row.
+static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
     const int G = ctx->tune.group;
-    walk_fn f = walk_kernel(G);
-    if (ctx->walk_blocks == 0 || ctx->walk_blocks_group != G) {
+    walk_fn f = walk_kernel(G, full);
+    const int variant = 2 * G + (full ? 1 : 0);
+    // the walk reads col[0] unconditionally (masked afterwards): give it one valid word when the graph has no edges
+    const int32_t *col = g->nnz > 0 ? g->col_idx : (const int32_t *)ctx->scal;
+    // without split rows the hub arrays are never touched
+    int32_t *hub_cnt = ctx->hub_cnt ? ctx->hub_cnt : (int32_t *)ctx->scal;
+    unsigned long long *hub_bits = ctx->hub_bits ? ctx->hub_bits : ctx->scal;
+    const int32_t split_len = ctx->tune.split_len;
+    if (ctx->walk_blocks == 0 || ctx->walk_blocks_group != variant) {
         // The occupancy query is an upper bound; the walk needs every workgroup
         // resident at once, so measure it: a probe launch (no work) where every
         // workgroup checks in and waits, bounded, for all the others.  Step the
@@ -475,8 +734,8 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, hipS
             if (blocks >= 8) blocks -= blocks & 7;
             GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
             GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
-            hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, (const int32_t *)ctx->scal, g->nnz, g->n, C, ctx->list,
-                               ctx->off, ctx->coff, ctx->scal, 0, 2);
+            hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C, ctx->list, ctx->off,
+                               ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2);
             GC_LAUNCHED();
             gc_status st = gc_sync_scalars(ctx, s);
             if (st) return st;
@@ -485,20 +744,19 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, hipS
         if (per_cu < 1) return gc_fail(ctx, GC_ERR_DEVICE, "walk kernel: no grid was fully resident");
         GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
         ctx->walk_blocks = blocks;
-        ctx->walk_blocks_group = G;
+        ctx->walk_blocks_group = variant;
     }
-    // An ordinary stream-ordered launch whose grid is exactly what the device
-    // holds at once: the kernel starts after the previous kernel of the stream
-    // has finished, so every workgroup is dispatched at once on an otherwise idle
-    // device (kernels of other streams can only delay some workgroups until they
-    // finish; the bounded waits keep even that case from hanging).
+    // An ordinary stream-ordered launch whose grid is what the device holds at
+    // once (measured above): the kernel starts after the previous kernel of the
+    // stream has finished, so every workgroup is dispatched at once on an
+    // otherwise idle device (kernels of other streams can only delay some
+    // workgroups until they finish; the bounded waits keep even that case from
+    // hanging).
     const int32_t xcd = ctx->tune.xcd_chunks > 0 ? 1 : 0;
     if (ctx->tune.check_resident) GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
-    // the walk reads col[0] unconditionally (masked afterwards): give it one valid word when the graph has no edges
-    const int32_t *col = g->nnz > 0 ? g->col_idx : (const int32_t *)ctx->scal;
-    GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col,
-                                              g->nnz, g->n, C, ctx->list, ctx->off, ctx->coff, ctx->scal, xcd,
-                                              ctx->tune.check_resident));
+    GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C,
+                                              ctx->list, ctx->off, ctx->coff, ctx->hsub, ctx->sbase, split_len,
+                                              hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident));
     GC_LAUNCHED();
     return GC_OK;
 }
@@ -520,22 +778,43 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
     const int block = 256;
     const int G = ctx->tune.group;
     const int32_t deg_wave = ctx->tune.deg_wave;
+    // the split bin exists in the persistent walk only
+    bool full = false;
+    if (ctx->tune.walk_mode == 0) {
+        int32_t maxdeg = 0;
+        status = graph_max_degree(ctx, g, s, &maxdeg);
+        if (status) return status;
+        full = maxdeg >= 64;
+    }
+    const int32_t deg_split = full ? ctx->tune.deg_split : 0;
+    const int32_t split_len = ctx->tune.split_len;
+    if (deg_split > 0) {
+        status = ensure_hub_slots(ctx, g, deg_split, s);
+        if (status) return status;
+    }
     const int hist_grid = gc_grid(ctx, n, block) < 2 * ctx->num_cu ? gc_grid(ctx, n, block) : 2 * ctx->num_cu;
     GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8, s));
     GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
-    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, ctx->ccap, ctx->hist,
-                                                     ctx->histw, ctx->scal));
+    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, deg_split,
+                                                             split_len, ctx->ccap, ctx->hist, ctx->histw, ctx->hist_s,
+                                                             ctx->hist_sc, ctx->scal));
     GC_LAUNCHED();
-    GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G,
-                                            ctx->hist, ctx->histw, (int32_t *)ctx->keys, ctx->pi, ctx->rank, ctx->off,
-                                            ctx->coff, ctx->cursor, ctx->scal));
+    GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
+                                ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, ctx->hist,
+                                ctx->histw, ctx->hist_s, ctx->hist_sc, (int32_t *)ctx->keys, ctx->pi, ctx->rank,
+                                ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->scal));
     GC_LAUNCHED();
-    int64_t tiles = ((int64_t)n + block * SCATTER_ITEMS - 1) / (block * SCATTER_ITEMS);
-    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, g->row_ptr, g->nnz, deg_wave, ctx->ccap,
-                                                ctx->rank, ctx->cursor, ctx->list, ctx->rows, ctx->scal));
+    const int64_t tiles = ((int64_t)n + block * SCATTER_ITEMS - 1) / (block * SCATTER_ITEMS);
+    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, g->row_ptr, g->nnz,
+                                                                         deg_wave, deg_split, ctx->ccap, ctx->rank,
+                                                                         ctx->cursor, ctx->list, ctx->rows, ctx->scal));
     GC_LAUNCHED();
+    if (deg_split > 0) {
+        GC_TIMED(GC_K_SCATTER, s, k_split_prefix<<<4, 256, 0, s>>>(ctx->off, ctx->rows, split_len, ctx->hsub, ctx->scal));
+        GC_LAUNCHED();
+    }
     if (ctx->tune.walk_mode == 0) {
-        status = launch_walk_flow(ctx, g, colors_out, s);
+        status = launch_walk_flow(ctx, g, colors_out, full, s);
         if (status) return status;
     } else {
         status = gc_sync_scalars(ctx, s);
@@ -543,8 +822,9 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         if (ctx->hscal[S_ERR] & 1) return gc_fail(ctx, GC_ERR_COLORING, "input color outside [1, %d]", ctx->ccap);
         const int32_t k = (int32_t)ctx->hscal[S_K];
         for (int32_t r = 0; r < k; r++) {
-            GC_TIMED(GC_K_WALK, s, k_walk_class<<<gc_grid(ctx, n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors_out, ctx->list,
-                                                                  ctx->off, r));
+            GC_TIMED(GC_K_WALK, s, k_walk_class<<<gc_grid(ctx, n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
+                                                                                      n, colors_out, ctx->list,
+                                                                                      ctx->off, r));
             GC_LAUNCHED();
         }
     }
@@ -554,7 +834,8 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         status = gc_sync_scalars(ctx, s);
         if (status) return status;
         if (ctx->hscal[S_ERR] & 1) return gc_fail(ctx, GC_ERR_COLORING, "input color outside [1, %d]", ctx->ccap);
-        if (ctx->hscal[S_ERR] & 4) return gc_fail(ctx, GC_ERR_DEVICE, "class walk: workgroups were not all resident (grid %d)", ctx->walk_blocks);
+        if (ctx->hscal[S_ERR] & 4)
+            return gc_fail(ctx, GC_ERR_DEVICE, "class walk: workgroups were not all resident (grid %d)", ctx->walk_blocks);
         if (ctx->hscal[S_ERR] & 2) return gc_fail(ctx, GC_ERR_DEVICE, "class walk: a dependency wait ran out");
         st->rounds = 0;
         st->losers_total = 0;

@@ -34,6 +34,7 @@ GRAPHS = {
     "rmat": lambda: gen.rmat(12, 16, seed=5),
     "rgg": lambda: gen.rgg(2500, 0.05, 7),
     "complete": lambda: gen.complete(40),
+    "complete100": lambda: gen.complete(100),
     "star": lambda: gen.star(700),
     "crown": lambda: gen.crown(30),
     "path": lambda: gen.path(1000),
@@ -182,10 +183,12 @@ TUNINGS = [
     dict(walk_mode=1), dict(walk_mode=1, deg_wave=3),
     dict(xcd_chunks=1), dict(xcd_chunks=1, group=4, deg_wave=16),
     dict(block=64, grid_per_cu=1), dict(block=1024, grid_per_cu=2),
+    dict(deg_split=0), dict(deg_wave=4, deg_split=16, split_len=64),
+    dict(deg_wave=8, deg_split=64, split_len=64, group=8, xcd_chunks=1),
 ]
 
 
-@pytest.mark.parametrize("name", ["rmat", "mesh", "star", "complete"])
+@pytest.mark.parametrize("name", ["rmat", "mesh", "star", "complete", "complete100"])
 def test_tuning_invariance(gc, name):
     """No tuning knob changes any color (integer work: bit-exact)."""
     g = GRAPHS[name]()
@@ -221,3 +224,47 @@ def test_recolor_without_stats_matches(gc):
         exp = oracle.recolor(g, exp, oracle.PERM_RANDOM, 2, p).colors
     torch.cuda.synchronize()
     assert np.array_equal(c.cpu().numpy(), exp)
+
+
+MANY_CLASS_TUNINGS = [
+    dict(),                                         # rows in the wavefront bin, LDS mask words
+    dict(group=1, deg_wave=512),                    # one lane per row: 64-color windows beyond the LDS word
+    dict(group=4, deg_wave=512),
+    dict(deg_wave=16, deg_split=128, split_len=64),  # split rows, multi-word hub bitmaps
+    dict(walk_mode=1),
+]
+
+
+@pytest.mark.parametrize("t", MANY_CLASS_TUNINGS, ids=str)
+def test_recolor_many_classes(gc, t):
+    """K_300 from a random proper coloring (300 classes, every rank >= 64 needs
+    colors above the first 64): all walk paths against the oracle."""
+    g = gen.complete(300)
+    rp, col = dev(g)
+    rng = np.random.default_rng(11)
+    c0 = (rng.permutation(300) + 1).astype(np.int32)
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(**t)
+    exp = c0
+    cur = torch.from_numpy(c0.copy()).cuda()
+    for p, perm in enumerate((gc.PERM_REVERSE, gc.PERM_RANDOM, gc.PERM_NONINC, gc.PERM_RANDOM)):
+        cur, st = gc.recolor(rp, col, cur, perm, 5, p, out=cur, ctx=ctx)
+        exp = oracle.recolor(g, exp, perm, 5, p).colors
+        assert np.array_equal(cur.cpu().numpy(), exp), (t, p)
+        assert st["num_colors"] == 300
+    ctx.close()
+
+
+def test_recolor_beyond_hub_ranks(gc):
+    """K_4200 colored 1..4200: rows longer than the split threshold at ranks
+    below 4096 take the split path, those above the wavefront bin."""
+    g = gen.complete(4200)
+    rp, col = dev(g)
+    c0 = np.arange(1, 4201, dtype=np.int32)
+    cur = torch.from_numpy(c0.copy()).cuda()
+    exp = c0
+    for p, perm in enumerate((gc.PERM_RANDOM, gc.PERM_NONINC)):
+        print(f"[K_4200] pass {p}", flush=True)
+        cur, st = gc.recolor(rp, col, cur, perm, 3, p, out=cur)
+        exp = oracle.recolor(g, exp, perm, 3, p).colors
+        assert np.array_equal(cur.cpu().numpy(), exp), p
