@@ -11,7 +11,13 @@ Metric (GTEPS/pass): undirected edges m = nnz / 2 times the passes of a step
 (the initial coloring counts as one pass) per second of the whole step.
 Printed as ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--workload mesh128|er10k|rmat22]
+    python bench.py [--steps K] [--warmup W] [--workload mesh128|er10k|rmat22|batch4096]
+
+The batch4096 workload colors 4,096 random geometric graphs (n uniform in
+[500, 50000], target degree uniform in [8, 40]) packed into one CSR, each with
+Random-X (X=4) + 5 reverse-order recoloring passes, in one persistent launch,
+and compares graphs/s with plain per-graph calls of the same library on the
+same GPU (same seeds, colorings checked identical).
 """
 from __future__ import annotations
 
@@ -20,6 +26,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -66,12 +74,124 @@ def cpu_baseline(g, select, X, perm, passes, seed, budget_s=12.0):
             "seconds": round(el, 3)}, c
 
 
+def batch_cpu_baseline(b, X, passes, seed, budget_s=12.0):
+    """The oracle (single thread, as it stands) on the first graphs of the batch, whole method per graph."""
+    import oracle
+    import paper_1407_6745_amd as gc
+
+    t0 = time.perf_counter()
+    done = 0
+    edges = 0
+    while done < b.num_graphs and time.perf_counter() - t0 < budget_s:
+        g = b.graph(done)
+        sg = gc.batch_graph_seed(seed, done)
+        c = oracle.init_color(g, oracle.RANDOM_X, X, sg).colors
+        for p in range(passes):
+            c = oracle.recolor(g, c, oracle.PERM_REVERSE, sg, p).colors
+        edges += g.m
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": round(done / el, 3), "unit": "graphs/s", "cores": 1, "kind": "oracle",
+            "sample": f"graphs 0..{done - 1} of the batch ({edges} undirected edges), whole method each, one thread",
+            "gteps": round(edges * (passes + 1) / el / 1e9, 4), "seconds": round(el, 3)}
+
+
+def run_batch(args):
+    import torch
+
+    import gen
+    import paper_1407_6745_amd as gc
+
+    X, passes, G = 4, 5, args.graphs
+    t0 = time.perf_counter()
+    b = gen.rgg_batch(G, args.seed)
+    n_tot, nnz_tot = int(b.vtx_off[-1]), int(b.edge_off[-1])
+    log(f"[bench] batch of {G} RGGs: n={n_tot} nnz={nnz_tot} ({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    vo = torch.from_numpy(b.vtx_off).to(dev)
+    eo = torch.from_numpy(b.edge_off).to(dev)
+    rp = torch.from_numpy(b.row_ptr).to(dev)
+    col = torch.from_numpy(b.col).to(dev)
+    ns = np.diff(b.vtx_off)
+    max_n = int(ns.max())
+    max_nnz = int(np.diff(b.edge_off).max())
+    ctx = gc.Context(max_n, max_nnz)
+    if args.tune:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tune.split(","))})
+    colors = torch.empty(n_tot, dtype=torch.int32, device=dev)
+    per = torch.empty((G, 4), dtype=torch.int32, device=dev)
+
+    def batched():
+        gc.batch_color(vo, eo, rp, col, gc.RANDOM_X, X, gc.PERM_REVERSE, passes, args.seed,
+                       max_vertices_per_graph=max_n, out=colors, per_graph=per, ctx=ctx)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+    pg = per.cpu().numpy()
+    log(f"[bench] batched: {t_b * 1e3:.1f} ms per launch, {G / t_b:.0f} graphs/s")
+
+    # plain: the single-graph library calls, graph after graph on the same stream
+    plain = torch.zeros(n_tot, dtype=torch.int32, device=dev)
+    seeds = [gc.batch_graph_seed(args.seed, g) for g in range(G)]
+    views = []
+    for g in range(G):
+        a, z = int(b.vtx_off[g]), int(b.vtx_off[g + 1])
+        e0, e1 = int(b.edge_off[g]), int(b.edge_off[g + 1])
+        views.append((rp[a + g:z + g + 1], col[e0:e1], plain[a:z]))
+
+    def plain_all():
+        for g in range(G):
+            grp, gcol, out = views[g]
+            gc.init_color(grp, gcol, gc.RANDOM_X, X, seeds[g], out=out, stats=False, ctx=ctx)
+            for p in range(passes):
+                gc.recolor(grp, gcol, out, gc.PERM_REVERSE, seeds[g], p, out=out, stats=False, ctx=ctx)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_all()
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    identical = bool(torch.equal(plain, colors))
+    log(f"[bench] plain: {t_p:.2f} s, {G / t_p:.0f} graphs/s; identical={identical}")
+    m_tot = nnz_tot // 2
+    out = {
+        "metric": "graphs/s (batched)", "value": round(G / t_b, 2), "unit": "graphs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{G} random geometric graphs, n uniform in [500, 50000], target degree uniform in "
+                               f"[8, 40], Random-X (X=4) + {passes} reverse-order recoloring passes each",
+                   "graphs": G, "n": n_tot, "nnz": nnz_tot, "m": m_tot, "seed": args.seed, "tuning": ctx.tuning},
+        "gteps_batched": round(m_tot * (passes + 1) / t_b / 1e9, 3),
+        "plain": {"graphs_per_s": round(G / t_p, 2), "seconds": round(t_p, 3),
+                  "gteps": round(m_tot * (passes + 1) / t_p / 1e9, 3)},
+        "speedup_vs_plain": round(t_p / t_b, 2),
+        "identical_to_plain": identical,
+        "all_converged": bool((pg[:, 3] == 0).all()),
+        "colors_final": {"min": int(pg[:, 2].min()), "mean": round(float(pg[:, 2].mean()), 3),
+                         "max": int(pg[:, 2].max())},
+        "rounds": {"mean": round(float(pg[:, 0].mean()), 3), "max": int(pg[:, 0].max())},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = batch_cpu_baseline(b, X, passes, args.seed)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mesh128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mesh128", choices=sorted(WORKLOADS) + ["batch4096"])
+    ap.add_argument("--graphs", type=int, default=4096, help="batch4096: number of graphs")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="comma list key=value of library tuning knobs")
@@ -92,6 +212,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the coloring of one graph here is a "
               "single-GPU kernel pipeline; sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch4096":
+        return run_batch(args)
 
     import torch
 
