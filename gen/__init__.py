@@ -332,3 +332,54 @@ def mesh27_nnz(N: int) -> int:
 
 def log_uniform(rng: np.random.Generator, lo: float, hi: float) -> float:
     return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+# ---- serving workload: a pool of request graphs and a Poisson arrival trace ----
+
+SERVE_FAMILIES = ("grid5", "er", "rmat")
+
+
+def serve_graph_spec(rng: np.random.Generator, small: bool = False) -> tuple:
+    """One request graph, family uniform over 2D 5-point grids (side
+    log-uniform in [32, 2048]), Erdos-Renyi G(n, m) (n log-uniform in
+    [10^3, 10^6], average degree uniform in [4, 32]) and RMAT (scale uniform in
+    10..20, edge factor 16, Graph500 a, b, c).  small: the same families at
+    test sizes (side 16..96, n 500..20000, scale 6..12)."""
+    fam = SERVE_FAMILIES[int(rng.integers(0, 3))]
+    seed = int(rng.integers(1, 2**31))
+    if fam == "grid5":
+        side = int(round(log_uniform(rng, 16, 96) if small else log_uniform(rng, 32, 2048)))
+        return ("grid5", side)
+    if fam == "er":
+        n = int(round(log_uniform(rng, 500, 20000) if small else log_uniform(rng, 1e3, 1e6)))
+        d = float(rng.uniform(4, 32))
+        m = min(int(n * d / 2), n * (n - 1) // 2)
+        return ("er", n, m, seed)
+    scale = int(rng.integers(6, 13) if small else rng.integers(10, 21))
+    return ("rmat", scale, seed)
+
+
+def serve_graph(spec: tuple) -> CSR:
+    if spec[0] == "grid5":
+        return grid5(spec[1], spec[1])
+    if spec[0] == "er":
+        return er(spec[1], spec[2], spec[3])
+    return rmat(spec[1], 16, 0.57, 0.19, 0.19, spec[2])
+
+
+def serve_pool(count: int, seed: int = 1, small: bool = False) -> list:
+    """`count` request graphs (specs drawn from one seeded stream)."""
+    rng = np.random.default_rng(seed)
+    specs = [serve_graph_spec(rng, small) for _ in range(count)]
+    return [serve_graph(s) for s in specs]
+
+
+def serve_trace(count: int, pool_size: int, rate: float, seed: int = 1):
+    """Arrival times (seconds, Poisson process of `rate` per second), the pool
+    graph of each request and its coloring seed."""
+    rng = np.random.default_rng(seed + 7919)
+    gaps = rng.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
+    t = np.cumsum(gaps) - (gaps[0] if count else 0.0)
+    which = rng.integers(0, pool_size, count)
+    seeds = rng.integers(1, 2**62, count, dtype=np.int64)
+    return t, which, seeds

@@ -101,18 +101,21 @@ typedef struct gc_stats {
 typedef struct gc_tuning {
     int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
     int32_t deg_wave;      /* recoloring: rows with degree > deg_wave get a whole wavefront per vertex */
-    int32_t group;         /* recoloring: lanes per vertex for the other rows (power of two, 1..64) */
+    int32_t group;         /* lanes per vertex for the other rows (power of two, 1..64) */
     int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
     int32_t walk_mode;     /* recoloring class walk: 0 = one persistent launch, waits per dependency;
                               1 = one launch per class (host reads the class count) */
     int32_t xcd_chunks;    /* persistent walk: consecutive work chunks kept on one XCD (0 = round robin) */
     int32_t check_resident;/* persistent walk: verify at start that every workgroup is resident (diagnostic;
                               a failed check makes the call return GC_ERR_DEVICE when it synchronizes) */
-    int32_t deg_split;     /* recoloring: rows longer than both deg_wave and deg_split (0 = never) are
-                              scanned by several wavefronts at once, split_len entries each (graphs whose
-                              longest row is under 64 use a walk without this path) */
+    int32_t deg_split;     /* rows longer than both deg_wave and deg_split (0 = never) are scanned by
+                              several wavefronts at once, split_len entries each, in the initial coloring's
+                              rounds and in the recoloring walk (graphs whose longest row is under 64 use a
+                              walk without this path) */
     int32_t split_len;     /* entries per wavefront for split rows (>= 64) */
-    int32_t reserved;
+    int32_t hub_words;     /* 64-bit mask words per split row (1..64): colors up to 64 * hub_words are merged
+                              across wavefronts; larger colors rescan the row, and recoloring ranks of
+                              64 * hub_words and above keep their long rows on one wavefront */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);

@@ -44,10 +44,10 @@ class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("deg_wave", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("walk_mode", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
                 ("check_resident", ctypes.c_int32), ("deg_split", ctypes.c_int32), ("split_len", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("hub_words", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
-                 "split_len")
+                 "split_len", "hub_words")
 
 
 class BatchArgs(ctypes.Structure):
@@ -85,6 +85,14 @@ _SIGS = {
     "gc_ctx_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
     "gc_ctx_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
+    # request server (include/gc_serve.h)
+    "gc_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "gc_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gc_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "gc_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gc_server_now": (ctypes.c_double, [ctypes.c_void_p]),
+    "gc_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 KERNEL_KINDS = ("round0", "assign", "detect", "hist", "order", "scatter", "walk", "count", "batch", "other")
@@ -364,3 +372,106 @@ def color(row_ptr, col_idx, select=RANDOM_X, X=4, seed=1, perms=(PERM_REVERSE,),
         c, sp = recolor(row_ptr, col_idx, c, perm, seed, p, out=c, ctx=ctx, stream=stream, stats=stats)
         hist.append(sp)
     return c, hist
+
+
+# ---------------------------------------------------------------------------
+# request server (continuous batching of independent graphs on one GPU)
+# ---------------------------------------------------------------------------
+
+class ServerConfigArgs(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
+                ("max_n", ctypes.c_int64), ("max_nnz", ctypes.c_int64)]
+
+
+class RequestArgs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("colors", ctypes.c_void_p),
+                ("select", ctypes.c_int32), ("X", ctypes.c_int32), ("perm", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("tag", ctypes.c_uint64)]
+
+
+class RequestDoneArgs(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("colors_init", ctypes.c_int32), ("colors_final", ctypes.c_int32),
+                ("running_at_admit", ctypes.c_int32), ("footprint", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
+class ServerStatsArgs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "waiting", "running", "peak_running",
+                                              "arena_size", "arena_used", "arena_peak")]
+
+
+def request_footprint(n: int, nnz: int) -> int:
+    """Arena bytes a request holds: row_ptr, col_idx and colors, each rounded up to 256 bytes."""
+    a = lambda x: (x + 255) // 256 * 256
+    return a(4 * (n + 1)) + a(4 * nnz) + a(4 * n)
+
+
+class Server:
+    """Continuous-batching request server of libgc (gc_serve.h).  Requests are
+    host CSR graphs (numpy int32); results come back as host color arrays."""
+
+    def __init__(self, slots=4, hbm_budget=16 << 30, max_n=1 << 22, max_nnz=1 << 26, device=0):
+        cfg = ServerConfigArgs(device, slots, hbm_budget, max_n, max_nnz)
+        h = ctypes.c_void_p()
+        rc = lib().gc_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc:
+            raise GCError(rc, f"gc_server_create: {status_string(rc)}")
+        self.handle = h
+        self._live = {}
+        self._lock = threading.Lock()
+        self._next = 0
+
+    def submit(self, row_ptr, col, select=RANDOM_X, X=4, perm=PERM_REVERSE, passes=3, seed=1, tag=None) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        n = rp.shape[0] - 1
+        out = np.zeros(max(n, 0), np.int32)
+        with self._lock:
+            if tag is None:
+                tag = self._next
+            self._next = max(self._next, tag + 1)
+            self._live[tag] = (rp, cl, out)
+        r = RequestArgs(n, 0, cl.shape[0], rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                        out.ctypes.data if n else None, select, X if select == RANDOM_X else 1, perm, passes,
+                        seed, tag)
+        rc = lib().gc_server_submit(self.handle, ctypes.byref(r))
+        if rc:
+            with self._lock:
+                self._live.pop(tag, None)
+            raise GCError(rc, f"gc_server_submit: {status_string(rc)}")
+        return tag
+
+    def poll(self, timeout_ms=-1, cap=256) -> list:
+        buf = (RequestDoneArgs * cap)()
+        cnt = ctypes.c_int32()
+        rc = lib().gc_server_poll(self.handle, buf, cap, ctypes.byref(cnt), timeout_ms)
+        if rc:
+            raise GCError(rc, f"gc_server_poll: {status_string(rc)}")
+        res = []
+        for i in range(cnt.value):
+            d = {k: getattr(buf[i], k) for k, _ in RequestDoneArgs._fields_}
+            with self._lock:
+                d["colors"] = self._live.pop(d["tag"])[2]
+            res.append(d)
+        return res
+
+    def stats(self) -> dict:
+        st = ServerStatsArgs()
+        lib().gc_server_get_stats(self.handle, ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in ServerStatsArgs._fields_}
+
+    def now(self) -> float:
+        return lib().gc_server_now(self.handle)
+
+    def close(self):
+        if self.handle:
+            lib().gc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -52,7 +52,7 @@ gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
 static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
-                    c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt};
+                    c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -76,6 +76,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.xcd_chunks = 0;
     ctx->tune.deg_split = 4096;
     ctx->tune.split_len = 1024;
+    ctx->tune.hub_words = GC_HUB_WORDS;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -229,6 +230,8 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->check_resident < 0 || t->check_resident > 1) return gc_fail(ctx, GC_ERR_ARG, "check_resident must be 0 or 1");
     if (t->deg_split < 0) return gc_fail(ctx, GC_ERR_ARG, "deg_split must be >= 0");
     if (t->split_len < 64) return gc_fail(ctx, GC_ERR_ARG, "split_len must be >= 64");
+    if (t->hub_words < 1 || t->hub_words > GC_HUB_WORDS)
+        return gc_fail(ctx, GC_ERR_ARG, "hub_words must be in [1, %d]", GC_HUB_WORDS);
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
     ctx->tune = *t;
     return GC_OK;
@@ -514,4 +517,24 @@ extern "C" gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream) {
 
 extern "C" uint64_t gc_batch_graph_seed(uint64_t base_seed, int32_t g) {
     return gc_mix64(base_seed + GC_GOLDEN * (((uint64_t)GC_TAG_GRAPH << 32) | (uint32_t)g));
+}
+
+gc_status gc_ensure_hub_slots(gc_ctx *ctx, int64_t nnz, int32_t deg_split, hipStream_t s) {
+    const int64_t need = nnz / ((int64_t)deg_split + 1) + 1;
+    if (need <= ctx->hub_cap) return GC_OK;
+    GC_HIP(hipStreamSynchronize(s));
+    void **bufs[4] = {(void **)&ctx->hub_bits, (void **)&ctx->hub_cnt, (void **)&ctx->hub_v, (void **)&ctx->hub_first};
+    for (void **b : bufs)
+        if (*b) { GC_HIP(hipFree(*b)); *b = nullptr; }
+    ctx->hub_cap = 0;
+    const int64_t cap = need + 64;
+    if (hipMalloc((void **)&ctx->hub_bits, (size_t)cap * GC_HUB_WORDS * 8) != hipSuccess ||
+        hipMalloc((void **)&ctx->hub_cnt, (size_t)cap * 4) != hipSuccess ||
+        hipMalloc((void **)&ctx->hub_v, (size_t)cap * 4) != hipSuccess ||
+        hipMalloc((void **)&ctx->hub_first, (size_t)cap * 4) != hipSuccess)
+        return gc_fail(ctx, GC_ERR_OOM, "hub slots (%lld)", (long long)cap);
+    GC_HIP(hipMemsetAsync(ctx->hub_bits, 0, (size_t)cap * GC_HUB_WORDS * 8, s));
+    GC_HIP(hipMemsetAsync(ctx->hub_cnt, 0, (size_t)cap * 4, s));
+    ctx->hub_cap = cap;
+    return GC_OK;
 }

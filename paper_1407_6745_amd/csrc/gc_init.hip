@@ -20,9 +20,13 @@
 // (one global atomic per flush).
 #include "gc_internal.h"
 
+#include <climits>
+#include <cstdint>
 #include <vector>
 
 #define INIT_BLOCK 256
+// loads in flight per lane: whole-wavefront rows are long, so they keep more
+#define ROW_UNROLL(G) ((G) >= 32 ? 16 : GC_UNROLL)
 
 // Tentative color of w in round 0: 1 + its Random-X offset (no color is held yet).
 __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, bool randx) {
@@ -32,22 +36,22 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
-template <int G, bool ROUND0>
+template <int G, bool ROUND0, int UNR = GC_UNROLL>
 __device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
                                    const int32_t *C, int32_t n, uint32_t s_prio, uint32_t s_color, uint32_t X,
                                    bool randx) {
     const int l = __lane_id() & (G - 1);
     bool lose = false;
-    for (int32_t eb = e0 + l; eb < e1; eb += G * GC_UNROLL) {
-        int32_t w[GC_UNROLL], t[GC_UNROLL];
+    for (int32_t eb = e0 + l; eb < e1; eb += G * UNR) {
+        int32_t w[UNR], t[UNR];
 #pragma unroll
-        for (int u = 0; u < GC_UNROLL; u++) {
+        for (int u = 0; u < UNR; u++) {
             const int32_t e = eb + u * G;
             const int32_t wl = col[e < e1 ? e : eb];
             w[u] = e < e1 ? wl : -1;
         }
 #pragma unroll
-        for (int u = 0; u < GC_UNROLL; u++) {
+        for (int u = 0; u < UNR; u++) {
             const bool ok = (uint32_t)w[u] < (uint32_t)n;
             if (ROUND0) {
                 t[u] = ok ? round0_color(s_color, w[u], X, randx) : 0;
@@ -57,7 +61,7 @@ __device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t 
             }
         }
 #pragma unroll
-        for (int u = 0; u < GC_UNROLL; u++)
+        for (int u = 0; u < UNR; u++)
             if (t[u] == tv && gc_prio(s_prio, w[u]) > pv) lose = true;
     }
     return group_any<G>(lose);
@@ -84,12 +88,13 @@ __device__ inline void queues_flush(InitQueues &q, int32_t *wl_lo, unsigned long
 
 // Round 0, by vertex id (in_list == NULL) or over a list of long rows.  By
 // vertex id, rows longer than deg_wave are not processed but appended to the
-// second queue (they get their own launch, one wavefront each).  Writes
+// second queue (they get their own launch, one wavefront each); over a list,
+// rows longer than skip_len are left to the split kernels.  Writes
 // C[v] = +T (kept) or -T (lost) and appends losers by bin.
 template <int G>
 __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        int64_t nnz, int32_t n, int32_t *C, int32_t deg_wave,
-                                                       const int32_t *__restrict__ in_list,
+                                                       int32_t skip_len, const int32_t *__restrict__ in_list,
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, uint32_t s_prio, uint32_t s_color,
@@ -107,12 +112,13 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
             v = in_list ? in_list[i] : (int32_t)i;
             row_range(rp, v, nnz, e0, e1);
             if (!in_list && e1 - e0 > deg_wave) forward = true;
+            if (in_list && e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }  // split rows: their own kernels
         }
         const bool hub = e1 - e0 > deg_wave;
         if (forward) e1 = e0;
         const int32_t tv = v >= 0 ? round0_color(s_color, v, X, randx != 0) : 0;
         const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
-        const bool lose = group_loses<G, true>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0);
+        const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) C[v] = lose ? -tv : tv;
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
@@ -128,8 +134,11 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
                                                        int64_t nnz, int32_t n, int32_t *C,
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
-                                                       uint32_t X, int randx, unsigned long long *degsum) {
+                                                       uint32_t X, int randx, unsigned long long *degsum,
+                                                       int32_t skip_len) {
     __shared__ unsigned long long sdeg;
+    __shared__ unsigned long long lmask[INIT_BLOCK];
+    unsigned long long *lw = lmask + (threadIdx.x & ~63u);
     if (threadIdx.x == 0) sdeg = 0;
     __syncthreads();
     const int64_t cnt = (int64_t)*wcount;
@@ -142,9 +151,10 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
         if (i < cnt) {
             v = wl[i];
             row_range(rp, v, nnz, e0, e1);
+            if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
         }
         const uint32_t j = (v >= 0 && randx) ? gc_pick(s_color, v, X) : 0u;
-        const int32_t t = group_select<G>(col, e0, e1, C, n, j);
+        const int32_t t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, C, n, j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
             degs += (unsigned long long)(e1 - e0);
@@ -165,7 +175,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
-                                                       unsigned long long *c_hub, uint32_t s_prio) {
+                                                       unsigned long long *c_hub, uint32_t s_prio, int32_t skip_len) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -177,10 +187,11 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         if (i < cnt) {
             v = wl[i];
             row_range(rp, v, nnz, e0, e1);
-            t = -C[v];
+            if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
+            else t = -C[v];
         }
         const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
-        const bool lose = group_loses<G, false>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false);
+        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) C[v] = t;
         const bool hub = e1 - e0 > deg_wave;
@@ -192,29 +203,211 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// long rows (longer than deg_wave and deg_split): split_len-entry chunks,
+// one wavefront each, several wavefronts per row.  A per-round plan lists
+// the long rows of a worklist (hub slot = position in the plan) and the first
+// chunk of each.  Partial results meet in the row's hub slot (mask words for
+// the assign step, a lose flag for the detect step); the chunk that finishes
+// last completes the row and clears the slot.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__ rp, int64_t nnz,
+                                                     const int32_t *__restrict__ in_list,
+                                                     const unsigned long long *__restrict__ in_count, int32_t thresh,
+                                                     int32_t split_len, int32_t *__restrict__ hub_v,
+                                                     int32_t *__restrict__ hub_first, unsigned long long *plan) {
+    __shared__ int32_t lds[32];
+    const int64_t cnt = (int64_t)*in_count;
+    int32_t nrow = 0, nch = 0;
+    for (int64_t base = 0; base < cnt; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        int32_t v = -1, len = 0;
+        if (i < cnt) {
+            v = in_list[i];
+            int32_t e0, e1;
+            row_range(rp, v, nnz, e0, e1);
+            len = e1 - e0;
+        }
+        const bool lg = v >= 0 && len > thresh;
+        int32_t tr, tc;
+        const int32_t er = block_exclusive_scan(lg ? 1 : 0, &tr, lds);
+        const int32_t ec = block_exclusive_scan(lg ? (len + split_len - 1) / split_len : 0, &tc, lds);
+        if (lg) {
+            hub_v[nrow + er] = v;
+            hub_first[nrow + er] = nch + ec;
+        }
+        nrow += tr;
+        nch += tc;
+    }
+    if (threadIdx.x == 0) {
+        plan[0] = (unsigned long long)nrow;
+        plan[1] = (unsigned long long)nch;
+    }
+}
+
+// Chunk c of the plan: its row's slot, vertex, row range and chunk range.
+
+struct SplitChunk {
+    int32_t slot, v, e0, e1, a, b, nsub;
+};
+
+__device__ inline SplitChunk split_chunk(int32_t c, int32_t nrow, const int32_t *__restrict__ hub_v,
+                                         const int32_t *__restrict__ hub_first, const int32_t *__restrict__ rp,
+                                         int64_t nnz, int32_t split_len) {
+    int32_t lo = 0, hi = nrow - 1;  // last slot whose first chunk is <= c
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (hub_first[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    SplitChunk k;
+    k.slot = lo;
+    k.v = hub_v[lo];
+    row_range(rp, k.v, nnz, k.e0, k.e1);
+    k.nsub = (k.e1 - k.e0 + split_len - 1) / split_len;
+    k.a = k.e0 + (c - hub_first[lo]) * split_len;
+    k.b = min(k.e1, k.a + split_len);
+    return k;
+}
+
+// Counts a finished chunk of slot; true (wavefront-uniform) for the last one.
+__device__ inline bool split_last(int32_t *hub_cnt, int32_t slot, int32_t nsub) {
+    __threadfence();
+    int32_t done = 0;
+    if (__lane_id() == 0) done = atomicAdd(&hub_cnt[slot], 1) + 1;
+    done = __shfl(done, 0);
+    if (done != nsub) return false;
+    __threadfence();
+    return true;
+}
+
+// Assign step for long rows (rounds >= 1): committed neighbor colors 1..64
+// in a register word, 65 .. 64 * hub_words in the wavefront's LDS words,
+// merged into the row's hub words; the last chunk takes the (j+1)-th free
+// color (past color 64 * hub_words it rescans the row).
+__global__ void __launch_bounds__(INIT_BLOCK) k_split_assign(const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                                                             int32_t *C, const int32_t *__restrict__ hub_v,
+                                                             const int32_t *__restrict__ hub_first,
+                                                             const unsigned long long *__restrict__ plan,
+                                                             int32_t split_len, int32_t hub_words, uint32_t s_color,
+                                                             uint32_t X, int randx, unsigned long long *hub_bits,
+                                                             int32_t *hub_cnt, unsigned long long *degsum) {
+    __shared__ unsigned long long lmask[INIT_BLOCK];
+    const int lane = __lane_id();
+    unsigned long long *lw = lmask + (threadIdx.x & ~63u);
+    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int wpb = INIT_BLOCK / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
+        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        unsigned long long *bits = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
+        lw[lane] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint64_t m = 0;
+        for (int32_t eb = k.a + lane; __ballot(eb < k.b); eb += 64 * ROW_UNROLL(64)) {
+            int32_t w[ROW_UNROLL(64)], x[ROW_UNROLL(64)];
+#pragma unroll
+            for (int u = 0; u < ROW_UNROLL(64); u++) {
+                const int32_t e = eb + u * 64;
+                const int32_t wl = col[e < k.b ? e : k.a];
+                w[u] = e < k.b ? wl : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < ROW_UNROLL(64); u++) {
+                const bool ok = (uint32_t)w[u] < (uint32_t)n;
+                const int32_t cl = C[ok ? w[u] : 0];
+                x[u] = ok ? cl : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < ROW_UNROLL(64); u++) mask_mark<true>(x[u], 0u, m, lw, 0, hub_words - 1);
+        }
+        m = group_or_rt(m, 64);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t lword = lane >= 1 ? lw[lane - 1] : 0ull;
+        const uint64_t mine = lane == 0 ? m : lword;
+        if (lane < hub_words && mine) atomicOr(&bits[lane], mine);
+        if (split_last(hub_cnt, k.slot, k.nsub)) {
+            const uint64_t word = lane < hub_words ? atomicOr(&bits[lane], 0ull) : ~0ull;
+            const uint32_t j = randx ? gc_pick(s_color, k.v, X) : 0u;
+            uint32_t t = wave_nth_free(word, j);
+            if (t == 0) t = (uint32_t)group_select<64>(col, k.e0, k.e1, C, n, j);  // beyond color 64 * hub_words
+            if (lane < hub_words) atomicExch(&bits[lane], 0ull);
+            if (lane == 0) {
+                atomicExch(&hub_cnt[k.slot], 0);
+                C[k.v] = -(int32_t)t;
+                atomicAdd(degsum, (unsigned long long)(k.e1 - k.e0));
+            }
+        }
+    }
+}
+
+// Detect step for long rows: a chunk that finds a neighbor with the same
+// tentative color and a larger priority raises the row's lose flag (hub word
+// 0); the last chunk commits the row or appends it to the long-row worklist.
+// ROUND0: tentative colors come from the hash and the row's own word is
+// written here (+T kept, -T lost).
+template <bool ROUND0>
+__global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                                                             int32_t *C, const int32_t *__restrict__ hub_v,
+                                                             const int32_t *__restrict__ hub_first,
+                                                             const unsigned long long *__restrict__ plan,
+                                                             int32_t split_len, uint32_t s_prio, uint32_t s_color,
+                                                             uint32_t X, int randx, unsigned long long *hub_bits,
+                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub) {
+    const int lane = __lane_id();
+    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int wpb = INIT_BLOCK / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
+        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        unsigned long long *flag = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
+        const int32_t t = ROUND0 ? round0_color(s_color, k.v, X, randx != 0) : -C[k.v];
+        const uint32_t pv = gc_prio(s_prio, k.v);
+        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, s_prio, s_color, X, randx != 0);
+        if (lose && lane == 0) atomicOr(flag, 1ull);
+        if (split_last(hub_cnt, k.slot, k.nsub)) {
+            if (lane == 0) {
+                const bool lost = atomicExch(flag, 0ull) != 0ull;
+                atomicExch(&hub_cnt[k.slot], 0);
+                if (ROUND0) C[k.v] = lost ? -t : t;
+                else if (!lost) C[k.v] = t;
+                if (lost) wl_hub[atomicAdd(c_hub, 1ull)] = k.v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
 template <int G>
-static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *in_list,
+static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, int32_t skip_len,
+                          const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
                           int32_t *wl_hub, unsigned long long *c_hub, uint32_t sp, uint32_t sc, uint32_t X, int randx) {
-    k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, in_list, in_count, wl_lo,
+    k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, skip_len, in_list, in_count, wl_lo,
                                             c_lo, wl_hub, c_hub, sp, sc, X, randx);
 }
 
 template <int G>
 static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
-                          const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum) {
-    k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum);
+                          const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
+                          int32_t skip_len) {
+    k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum,
+                                            skip_len);
 }
 
 template <int G>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                          unsigned long long *c_hub, uint32_t sp) {
+                          unsigned long long *c_hub, uint32_t sp, int32_t skip_len) {
     k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, sp);
+                                            c_hub, sp, skip_len);
 }
 
 #define GC_DISPATCH_G(G, CALL)                           \
@@ -265,14 +458,37 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     sizes.push_back(n);
     degsum.push_back(g->nnz);
     GC_HIP(hipMemsetAsync(cnt, 0, 5 * 8, s));
+    // Long rows (longer than deg_wave and deg_split) go to the split kernels;
+    // the others skip them.
+    const bool split = ctx->tune.deg_split > 0;
+    const int32_t thresh = deg_wave > ctx->tune.deg_split ? deg_wave : ctx->tune.deg_split;
+    const int32_t skip = split ? thresh : INT32_MAX;
+    const int32_t split_len = ctx->tune.split_len;
+    if (split) {
+        status = gc_ensure_hub_slots(ctx, g->nnz, ctx->tune.deg_split, s);
+        if (status) return status;
+    }
+    unsigned long long *plan = ctx->scal + S_PLAN;
+    auto split_plan = [&](const int32_t *list, const unsigned long long *count) {
+        k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan);
+    };
     const uint32_t sp0 = prio_stream(0), sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
-    GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, nullptr, nullptr,
-                                                                ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0, sc0,
-                                                                (uint32_t)X, randx)));
+    GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
+                                                                nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
+                                                                sc0, (uint32_t)X, randx)));
     GC_LAUNCHED();
-    GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
+    GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
                                                ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx));
     GC_LAUNCHED();
+    if (split) {
+        GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3));
+        GC_LAUNCHED();
+        GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
+                                     g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
+                                     split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
+                                     cnt + 1));
+        GC_LAUNCHED();
+    }
     int32_t r = 1, cur = 0;
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
@@ -292,25 +508,43 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
         GC_HIP(hipMemsetAsync(c_lo_out, 0, 2 * 8, s));
         GC_HIP(hipMemsetAsync(cnt + 4, 0, 8, s));
         const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r), sp = prio_stream(r);
+        const bool split_round = split && nhub > 0;
+        if (split_round) {
+            GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in));
+            GC_LAUNCHED();
+        }
         if (nlo) {
             GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
-                                                                        sc, (uint32_t)X, randx, cnt + 4)));
+                                                                        sc, (uint32_t)X, randx, cnt + 4, skip)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
-                                                       randx, cnt + 4));
+                                                       randx, cnt + 4, skip));
+            GC_LAUNCHED();
+        }
+        if (split_round) {
+            GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
+                                         split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
+                                         ctx->hub_cnt, cnt + 4));
             GC_LAUNCHED();
         }
         if (nlo) {
             GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
                                                                         c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp)));
+                                                                        sp, skip)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp));
+                                                       c_lo_out, hub_out, c_hub_out, sp, skip));
+            GC_LAUNCHED();
+        }
+        if (split_round) {
+            GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
+                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out));
             GC_LAUNCHED();
         }
         cur = nxt;

@@ -28,6 +28,7 @@ enum {
     S_TICKET = 10,   // work ticket of persistent kernels
     S_DONE = 11,
     S_MAXDEG = 12,   // longest row of the graph
+    S_PLAN = 13,     // split plan of the initial coloring: long rows (13), their chunks (14)
     S_WL = 16,       // initial coloring: 4 worklist counts + the round's degree sum (16..20)
     S_COUNT = 64
 };
@@ -52,6 +53,8 @@ struct gc_ctx {
     int32_t *hsub;           // per list slot of a split row: its first chunk inside the segment (max_n + 64)
     unsigned long long *hub_bits;  // per hub slot: HUB_WORDS color-mask words, zero between calls
     int32_t *hub_cnt;        // per hub slot: finished chunks, zero between calls
+    int32_t *hub_v;          // initial coloring: per hub slot, the long row's vertex
+    int32_t *hub_first;      // initial coloring: per hub slot, its first chunk
     int64_t hub_cap;         // hub slots allocated
     int walk_blocks;         // co-resident workgroups of the persistent walk (0 = not computed)
     int walk_blocks_group;   // walk variant (2 * group + full) the count was computed for
@@ -112,6 +115,11 @@ int gc_grid(const gc_ctx *ctx, int64_t work, int block);
 // Launch helpers shared between files (defined in gc_api.hip).
 gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax);
 gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s);
+// Mask words of one split row (colors 1 .. 64 * GC_HUB_WORDS).
+#define GC_HUB_WORDS 64
+// Hub slots for rows longer than deg_split (at most nnz / (deg_split + 1)
+// rows), zeroed; grown on demand (synchronizes the stream when it grows).
+gc_status gc_ensure_hub_slots(gc_ctx *ctx, int64_t nnz, int32_t deg_split, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // hash: counter-based randomness of the method (written from the published
@@ -461,9 +469,8 @@ __device__ inline void bq_flush(int32_t *lbuf, int32_t *lcnt, int32_t *lbase, in
 // group of G lanes (group-uniform result).  Colors <= 0 are "no color".
 template <int G>
 __device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
-                                       int32_t n, uint32_t j) {
+                                       int32_t n, uint32_t j, uint32_t base = 0) {
     const int l = __lane_id() & (G - 1);
-    uint32_t base = 0;
     for (;;) {
         uint64_t mask = 0;
         for (int32_t eb = e0 + l; eb < e1; eb += G * GC_UNROLL) {
@@ -496,59 +503,103 @@ __device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// multi-word color masks: bit d of word w marks color base + 64 * w + d + 1
-// (static word indices only, so the words stay in registers)
+// color masks wider than one register word
 // ---------------------------------------------------------------------------
 
-template <int NW>
-struct CMask {
-    uint64_t w[NW];
-    __device__ inline void clear() {
-#pragma unroll
-        for (int i = 0; i < NW; i++) w[i] = 0;
+// Marks color x (> base) for First Fit: colors base+1 .. base+64 in the
+// register word m; with WIDE also colors base+65 .. base+64*(gw+1) in the
+// group's LDS words lw[gfirst + o].  Values <= base (no color, a tentative
+// color, a class not recolored yet) fall outside both.
+template <bool WIDE>
+__device__ inline void mask_mark(int32_t x, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw) {
+    const uint32_t d = (uint32_t)x - base - 1u;
+    m |= (d < 64u ? 1ull : 0ull) << (d & 63u);
+    if (WIDE) {
+        const uint32_t o = (d >> 6) - 1u;
+        if (o < (uint32_t)gw) atomicOr(&lw[gfirst + (int)o], 1ull << (d & 63u));
     }
-    // marks color base + d + 1 when d < 64 * NW (d = color - base - 1, unsigned)
-    __device__ inline void set(uint32_t d) {
-        const uint32_t wi = d >> 6;
-        const uint64_t bit = 1ull << (d & 63u);
-#pragma unroll
-        for (int i = 0; i < NW; i++) w[i] |= (wi == (uint32_t)i) ? bit : 0ull;
+}
+
+// OR of m over the aligned group of gsz lanes (gsz a power of two <= 64).
+__device__ inline uint64_t group_or_rt(uint64_t m, int gsz) {
+    for (int o = gsz >> 1; o > 0; o >>= 1) m |= __shfl_xor(m, o);
+    return m;
+}
+
+// First color of the j-th (0-based) unmarked position of 64 words, one word
+// per lane (bit d of lane L's word marks color 64 L + d + 1): the color, or 0
+// when the words hold at most j unmarked positions.  Whole wavefront.
+__device__ inline uint32_t wave_nth_free(uint64_t word, uint32_t j) {
+    const int lane = __lane_id();
+    const uint64_t fr = ~word;
+    const uint32_t cnt = (uint32_t)__popcll(fr);
+    uint32_t inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
     }
-    template <int G>
-    __device__ inline void group_or() {
+    const uint32_t ex = inc - cnt;
+    const bool mine = j >= ex && j < inc;  // exactly one lane when any
+    const uint64_t hit = __ballot(mine);
+    if (!hit) return 0u;
+    const int fl = __ffsll((long long)hit) - 1;
+    const uint32_t r = mine ? 64u * (uint32_t)lane + 1u + nth_set_bit(fr, j - ex) : 0u;
+    return __shfl(r, fl);
+}
+
+// (j+1)-th smallest positive color absent from {C[w] > 0 : w in col[e0..e1)}
+// for a group of G lanes in one scan: colors 1..64 in a register word,
+// 65 .. 64 * G in the group's LDS words (lw: the wavefront's 64 words, lane L
+// owns lw[L]); colors beyond rescan the row in 64-color windows.  Result
+// uniform over the group.
+template <int G, int UNR = GC_UNROLL>
+__device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+                                            int32_t n, uint32_t j, unsigned long long *lw) {
+    const int lane = __lane_id();
+    const int o = lane & (G - 1);
+    const int gfirst = lane - o;
+    lw[lane] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint64_t m = 0;
+    for (int32_t eb = e0 + o; eb < e1; eb += G * UNR) {
+        int32_t w[UNR], x[UNR];
 #pragma unroll
-        for (int i = 0; i < NW; i++) w[i] = group_or_u64<G>(w[i]);
-    }
-    __device__ inline void group_or_rt(int gsz) {
-#pragma unroll
-        for (int i = 0; i < NW; i++)
-            for (int o = gsz >> 1; o > 0; o >>= 1) w[i] |= __shfl_xor(w[i], o);
-    }
-    // smallest unmarked position + 1 in [1, 64 * NW], or 0 if every bit is set
-    __device__ inline uint32_t first_free() const {
-        uint32_t r = 0;
-#pragma unroll
-        for (int i = NW - 1; i >= 0; i--)
-            if (~w[i]) r = 64u * i + (uint32_t)__ffsll((long long)~w[i]);
-        return r;
-    }
-    // position + 1 of the (j+1)-th unmarked bit, or 0 and j reduced by the free count
-    __device__ inline uint32_t nth_free(uint32_t &j) const {
-        uint32_t r = 0;
-        bool found = false;
-#pragma unroll
-        for (int i = 0; i < NW; i++) {
-            const uint64_t fr = ~w[i];
-            const uint32_t cnt = (uint32_t)__popcll(fr);
-            if (!found) {
-                if (j < cnt) {
-                    r = 64u * i + 1u + nth_set_bit(fr, j);
-                    found = true;
-                } else {
-                    j -= cnt;
-                }
-            }
+        for (int u = 0; u < UNR; u++) {
+            const int32_t e = eb + u * G;
+            const int32_t wl = col[e < e1 ? e : eb];
+            w[u] = e < e1 ? wl : -1;
         }
-        return r;
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const bool ok = (uint32_t)w[u] < (uint32_t)n;
+            const int32_t xl = C[ok ? w[u] : 0];
+            x[u] = ok ? xl : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) mask_mark<true>(x[u], 0u, m, lw, gfirst, G - 1);
     }
-};
+    m = group_or_u64<G>(m);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // lane o of the group holds colors 64 o + 1 .. 64 o + 64
+    const uint64_t word = o == 0 ? m : lw[lane - 1];
+    const uint64_t fr = ~word;
+    const uint32_t cnt = (uint32_t)__popcll(fr);
+    uint32_t inc = cnt;
+    for (int d = 1; d < G; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, G);
+        if (o >= d) inc += y;
+    }
+    const uint32_t ex = inc - cnt;
+    const bool mine = j >= ex && j < inc;
+    const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gfirst);
+    const uint64_t hit = __ballot(mine) & gmask;
+    if (hit) {
+        const int fl = __ffsll((long long)hit) - 1;
+        const uint32_t r = mine ? 64u * (uint32_t)o + 1u + nth_set_bit(fr, j - ex) : 0u;
+        return (int32_t)__shfl(r, fl);
+    }
+    const uint32_t total = __shfl(inc, gfirst + G - 1);
+    return group_select<G>(col, e0, e1, C, n, j - total, 64u * G);
+}

@@ -44,10 +44,9 @@
 #define WALK_BLOCK 256
 #define SPIN_LIMIT (1u << 20)
 #define NSEG_PER_RANK 3
-#define HUB_WORDS 64        // mask words per split row: colors 1..4096
-#define HUB_MAX_RANK (64 * HUB_WORDS - 1)  // higher ranks keep long rows in the wavefront bin
+#define HUB_WORDS GC_HUB_WORDS  // hub slot stride; ranks above 64 * hub_words - 1 keep long rows in bin 1
 
-// bin of a row of length d (a split row of a rank above HUB_MAX_RANK goes to bin 1 later)
+// bin of a row of length d (a split row of a rank above hub_max_rank goes to bin 1 later)
 __device__ inline int row_bin(int32_t d, int32_t deg_wave, int32_t deg_split) {
     return d <= deg_wave ? 0 : ((deg_split > 0 && d > deg_split) ? 2 : 1);
 }
@@ -109,7 +108,7 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
 // a bin-0 segment, one vertex of a bin-1 segment, split_len entries of a row
 // of a bin-2 segment.
 __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int32_t perm, uint32_t s_perm, int32_t vpc,
-                                                               int32_t *hist, int32_t *histw, int32_t *hist_s,
+                                                               int32_t hub_max_rank, int32_t *hist, int32_t *histw, int32_t *hist_s,
                                                                int32_t *hist_sc, int32_t *cls, int32_t *pi,
                                                                int32_t *rank, int32_t *off, int32_t *coff,
                                                                int32_t *cursor, int32_t *sbase,
@@ -126,7 +125,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
         if (g < nseg) {
             const int32_t s = g / NSEG_PER_RANK, b = g % NSEG_PER_RANK;
             const int32_t c = pi[s];
-            const bool split = s <= HUB_MAX_RANK;
+            const bool split = s <= hub_max_rank;
             if (b == 0) {
                 sz = hist[c] - histw[c] - hist_s[c];
                 ch = (sz + vpc - 1) / vpc;
@@ -154,7 +153,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
     for (int32_t base = 0; base < k; base += blockDim.x) {
         const int32_t s = base + (int32_t)threadIdx.x;
         int32_t sz = 0;
-        if (s < k && s <= HUB_MAX_RANK) sz = hist_s[pi[s]];
+        if (s < k && s <= hub_max_rank) sz = hist_s[pi[s]];
         int32_t tot;
         const int32_t ex = block_exclusive_scan(sz, &tot, lds);
         if (s < k) sbase[s] = hacc + ex;
@@ -179,7 +178,8 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
 // range once per workgroup.  Writes Cout[v] = -(rank + 1) and the row range
 // next to each list entry.
 __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const int32_t *__restrict__ rp, int64_t nnz,
-                          int32_t deg_wave, int32_t deg_split, int32_t ccap, const int32_t *__restrict__ rank,
+                          int32_t deg_wave, int32_t deg_split, int32_t hub_max_rank, int32_t ccap,
+                          const int32_t *__restrict__ rank,
                           int32_t *__restrict__ cursor, int32_t *__restrict__ list, int2 *__restrict__ rows,
                           const unsigned long long *__restrict__ scal) {
     __shared__ int32_t cnt[SCATTER_BINS];
@@ -209,7 +209,7 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const in
                 row_range(rp, (int32_t)v, nnz, e0, e1);
                 rw[it] = make_int2(e0, e1);
                 int b = row_bin(e1 - e0, deg_wave, deg_split);
-                if (b == 2 && s > HUB_MAX_RANK) b = 1;
+                if (b == 2 && s > hub_max_rank) b = 1;
                 g = NSEG_PER_RANK * s + b;
                 sg[it] = g;
                 if (g >= SCATTER_BINS) {
@@ -281,20 +281,6 @@ struct WalkChunk {
     int32_t seg, v, e0, e1, slot, nsub;
 };
 
-// Marks color x (> base) for First Fit: colors base+1 .. base+64 in the
-// register word m; with WIDE also colors base+65 .. base+64*(gw+1) in the
-// group's LDS words lw[gfirst + o].  Words <= 0 (ranks >= s, invalid ids)
-// fall outside both.
-template <bool WIDE>
-__device__ inline void mark(int32_t x, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw) {
-    const uint32_t d = (uint32_t)x - base - 1u;
-    m |= (d < 64u ? 1ull : 0ull) << (d & 63u);
-    if (WIDE) {
-        const uint32_t o = (d >> 6) - 1u;
-        if (o < (uint32_t)gw) atomicOr(&lw[gfirst + (int)o], 1ull << (d & 63u));
-    }
-}
-
 // Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
 // that are not final yet are waited for in one wavefront-uniform slow path;
 // the rest is branch-free.
@@ -310,7 +296,7 @@ __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t
             if (xv[u] < 0) xv[u] = (-xv[u] - 1 < s) ? wait_positive(&C[w[u]], scal) : 0;
     }
 #pragma unroll
-    for (int u = 0; u < U; u++) mark<WIDE>(xv[u], base, m, lw, gfirst, gw);
+    for (int u = 0; u < U; u++) mask_mark<WIDE>(xv[u], base, m, lw, gfirst, gw);
 }
 
 // Gathers the colors of the neighbor ids w (invalid ids read as 0).
@@ -343,10 +329,6 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
     }
 }
 
-__device__ inline uint64_t group_or_rt(uint64_t m, int gsz) {
-    for (int o = gsz >> 1; o > 0; o >>= 1) m |= __shfl_xor(m, o);
-    return m;
-}
 
 // First Fit for bins 0 and 1.  Colors 1..64 are tracked in a register word;
 // with WIDE (ranks >= 64) each group also owns gsz LDS words (one per lane of
@@ -688,24 +670,6 @@ static gc_status graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, i
     return GC_OK;
 }
 
-// Hub slots for rows longer than deg_split: at most nnz / (deg_split + 1) rows.
-static gc_status ensure_hub_slots(gc_ctx *ctx, const gc_csr *g, int32_t deg_split, hipStream_t s) {
-    const int64_t need = g->nnz / ((int64_t)deg_split + 1) + 1;
-    if (need <= ctx->hub_cap) return GC_OK;
-    GC_HIP(hipStreamSynchronize(s));
-    if (ctx->hub_bits) { GC_HIP(hipFree(ctx->hub_bits)); ctx->hub_bits = nullptr; }
-    if (ctx->hub_cnt) { GC_HIP(hipFree(ctx->hub_cnt)); ctx->hub_cnt = nullptr; }
-    ctx->hub_cap = 0;
-    const int64_t cap = need + 64;
-    if (hipMalloc((void **)&ctx->hub_bits, (size_t)cap * HUB_WORDS * 8) != hipSuccess ||
-        hipMalloc((void **)&ctx->hub_cnt, (size_t)cap * 4) != hipSuccess)
-        return gc_fail(ctx, GC_ERR_OOM, "hub slots (%lld)", (long long)cap);
-    GC_HIP(hipMemsetAsync(ctx->hub_bits, 0, (size_t)cap * HUB_WORDS * 8, s));
-    GC_HIP(hipMemsetAsync(ctx->hub_cnt, 0, (size_t)cap * 4, s));
-    ctx->hub_cap = cap;
-    return GC_OK;
-}
-
 // full: the variant with split rows and LDS mask words (rows of 64 or more
 // entries); the narrow one keeps only a 64-color register window (further
 // windows rescan the row) and lets the first sub-chunk of a split row scan the
@@ -788,8 +752,9 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
     }
     const int32_t deg_split = full ? ctx->tune.deg_split : 0;
     const int32_t split_len = ctx->tune.split_len;
+    const int32_t hub_max_rank = 64 * ctx->tune.hub_words - 1;
     if (deg_split > 0) {
-        status = ensure_hub_slots(ctx, g, deg_split, s);
+        status = gc_ensure_hub_slots(ctx, g->nnz, deg_split, s);
         if (status) return status;
     }
     const int hist_grid = gc_grid(ctx, n, block) < 2 * ctx->num_cu ? gc_grid(ctx, n, block) : 2 * ctx->num_cu;
@@ -800,13 +765,14 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
                                                              ctx->hist_sc, ctx->scal));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
-                                ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, ctx->hist,
+                                ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, hub_max_rank, ctx->hist,
                                 ctx->histw, ctx->hist_s, ctx->hist_sc, (int32_t *)ctx->keys, ctx->pi, ctx->rank,
                                 ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->scal));
     GC_LAUNCHED();
     const int64_t tiles = ((int64_t)n + block * SCATTER_ITEMS - 1) / (block * SCATTER_ITEMS);
     GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, g->row_ptr, g->nnz,
-                                                                         deg_wave, deg_split, ctx->ccap, ctx->rank,
+                                                                         deg_wave, deg_split, hub_max_rank, ctx->ccap,
+                                                                         ctx->rank,
                                                                          ctx->cursor, ctx->list, ctx->rows, ctx->scal));
     GC_LAUNCHED();
     if (deg_split > 0) {

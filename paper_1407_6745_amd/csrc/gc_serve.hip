@@ -1,0 +1,319 @@
+// gc_serve.hip - request server: continuous batching of independent coloring
+// requests on one GPU (host code only; the kernels are those of the
+// single-graph calls).
+//
+// Threads.  One worker thread per slot.  A worker waits until the oldest
+// queued request fits: a slot (itself) is idle and the arena has room for the
+// request's footprint.  It then takes the request, copies the graph into its
+// arena block on the slot's stream, runs the initial coloring and the
+// recoloring passes through the public calls with the slot's context, copies
+// the colors back, frees the block and posts a completion record.  Every
+// state change (queue, arena, completions) happens under one mutex; GPU work
+// happens outside it.
+#include "gc_internal.h"
+#include "gc_serve.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr int64_t ARENA_ALIGN = 256;
+
+int64_t align_up(int64_t x) { return (x + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN; }
+
+// First-fit allocator over [0, size): free blocks keyed by offset, merged
+// with their neighbors on release.
+class Arena {
+   public:
+    void reset(int64_t size) {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+        size_ = size;
+        used_ = peak_ = 0;
+    }
+    bool alloc(int64_t bytes, int64_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const int64_t rest = it->second - bytes;
+            const int64_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest > 0) free_[at] = rest;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(int64_t off, int64_t bytes) {
+        auto next = free_.lower_bound(off);
+        int64_t start = off, len = bytes;
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        if (next != free_.end() && off + bytes == next->first) {
+            len += next->second;
+            free_.erase(next);
+        }
+        free_[start] = len;
+        used_ -= bytes;
+    }
+    int64_t size() const { return size_; }
+    int64_t used() const { return used_; }
+    int64_t peak() const { return peak_; }
+
+   private:
+    std::map<int64_t, int64_t> free_;
+    int64_t size_ = 0, used_ = 0, peak_ = 0;
+};
+
+struct Waiting {
+    gc_request req;
+    int64_t footprint;
+    double t_submit;
+};
+
+struct Slot {
+    gc_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+int64_t footprint_of(const gc_request &r) {
+    return align_up(4 * ((int64_t)r.n + 1)) + align_up(4 * r.nnz) + align_up(4 * (int64_t)r.n);
+}
+
+}  // namespace
+
+struct gc_server {
+    gc_server_config cfg{};
+    char *arena_base = nullptr;
+    Arena arena;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Waiting> queue;
+    std::deque<gc_request_done> done;
+    std::vector<Slot> slots;
+    std::vector<std::thread> workers;
+    bool stopping = false;
+    int64_t submitted = 0, completed = 0, running = 0, peak_running = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    void worker(int idx);
+    gc_request_done run(int idx, const Waiting &w, int64_t off);
+};
+
+gc_request_done gc_server::run(int idx, const Waiting &w, int64_t off) {
+    Slot &sl = slots[idx];
+    const gc_request &r = w.req;
+    gc_request_done d{};
+    d.tag = r.tag;
+    d.slot = idx;
+    d.footprint = w.footprint;
+    d.t_submit = w.t_submit;
+    char *base = arena_base + off;
+    int32_t *rp = (int32_t *)base;
+    int32_t *col = (int32_t *)(base + align_up(4 * ((int64_t)r.n + 1)));
+    int32_t *colors = (int32_t *)((char *)col + align_up(4 * r.nnz));
+    gc_status st = GC_OK;
+    auto hip_ok = [&](hipError_t e) {
+        if (e != hipSuccess && st == GC_OK) st = GC_ERR_DEVICE;
+        return e == hipSuccess;
+    };
+    hip_ok(hipEventRecord(sl.ev0, sl.stream));
+    hip_ok(hipMemcpyAsync(rp, r.row_ptr, 4 * ((size_t)r.n + 1), hipMemcpyHostToDevice, sl.stream));
+    if (r.nnz > 0) hip_ok(hipMemcpyAsync(col, r.col_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, sl.stream));
+    gc_csr g{r.n, 0, r.nnz, rp, r.nnz > 0 ? col : nullptr};
+    gc_stats s0{}, s1{};
+    if (st == GC_OK) st = gc_init_color(sl.ctx, &g, r.select, r.X, r.seed, 0, 0, colors, &s0, sl.stream);
+    d.rounds = s0.rounds;
+    d.colors_init = s0.num_colors;
+    d.colors_final = s0.num_colors;
+    for (int32_t p = 0; p < r.passes && st == GC_OK; p++) {
+        st = gc_recolor(sl.ctx, &g, r.perm, r.seed, p, colors, colors, p == r.passes - 1 ? &s1 : nullptr, sl.stream);
+        if (st == GC_OK && p == r.passes - 1) d.colors_final = s1.num_colors;
+    }
+    if (st == GC_OK && r.n > 0)
+        hip_ok(hipMemcpyAsync(r.colors, colors, 4 * (size_t)r.n, hipMemcpyDeviceToHost, sl.stream));
+    hip_ok(hipEventRecord(sl.ev1, sl.stream));
+    hip_ok(hipStreamSynchronize(sl.stream));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sl.ev0, sl.ev1) == hipSuccess) d.device_ms = ms;
+    d.status = st;
+    return d;
+}
+
+void gc_server::worker(int idx) {
+    if (hipSetDevice(cfg.device) != hipSuccess) return;
+    for (;;) {
+        Waiting w{};
+        int64_t off = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                if (!queue.empty() && arena.alloc(queue.front().footprint, &off)) break;
+                if (stopping && queue.empty()) return;
+                cv_work.wait(lk);
+            }
+            w = queue.front();
+            queue.pop_front();
+            running++;
+            peak_running = std::max(peak_running, running);
+        }
+        // a request just left the queue: the next one may fit as well
+        cv_work.notify_all();
+        const double t_admit = now();
+        int64_t conc;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            conc = running;
+        }
+        gc_request_done d = run(idx, w, off);
+        d.t_admit = t_admit;
+        d.running_at_admit = (int32_t)conc;
+        d.t_done = now();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            arena.release(off, w.footprint);
+            running--;
+            completed++;
+            done.push_back(d);
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+static void server_free(gc_server *s) {
+    for (Slot &sl : s->slots) {
+        if (sl.ev0) (void)hipEventDestroy(sl.ev0);
+        if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.ctx) gc_ctx_destroy(sl.ctx);
+    }
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    delete s;
+}
+
+extern "C" gc_status gc_server_create(const gc_server_config *cfg, gc_server **out) {
+    if (!cfg || !out) return GC_ERR_ARG;
+    *out = nullptr;
+    if (cfg->slots < 1 || cfg->slots > 64 || cfg->hbm_budget <= 0 || cfg->max_n < 0 || cfg->max_nnz < 0 ||
+        cfg->max_n >= INT32_MAX || cfg->max_nnz >= INT32_MAX)
+        return GC_ERR_ARG;
+    gc_server *s = new (std::nothrow) gc_server();
+    if (!s) return GC_ERR_OOM;
+    s->cfg = *cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    if (hipSetDevice(cfg->device) != hipSuccess) {
+        delete s;
+        return GC_ERR_DEVICE;
+    }
+    if (hipMalloc((void **)&s->arena_base, (size_t)cfg->hbm_budget) != hipSuccess) {
+        s->arena_base = nullptr;
+        server_free(s);
+        return GC_ERR_OOM;
+    }
+    s->arena.reset(cfg->hbm_budget);
+    s->slots.resize(cfg->slots);
+    for (Slot &sl : s->slots) {
+        gc_status st = gc_ctx_create(cfg->device, cfg->max_n, cfg->max_nnz, &sl.ctx);
+        if (st != GC_OK) {
+            sl.ctx = nullptr;
+            server_free(s);
+            return st;
+        }
+        gc_tuning t;
+        gc_ctx_get_tuning(sl.ctx, &t);
+        t.walk_mode = 1;  // per-class launches: no kernel waits on other workgroups
+        gc_ctx_set_tuning(sl.ctx, &t);
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreate(&sl.ev0) != hipSuccess || hipEventCreate(&sl.ev1) != hipSuccess) {
+            server_free(s);
+            return GC_ERR_DEVICE;
+        }
+    }
+    for (int i = 0; i < cfg->slots; i++) s->workers.emplace_back(&gc_server::worker, s, i);
+    *out = s;
+    return GC_OK;
+}
+
+extern "C" gc_status gc_server_submit(gc_server *s, const gc_request *r) {
+    if (!s || !r) return GC_ERR_ARG;
+    if (r->n < 0 || r->nnz < 0 || r->n > s->cfg.max_n || r->nnz > s->cfg.max_nnz) return GC_ERR_ARG;
+    if (!r->row_ptr || (r->nnz > 0 && !r->col_idx) || (r->n > 0 && !r->colors)) return GC_ERR_ARG;
+    if (r->select != GC_FIRST_FIT && r->select != GC_RANDOM_X) return GC_ERR_ARG;
+    if (r->select == GC_RANDOM_X && (r->X < 1 || r->X > GC_MAX_X)) return GC_ERR_ARG;
+    if (r->perm < 0 || r->perm > 3 || r->passes < 0) return GC_ERR_ARG;
+    Waiting w{*r, footprint_of(*r), 0.0};
+    if (w.footprint > s->arena.size()) return GC_ERR_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        w.t_submit = s->now();
+        s->queue.push_back(w);
+        s->submitted++;
+    }
+    s->cv_work.notify_all();
+    return GC_OK;
+}
+
+extern "C" gc_status gc_server_poll(gc_server *s, gc_request_done *out, int32_t cap, int32_t *count, int32_t timeout_ms) {
+    if (!s || !count || cap < 0 || (cap > 0 && !out)) return GC_ERR_ARG;
+    *count = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && timeout_ms != 0) {
+        auto ready = [&] { return !s->done.empty(); };
+        if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+        else s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+    }
+    int32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *count = k;
+    return GC_OK;
+}
+
+extern "C" gc_status gc_server_get_stats(gc_server *s, gc_server_stats *o) {
+    if (!s || !o) return GC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    o->submitted = s->submitted;
+    o->completed = s->completed;
+    o->waiting = (int64_t)s->queue.size();
+    o->running = s->running;
+    o->peak_running = s->peak_running;
+    o->arena_size = s->arena.size();
+    o->arena_used = s->arena.used();
+    o->arena_peak = s->arena.peak();
+    return GC_OK;
+}
+
+extern "C" double gc_server_now(gc_server *s) { return s ? s->now() : 0.0; }
+
+extern "C" void gc_server_destroy(gc_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_work.notify_all();
+    for (std::thread &t : s->workers) t.join();
+    server_free(s);
+}

@@ -12,19 +12,22 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1407_6745_amd", "libgc.so")
-HEADER = os.path.join(ROOT, "include", "gc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gc.h", "gc_serve.h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gc_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(gc_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("gc_init_color", "gc_recolor", "gc_validate", "gc_count_colors", "gc_batch_color", "gc_check_csr",
-                 "gc_ctx_create", "gc_ctx_destroy", "gc_status_string"):
+                 "gc_ctx_create", "gc_ctx_destroy", "gc_status_string", "gc_server_create", "gc_server_submit",
+                 "gc_server_poll", "gc_server_destroy"):
         assert must in names
 
 
@@ -83,3 +86,30 @@ def test_no_oracle_in_product_path():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "liboracle" not in text and "gc_oracle" not in text, f
+
+
+def test_server_struct_layouts():
+    """The binding's ctypes mirrors of the server structs have the C sizes."""
+    import paper_1407_6745_amd as gc
+
+    assert ctypes.sizeof(gc.ServerConfigArgs) == 32
+    assert ctypes.sizeof(gc.RequestArgs) == 72
+    assert ctypes.sizeof(gc.RequestDoneArgs) == 72
+    assert ctypes.sizeof(gc.ServerStatsArgs) == 64
+    assert gc.request_footprint(0, 0) == 256 + 0 + 0
+    assert gc.request_footprint(100, 1000) == 512 + 4096 + 512
+
+
+def test_server_create_rejects_bad_config_without_gpu():
+    import torch
+
+    import paper_1407_6745_amd as gc
+
+    h = ctypes.c_void_p()
+    for cfg in (gc.ServerConfigArgs(0, 0, 1 << 20, 10, 10), gc.ServerConfigArgs(0, 65, 1 << 20, 10, 10),
+                gc.ServerConfigArgs(0, 2, 0, 10, 10), gc.ServerConfigArgs(0, 2, 1 << 20, -1, 10)):
+        assert gc.lib().gc_server_create(ctypes.byref(cfg), ctypes.byref(h)) == gc.ERR_ARG and not h.value
+    if not torch.cuda.is_available():
+        cfg = gc.ServerConfigArgs(0, 2, 1 << 20, 10, 10)
+        rc = gc.lib().gc_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        assert rc in (gc.ERR_DEVICE, gc.ERR_OOM) and not h.value

@@ -43,9 +43,9 @@ GRAPHS = {
 }
 
 
-def _init_equal(gc, g, sel, X, seed, flags=0):
+def _init_equal(gc, g, sel, X, seed, flags=0, ctx=None):
     rp, col = dev(g)
-    c, st = gc.init_color(rp, col, sel, X, seed, flags=flags)
+    c, st = gc.init_color(rp, col, sel, X, seed, flags=flags, ctx=ctx)
     ref = oracle.init_color(g, sel, X, seed, flags=flags)
     got = c.cpu().numpy()
     assert np.array_equal(got, ref.colors), f"{g.name}: {int((got != ref.colors).sum())} vertex colors differ"
@@ -185,6 +185,7 @@ TUNINGS = [
     dict(block=64, grid_per_cu=1), dict(block=1024, grid_per_cu=2),
     dict(deg_split=0), dict(deg_wave=4, deg_split=16, split_len=64),
     dict(deg_wave=8, deg_split=64, split_len=64, group=8, xcd_chunks=1),
+    dict(deg_wave=4, deg_split=16, split_len=64, hub_words=1),
 ]
 
 
@@ -231,6 +232,7 @@ MANY_CLASS_TUNINGS = [
     dict(group=1, deg_wave=512),                    # one lane per row: 64-color windows beyond the LDS word
     dict(group=4, deg_wave=512),
     dict(deg_wave=16, deg_split=128, split_len=64),  # split rows, multi-word hub bitmaps
+    dict(deg_wave=16, deg_split=128, split_len=64, hub_words=1),  # ranks >= 64: long rows on one wavefront
     dict(walk_mode=1),
 ]
 
@@ -268,3 +270,34 @@ def test_recolor_beyond_hub_ranks(gc):
         cur, st = gc.recolor(rp, col, cur, perm, 3, p, out=cur)
         exp = oracle.recolor(g, exp, perm, 3, p).colors
         assert np.array_equal(cur.cpu().numpy(), exp), p
+
+
+SPLIT_TUNINGS = [
+    dict(deg_wave=8, deg_split=64, split_len=64),
+    dict(deg_wave=8, deg_split=64, split_len=64, hub_words=1),  # colors above 64: the row is rescanned
+    dict(deg_wave=0, deg_split=1, split_len=64, group=1),        # every row of 2+ entries split
+]
+
+
+@pytest.mark.parametrize("t", SPLIT_TUNINGS, ids=str)
+@pytest.mark.parametrize("name", ["rmat", "star", "complete100", "er"])
+def test_init_split_rows(gc, name, t):
+    """Initial coloring with long rows split across wavefronts (round 0 and
+    later rounds, First Fit and Random-X) against the oracle."""
+    g = GRAPHS[name]()
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(**t)
+    for sel, X, seed in ((gc.FIRST_FIT, 1, 4), (gc.RANDOM_X, 7, 5)):
+        _init_equal(gc, g, sel, X, seed, ctx=ctx)
+    ctx.close()
+
+
+def test_init_split_many_colors(gc):
+    """K_300 with First Fit (one vertex per round, colors up to 300) under
+    split rows with one hub word: every round past color 64 rescans."""
+    g = gen.complete(300)
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(deg_wave=16, deg_split=128, split_len=64, hub_words=1)
+    c, ref = _init_equal(gc, g, gc.FIRST_FIT, 1, 6, ctx=ctx)
+    assert ref.stats["rounds"] == 300
+    ctx.close()
