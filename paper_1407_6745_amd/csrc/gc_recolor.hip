@@ -258,22 +258,6 @@ __global__ void k_split_prefix(const int32_t *__restrict__ off, const int2 *__re
     }
 }
 
-// Waits (bounded) until *p holds a positive value, reading past the L2.  If
-// any wait of the launch has already given up, returns at once, so a broken
-// dependency cannot stretch the kernel beyond about one wait limit.
-__device__ inline int32_t wait_positive(int32_t *p, unsigned long long *scal) {
-    for (uint32_t it = 0; it < SPIN_LIMIT; it++) {
-        int32_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (x > 0) return x;
-        if ((it & 1023u) == 1023u &&
-            (__hip_atomic_load(&scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))
-            return 0;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    atomicOr(&scal[S_ERR], 2ull);  // gives up: the result is wrong but the kernel ends
-    return 0;
-}
-
 // One work chunk as a wavefront sees it: segment, the vertex of this lane's
 // group (-1: none) and the part of its row this chunk scans; for a split row
 // also its hub slot and number of sub-chunks.
@@ -282,18 +266,52 @@ struct WalkChunk {
 };
 
 // Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
-// that are not final yet are waited for in one wavefront-uniform slow path;
-// the rest is branch-free.
+// that are not final yet (or whose plain load saw a stale line) are re-read
+// in one wavefront-uniform slow path: every pending word of every lane is
+// reloaded past the L2 at once, so one round trip settles all words that
+// are final by then; the rest is branch-free.
 template <int U, bool WIDE>
 __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t base, uint64_t &m,
                               unsigned long long *lw, int gfirst, int gw, int32_t *C, unsigned long long *scal) {
+    bool pend[U];
     bool need = false;
 #pragma unroll
-    for (int u = 0; u < U; u++) need |= xv[u] < 0 && -xv[u] - 1 < s;
+    for (int u = 0; u < U; u++) {
+        pend[u] = xv[u] < 0 && -xv[u] - 1 < s;
+        need |= pend[u];
+    }
     if (__ballot(need)) {
 #pragma unroll
         for (int u = 0; u < U; u++)
-            if (xv[u] < 0) xv[u] = (-xv[u] - 1 < s) ? wait_positive(&C[w[u]], scal) : 0;
+            if (xv[u] < 0 && !pend[u]) xv[u] = 0;  // a rank >= s: not a constraint
+        for (uint32_t it = 0;; it++) {
+            int32_t y[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                y[u] = 0;
+                if (pend[u]) y[u] = __hip_atomic_load(&C[w[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            bool left = false;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (pend[u] && y[u] > 0) {
+                    xv[u] = y[u];
+                    pend[u] = false;
+                }
+                left |= pend[u];
+            }
+            if (!__ballot(left)) break;
+            if (it >= SPIN_LIMIT ||
+                ((it & 1023u) == 1023u &&
+                 (__hip_atomic_load(&scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))) {
+                if (it >= SPIN_LIMIT) atomicOr(&scal[S_ERR], 2ull);  // gives up: wrong result, but the kernel ends
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (pend[u]) xv[u] = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
     }
 #pragma unroll
     for (int u = 0; u < U; u++) mask_mark<WIDE>(xv[u], base, m, lw, gfirst, gw);
@@ -336,8 +354,9 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
 // Colors beyond (a free color is at most the row length + 1) rescan the row
 // in 64-color windows.  The first window takes the prefetched ids w.
 template <int U, bool WIDE>
-__device__ inline void finish_row(const WalkChunk &t, const int32_t *w, int gsz, const int32_t *__restrict__ col,
-                                  int32_t n, int32_t *C, unsigned long long *lw, unsigned long long *scal) {
+__device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const int32_t *x, int gsz,
+                                  const int32_t *__restrict__ col, int32_t n, int32_t *C, unsigned long long *lw,
+                                  unsigned long long *scal) {
     const int32_t s = t.seg / NSEG_PER_RANK;
     const int lane = __lane_id();
     const int l = lane & (gsz - 1);
@@ -349,7 +368,8 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, int gsz,
     }
     uint64_t m = 0;
     int32_t xv[U];
-    gather<U>(w, xv, C, n);
+#pragma unroll
+    for (int u = 0; u < U; u++) xv[u] = x[u];
     absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, scal);
     scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, scal);
     m = group_or_rt(m, gsz);
@@ -387,7 +407,8 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, int gsz,
 // ends last reads the bitmap, publishes the color and clears the slot for the
 // next pass.
 template <int U>
-__device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const int32_t *__restrict__ col, int32_t n,
+__device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const int32_t *x,
+                                    const int32_t *__restrict__ col, int32_t n,
                                     int32_t *C, unsigned long long *lw, unsigned long long *hub_bits, int32_t *hub_cnt,
                                     unsigned long long *scal) {
     const int32_t s = t.seg / NSEG_PER_RANK;
@@ -399,7 +420,8 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
     __builtin_amdgcn_wave_barrier();
     uint64_t m = 0;
     int32_t xv[U];
-    gather<U>(w, xv, C, n);
+    #pragma unroll
+    for (int u = 0; u < U; u++) xv[u] = x[u];
     absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
     scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
     m = group_or_rt(m, 64);
@@ -519,30 +541,44 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             w[u] = ok ? wl : -1;
         }
     };
-    // stage C: gather, wait for lower ranks, First Fit, publish
-    auto finish = [&](const WalkChunk &t, const int32_t *w) {
+    // stage D: wait for lower ranks, First Fit, publish
+    auto finish = [&](const WalkChunk &t, const int32_t *w, const int32_t *x) {
         const int b = t.seg % NSEG_PER_RANK;
         const int32_t s = t.seg / NSEG_PER_RANK;
-        if (!FULL) finish_row<U, false>(t, w, b ? 64 : G, col, n, C, lw, scal);
-        else if (b == 2) finish_split<U>(t, w, col, n, C, lw, hub_bits, hub_cnt, scal);
-        else if (s < 64) finish_row<U, false>(t, w, b ? 64 : G, col, n, C, lw, scal);
-        else finish_row<U, true>(t, w, b ? 64 : G, col, n, C, lw, scal);
+        if (!FULL) finish_row<U, false>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
+        else if (b == 2) finish_split<U>(t, w, x, col, n, C, lw, hub_bits, hub_cnt, scal);
+        else if (s < 64) finish_row<U, false>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
+        else finish_row<U, true>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
     };
 
+    // Software pipeline, one stage per iteration: chunk i+3's vertex and row
+    // (A), chunk i+2's first U neighbor ids (B), chunk i+1's neighbor colors
+    // (C, plain loads; stale or unfinished words are re-read in stage D), and
+    // chunk i's waits, First Fit and store (D).  Every stage's inputs were
+    // requested one iteration earlier.
     advance();
-    WalkChunk cur, nxt, nxt2;
-    int32_t wcur[U], wnxt[U];
-    load_chunk(cur);
-    load_ids(cur, wcur);
-    load_chunk(nxt);
-    while (cur.seg < nseg) {
-        load_chunk(nxt2);                          // A: chunk i+2
-        if (nxt.seg < nseg) load_ids(nxt, wnxt);   // B: chunk i+1
-        finish(cur, wcur);                         // C: chunk i
-        cur = nxt;
-        nxt = nxt2;
+    WalkChunk c0, c1, c2, c3;
+    int32_t w0[U], w1[U], w2[U], x0[U], x1[U];
+    load_chunk(c0);
+    load_chunk(c1);
+    load_chunk(c2);
+    load_ids(c0, w0);
+    load_ids(c1, w1);
+    gather<U>(w0, x0, C, n);
+    while (c0.seg < nseg) {
+        load_chunk(c3);                                  // A: chunk i+3
+        if (c2.seg < nseg) load_ids(c2, w2);             // B: chunk i+2
+        if (c1.seg < nseg) gather<U>(w1, x1, C, n);      // C: chunk i+1
+        finish(c0, w0, x0);                              // D: chunk i
+        c0 = c1;
+        c1 = c2;
+        c2 = c3;
 #pragma unroll
-        for (int u = 0; u < U; u++) wcur[u] = wnxt[u];
+        for (int u = 0; u < U; u++) {
+            w0[u] = w1[u];
+            x0[u] = x1[u];
+            w1[u] = w2[u];
+        }
     }
 }
 
