@@ -51,6 +51,29 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_traffic_k_walk_flow_mesh27_128.txt")
+
+
+def recorded_traffic(workload, tuning):
+    """HBM-side bytes per walk launch from the committed rocprofv3 counter
+    summary, or None when that record does not describe the kernel that runs
+    now (different workload, tuning or kernel source)."""
+    import hashlib
+
+    try:
+        rec = dict(line.split(": ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
+                   if ": " in line and not line.startswith("#"))
+    except OSError:
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1407_6745_amd", "csrc", f), "rb").read()
+                   for f in ("gc_recolor.hip", "gc_internal.h"))
+    want = {k: int(v) for k, v in (kv.split("=") for kv in rec.get("tuning", "").split())}
+    if (rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256")
+            or any(tuning.get(k) != v for k, v in want.items())):
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(g, select, X, perm, passes, seed, budget_s=12.0):
     """The oracle (single thread, as it stands) on whole steps of the same workload."""
     import oracle
@@ -429,7 +452,8 @@ def main():
     pass_bytes = 8 * g.nnz + 12 * g.n + 4
     achieved = walk_bytes / (walk_avg_ms / 1e3) / 1e9 if walk_launches else 0.0
     roofline = {"kernel": "k_walk_flow (recoloring class walk)", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(args.workload, ctx.tuning),
                 "bytes_per_launch": walk_bytes, "avg_launch_ms": round(walk_avg_ms, 5), "launches": walk_launches,
                 "dominant_kind": dom}
     out = {
