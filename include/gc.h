@@ -100,8 +100,9 @@ typedef struct gc_stats {
 /* Tuning knobs.  No knob changes any result, only the speed. */
 typedef struct gc_tuning {
     int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
-    int32_t deg_wave;      /* recoloring: rows with degree > deg_wave get a whole wavefront per vertex */
-    int32_t group;         /* lanes per vertex for the other rows (power of two, 1..64) */
+    int32_t deg_wave;      /* rows with more than deg_wave entries get a whole wavefront per vertex */
+    int32_t group;         /* lanes per vertex for rows of at most deg_wave entries in the initial coloring
+                              (and in the walk when walk_group says so; power of two, 1..64) */
     int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
     int32_t walk_mode;     /* recoloring class walk: 0 = one persistent launch, waits per dependency;
                               1 = one launch per class (host reads the class count) */
@@ -116,6 +117,9 @@ typedef struct gc_tuning {
     int32_t hub_words;     /* 64-bit mask words per split row (1..64): colors up to 64 * hub_words are merged
                               across wavefronts; larger colors rescan the row, and recoloring ranks of
                               64 * hub_words and above keep their long rows on one wavefront */
+    int32_t walk_group;    /* lanes per vertex in the recoloring walk (power of two, 1..64); 0 = automatic:
+                              8 when every row is shorter than 64 entries, else `group` */
+    int32_t reserved;
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);

@@ -52,7 +52,7 @@ gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
 static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
-                    c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first};
+                    c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -77,6 +77,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.deg_split = 4096;
     ctx->tune.split_len = 1024;
     ctx->tune.hub_words = GC_HUB_WORDS;
+    ctx->tune.walk_group = 0;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -96,7 +97,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         {(void **)&ctx->coff, (3 * CC + 4) * 4},
         {(void **)&ctx->histw, CC * 4},      {(void **)&ctx->hist_s, CC * 4},
         {(void **)&ctx->hist_sc, CC * 4},    {(void **)&ctx->sbase, (CC + 2) * 4},
-        {(void **)&ctx->hsub, N * 4},
+        {(void **)&ctx->hsub, N * 4},        {(void **)&ctx->shadow, N * 2 + 256},
         {(void **)&ctx->cursor, (3 * CC + 4) * 4}, {(void **)&ctx->keys, CC * 8},
         {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
         {(void **)&ctx->round_stats, 2 * N * 8},
@@ -233,7 +234,10 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->hub_words < 1 || t->hub_words > GC_HUB_WORDS)
         return gc_fail(ctx, GC_ERR_ARG, "hub_words must be in [1, %d]", GC_HUB_WORDS);
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
+    if (t->walk_group < 0 || t->walk_group > 64 || (t->walk_group & (t->walk_group - 1)))
+        return gc_fail(ctx, GC_ERR_ARG, "walk_group must be 0 or a power of two in [1, 64]");
     ctx->tune = *t;
+    ctx->tune.reserved = 0;
     return GC_OK;
 }
 
@@ -538,3 +542,39 @@ gc_status gc_ensure_hub_slots(gc_ctx *ctx, int64_t nnz, int32_t deg_split, hipSt
     ctx->hub_cap = cap;
     return GC_OK;
 }
+
+__global__ void k_max_degree(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, unsigned long long *scal) {
+    __shared__ int32_t lds[32];
+    int32_t mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e0, e1;
+        row_range(rp, (int32_t)v, nnz, e0, e1);
+        mx = max(mx, e1 - e0);
+    }
+    const int32_t bm = block_max_i32(mx, lds);
+    if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXDEG], bm);
+}
+
+// Longest row of g, computed once per graph (keyed by its arrays and sizes;
+// it only picks the walk variant, every variant colors any graph correctly).
+gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out) {
+    if (ctx->deg_key_rp == g->row_ptr && ctx->deg_key_col == g->col_idx && ctx->deg_key_n == g->n &&
+        ctx->deg_key_nnz == g->nnz) {
+        *out = ctx->deg_max;
+        return GC_OK;
+    }
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXDEG, 0, 8, s));
+    const int grid = gc_grid(ctx, g->n, 256) < 2 * ctx->num_cu ? gc_grid(ctx, g->n, 256) : 2 * ctx->num_cu;
+    k_max_degree<<<grid, 256, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
+    GC_LAUNCHED();
+    gc_status st = gc_sync_scalars(ctx, s);
+    if (st) return st;
+    ctx->deg_max = (int32_t)ctx->hscal[S_MAXDEG];
+    ctx->deg_key_rp = g->row_ptr;
+    ctx->deg_key_col = g->col_idx;
+    ctx->deg_key_n = g->n;
+    ctx->deg_key_nnz = g->nnz;
+    *out = ctx->deg_max;
+    return GC_OK;
+}
+

@@ -460,8 +460,12 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     GC_HIP(hipMemsetAsync(cnt, 0, 5 * 8, s));
     // Long rows (longer than deg_wave and deg_split) go to the split kernels;
     // the others skip them.
-    const bool split = ctx->tune.deg_split > 0;
+    int32_t maxdeg = 0;
+    status = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (status) return status;
     const int32_t thresh = deg_wave > ctx->tune.deg_split ? deg_wave : ctx->tune.deg_split;
+    // split kernels only when some row is long enough (without them every row is handled by the others)
+    const bool split = ctx->tune.deg_split > 0 && maxdeg > thresh;
     const int32_t skip = split ? thresh : INT32_MAX;
     const int32_t split_len = ctx->tune.split_len;
     if (split) {

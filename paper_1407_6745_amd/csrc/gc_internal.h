@@ -53,6 +53,7 @@ struct gc_ctx {
     int32_t *hsub;           // per list slot of a split row: its first chunk inside the segment (max_n + 64)
     unsigned long long *hub_bits;  // per hub slot: HUB_WORDS color-mask words, zero between calls
     int32_t *hub_cnt;        // per hub slot: finished chunks, zero between calls
+    void *shadow;            // recoloring walk: compact copy of the colors (2 bytes per vertex)
     int32_t *hub_v;          // initial coloring: per hub slot, the long row's vertex
     int32_t *hub_first;      // initial coloring: per hub slot, its first chunk
     int64_t hub_cap;         // hub slots allocated
@@ -115,6 +116,18 @@ int gc_grid(const gc_ctx *ctx, int64_t work, int block);
 // Launch helpers shared between files (defined in gc_api.hip).
 gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax);
 gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s);
+// Longest row of g, computed once per graph (keyed by its arrays and sizes;
+// it only picks kernel variants, never results).  Synchronizes the stream on
+// a new graph.
+gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out);
+
+// Lanes per vertex of the recoloring walk: the walk_group knob, or when it is
+// 0, 8 for graphs whose rows are all shorter than 64 entries (full = false)
+// and the group knob otherwise.
+inline int gc_walk_group(const gc_ctx *ctx, bool full) {
+    return ctx->tune.walk_group ? ctx->tune.walk_group : (full ? ctx->tune.group : 8);
+}
+
 // Mask words of one split row (colors 1 .. 64 * GC_HUB_WORDS).
 #define GC_HUB_WORDS 64
 // Hub slots for rows longer than deg_split (at most nnz / (deg_split + 1)

@@ -44,6 +44,8 @@
 #define WALK_BLOCK 256
 #define SPIN_LIMIT (1u << 20)
 #define NSEG_PER_RANK 3
+#define CT_MAX_K1 127    // classes that fit the one-byte compact color copy
+#define CT_MAX_K2 32767  // classes that fit the two-byte compact color copy
 #define HUB_WORDS GC_HUB_WORDS  // hub slot stride; ranks above 64 * hub_words - 1 keep long rows in bin 1
 
 // bin of a row of length d (a split row of a rank above hub_max_rank goes to bin 1 later)
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
 // vertices per workgroup; segments below SCATTER_BINS reserve their list
 // range once per workgroup.  Writes Cout[v] = -(rank + 1) and the row range
 // next to each list entry.
-__global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const int32_t *__restrict__ rp, int64_t nnz,
+__global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S, const int32_t *__restrict__ rp, int64_t nnz,
                           int32_t deg_wave, int32_t deg_split, int32_t hub_max_rank, int32_t ccap,
                           const int32_t *__restrict__ rank,
                           int32_t *__restrict__ cursor, int32_t *__restrict__ list, int2 *__restrict__ rows,
@@ -218,6 +220,8 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, const in
                     rows[p] = rw[it];
                     Cout[v] = -(s + 1);
                 }
+                if (k <= CT_MAX_K1) ((uint8_t *)S)[v] = (uint8_t)(0x80 | s);
+                else if (k <= CT_MAX_K2) ((uint16_t *)S)[v] = (uint16_t)(0x8000 | s);
             } else {
                 Cout[v] = 0;
             }
@@ -264,6 +268,31 @@ __global__ void k_split_prefix(const int32_t *__restrict__ off, const int2 *__re
 struct WalkChunk {
     int32_t seg, v, e0, e1, slot, nsub;
 };
+
+// Compact copy of the colors for the neighbor gathers of the walk (CT = 1:
+// one byte per vertex when there are at most 127 classes, CT = 2: two bytes
+// when at most 32767; CT = 0: none).  The top bit marks "not recolored yet"
+// with the rank in the low bits; otherwise the word is the final color.  Two
+// or four times as many vertices share a cache line as in the int32 array,
+// so a gather instruction touches that many fewer lines.  The copy only
+// speeds up the first look: pending words are still re-read from the int32
+// array (coherently), which stays the reference.
+template <int CT>
+__device__ inline int32_t compact_load(const void *S, int32_t w) {
+    if (CT == 1) {
+        const uint32_t x = ((const uint8_t *)S)[w];
+        return (x & 0x80u) ? -(int32_t)(x & 0x7Fu) - 1 : (int32_t)x;
+    } else {
+        const uint32_t x = ((const uint16_t *)S)[w];
+        return (x & 0x8000u) ? -(int32_t)(x & 0x7FFFu) - 1 : (int32_t)x;
+    }
+}
+
+template <int CT>
+__device__ inline void compact_store(void *S, int32_t v, int32_t color) {
+    if (CT == 1) ((uint8_t *)S)[v] = (uint8_t)color;
+    if (CT == 2) ((uint16_t *)S)[v] = (uint16_t)color;
+}
 
 // Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
 // that are not final yet (or whose plain load saw a stale line) are re-read
@@ -353,10 +382,10 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
 // the group: this lane's word is lw[lane]) for colors 65 .. 64 * (gsz + 1).
 // Colors beyond (a free color is at most the row length + 1) rescan the row
 // in 64-color windows.  The first window takes the prefetched ids w.
-template <int U, bool WIDE>
+template <int U, bool WIDE, int CT>
 __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const int32_t *x, int gsz,
-                                  const int32_t *__restrict__ col, int32_t n, int32_t *C, unsigned long long *lw,
-                                  unsigned long long *scal) {
+                                  const int32_t *__restrict__ col, int32_t n, int32_t *C, void *S,
+                                  unsigned long long *lw, unsigned long long *scal) {
     const int32_t s = t.seg / NSEG_PER_RANK;
     const int lane = __lane_id();
     const int l = lane & (gsz - 1);
@@ -398,7 +427,10 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
         m = group_or_rt(m, gsz);
         r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
     }
-    if (t.v >= 0 && l == 0) __hip_atomic_store(&C[t.v], (int32_t)(base + r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t.v >= 0 && l == 0) {
+        __hip_atomic_store(&C[t.v], (int32_t)(base + r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        compact_store<CT>(S, t.v, (int32_t)(base + r));
+    }
 }
 
 // One sub-chunk of a split row (bin 2, whole wavefront).  The colors of lower
@@ -406,11 +438,11 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
 // wavefront's LDS words) go into the row's global bitmap; the sub-chunk that
 // ends last reads the bitmap, publishes the color and clears the slot for the
 // next pass.
-template <int U>
+template <int U, int CT>
 __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const int32_t *x,
                                     const int32_t *__restrict__ col, int32_t n,
-                                    int32_t *C, unsigned long long *lw, unsigned long long *hub_bits, int32_t *hub_cnt,
-                                    unsigned long long *scal) {
+                                    int32_t *C, void *S, unsigned long long *lw, unsigned long long *hub_bits,
+                                    int32_t *hub_cnt, unsigned long long *scal) {
     const int32_t s = t.seg / NSEG_PER_RANK;
     const int lane = __lane_id();
     const int32_t words = (s >> 6) + 1;  // lower ranks hold colors 1..s: words 0 .. s / 64
@@ -450,19 +482,20 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
         if (lane == 0) {
             atomicExch(&hub_cnt[t.slot], 0);
             __hip_atomic_store(&C[t.v], (int32_t)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            compact_store<CT>(S, t.v, (int32_t)r);
         }
     }
 }
 
 #define WALK_TAB 1536  // segment tables of up to WALK_TAB segments (512 classes) live in LDS
 
-template <int G, bool LDS_TAB, bool FULL>
+template <int G, bool LDS_TAB, bool FULL, int CT>
 __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, int32_t nseg,
                                           const int2 *__restrict__ rows, const int32_t *__restrict__ col,
                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
                                           const int32_t *__restrict__ hsub, const int32_t *__restrict__ sbase,
                                           int32_t split_len, unsigned long long *hub_bits, int32_t *hub_cnt,
-                                          unsigned long long *scal, int32_t xcd, unsigned long long *lw) {
+                                          unsigned long long *scal, int32_t xcd, unsigned long long *lw, void *S) {
     constexpr int U = 32 / G > 4 ? 32 / G : 4;
     const int lane = __lane_id();
     const int wpb = WALK_BLOCK / 64;
@@ -541,14 +574,27 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             w[u] = ok ? wl : -1;
         }
     };
+    // stage C: neighbor colors (from the compact copy when there is one)
+    auto gather_c = [&](const int32_t *w, int32_t *x) {
+        if (CT == 0) {
+            gather<U>(w, x, C, n);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const bool ok = (uint32_t)w[u] < (uint32_t)n;
+                const int32_t xl = compact_load<CT>(S, ok ? w[u] : 0);
+                x[u] = ok ? xl : 0;
+            }
+        }
+    };
     // stage D: wait for lower ranks, First Fit, publish
     auto finish = [&](const WalkChunk &t, const int32_t *w, const int32_t *x) {
         const int b = t.seg % NSEG_PER_RANK;
         const int32_t s = t.seg / NSEG_PER_RANK;
-        if (!FULL) finish_row<U, false>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
-        else if (b == 2) finish_split<U>(t, w, x, col, n, C, lw, hub_bits, hub_cnt, scal);
-        else if (s < 64) finish_row<U, false>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
-        else finish_row<U, true>(t, w, x, b ? 64 : G, col, n, C, lw, scal);
+        if (!FULL) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
+        else if (b == 2) finish_split<U, CT>(t, w, x, col, n, C, S, lw, hub_bits, hub_cnt, scal);
+        else if (s < 64) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
+        else finish_row<U, true, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
     };
 
     // Software pipeline, one stage per iteration: chunk i+3's vertex and row
@@ -564,11 +610,11 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     load_chunk(c2);
     load_ids(c0, w0);
     load_ids(c1, w1);
-    gather<U>(w0, x0, C, n);
+    gather_c(w0, x0);
     while (c0.seg < nseg) {
         load_chunk(c3);                                  // A: chunk i+3
         if (c2.seg < nseg) load_ids(c2, w2);             // B: chunk i+2
-        if (c1.seg < nseg) gather<U>(w1, x1, C, n);      // C: chunk i+1
+        if (c1.seg < nseg) gather_c(w1, x1);             // C: chunk i+1
         finish(c0, w0, x0);                              // D: chunk i
         c0 = c1;
         c1 = c2;
@@ -604,7 +650,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
                                                           const int32_t *__restrict__ hsub,
                                                           const int32_t *__restrict__ sbase, int32_t split_len,
                                                           unsigned long long *hub_bits, int32_t *hub_cnt,
-                                                          unsigned long long *scal, int32_t xcd, int32_t check_resident) {
+                                                          unsigned long long *scal, int32_t xcd, int32_t check_resident,
+                                                          void *S) {
     __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
     __shared__ unsigned long long lmask[WALK_BLOCK];  // per wavefront: 64 mask words for colors above 64
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
@@ -631,11 +678,15 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
         // loads in flight, so looking up the next chunk never drains the pipeline
         for (int32_t i = threadIdx.x; i <= nseg; i += WALK_BLOCK) { t_off[i] = off[i]; t_coff[i] = coff[i]; }
         __syncthreads();
-        walk_body<G, true, FULL>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt, scal,
-                           xcd, lw);
+        if (k <= CT_MAX_K1)
+            walk_body<G, true, FULL, 1>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
+                                        hub_cnt, scal, xcd, lw, S);
+        else
+            walk_body<G, true, FULL, 2>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
+                                        hub_cnt, scal, xcd, lw, S);
     } else {
-        walk_body<G, false, FULL>(off, coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt, scal,
-                            xcd, lw);
+        walk_body<G, false, FULL, 0>(off, coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt,
+                                     scal, xcd, lw, S);
     }
 }
 
@@ -654,7 +705,7 @@ __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__re
 
 typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const int32_t *, const int32_t *,
                         const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
-                        unsigned long long *, int32_t, int32_t);
+                        unsigned long long *, int32_t, int32_t, void *);
 
 template <bool FULL>
 static walk_fn walk_kernel_t(int G) {
@@ -671,47 +722,12 @@ static walk_fn walk_kernel_t(int G) {
 
 static walk_fn walk_kernel(int G, bool full) { return full ? walk_kernel_t<true>(G) : walk_kernel_t<false>(G); }
 
-__global__ void k_max_degree(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, unsigned long long *scal) {
-    __shared__ int32_t lds[32];
-    int32_t mx = 0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        int32_t e0, e1;
-        row_range(rp, (int32_t)v, nnz, e0, e1);
-        mx = max(mx, e1 - e0);
-    }
-    const int32_t bm = block_max_i32(mx, lds);
-    if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXDEG], bm);
-}
-
-// Longest row of g, computed once per graph (keyed by its arrays and sizes;
-// it only picks the walk variant, every variant colors any graph correctly).
-static gc_status graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out) {
-    if (ctx->deg_key_rp == g->row_ptr && ctx->deg_key_col == g->col_idx && ctx->deg_key_n == g->n &&
-        ctx->deg_key_nnz == g->nnz) {
-        *out = ctx->deg_max;
-        return GC_OK;
-    }
-    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXDEG, 0, 8, s));
-    const int grid = gc_grid(ctx, g->n, 256) < 2 * ctx->num_cu ? gc_grid(ctx, g->n, 256) : 2 * ctx->num_cu;
-    k_max_degree<<<grid, 256, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
-    GC_LAUNCHED();
-    gc_status st = gc_sync_scalars(ctx, s);
-    if (st) return st;
-    ctx->deg_max = (int32_t)ctx->hscal[S_MAXDEG];
-    ctx->deg_key_rp = g->row_ptr;
-    ctx->deg_key_col = g->col_idx;
-    ctx->deg_key_n = g->n;
-    ctx->deg_key_nnz = g->nnz;
-    *out = ctx->deg_max;
-    return GC_OK;
-}
-
 // full: the variant with split rows and LDS mask words (rows of 64 or more
 // entries); the narrow one keeps only a 64-color register window (further
 // windows rescan the row) and lets the first sub-chunk of a split row scan the
 // whole row.
 static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
-    const int G = ctx->tune.group;
+    const int G = gc_walk_group(ctx, full);
     walk_fn f = walk_kernel(G, full);
     const int variant = 2 * G + (full ? 1 : 0);
     // the walk reads col[0] unconditionally (masked afterwards): give it one valid word when the graph has no edges
@@ -735,7 +751,8 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
             GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
             GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
             hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C, ctx->list, ctx->off,
-                               ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2);
+                               ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2,
+                               ctx->shadow);
             GC_LAUNCHED();
             gc_status st = gc_sync_scalars(ctx, s);
             if (st) return st;
@@ -756,7 +773,8 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     if (ctx->tune.check_resident) GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
     GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C,
                                               ctx->list, ctx->off, ctx->coff, ctx->hsub, ctx->sbase, split_len,
-                                              hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident));
+                                              hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident,
+                                              ctx->shadow));
     GC_LAUNCHED();
     return GC_OK;
 }
@@ -776,17 +794,17 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         return GC_OK;
     }
     const int block = 256;
-    const int G = ctx->tune.group;
     const int32_t deg_wave = ctx->tune.deg_wave;
     // the split bin exists in the persistent walk only
     bool full = false;
     if (ctx->tune.walk_mode == 0) {
         int32_t maxdeg = 0;
-        status = graph_max_degree(ctx, g, s, &maxdeg);
+        status = gc_graph_max_degree(ctx, g, s, &maxdeg);
         if (status) return status;
         full = maxdeg >= 64;
     }
     const int32_t deg_split = full ? ctx->tune.deg_split : 0;
+    const int G = gc_walk_group(ctx, full);  // lanes per vertex of the walk; sets the chunk size of bin 0
     const int32_t split_len = ctx->tune.split_len;
     const int32_t hub_max_rank = 64 * ctx->tune.hub_words - 1;
     if (deg_split > 0) {
@@ -806,7 +824,7 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
                                 ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->scal));
     GC_LAUNCHED();
     const int64_t tiles = ((int64_t)n + block * SCATTER_ITEMS - 1) / (block * SCATTER_ITEMS);
-    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, g->row_ptr, g->nnz,
+    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, ctx->shadow, g->row_ptr, g->nnz,
                                                                          deg_wave, deg_split, hub_max_rank, ctx->ccap,
                                                                          ctx->rank,
                                                                          ctx->cursor, ctx->list, ctx->rows, ctx->scal));

@@ -66,7 +66,8 @@ def test_full_size_workload_other_tunings(gc):
     """The mesh at full size under non-default launch shapes (same colors)."""
     ref = GOLD["workloads"]["mesh128"]
     g = eval(ref["graph"])
-    for t in (dict(group=8, xcd_chunks=1), dict(group=16, deg_wave=8), dict(walk_mode=1)):
+    for t in (dict(group=8, xcd_chunks=1), dict(group=16, walk_group=16, deg_wave=8), dict(walk_group=4),
+              dict(walk_mode=1)):
         print(f"[full-size] mesh128 tuning {t}", flush=True)
         ctx = gc.Context(g.n, g.nnz)
         ctx.set_tuning(**t)

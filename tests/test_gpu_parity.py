@@ -178,7 +178,8 @@ def test_many_small_random_graphs(gc):
 
 
 TUNINGS = [
-    dict(group=1), dict(group=2), dict(group=4), dict(group=16), dict(group=32), dict(group=64),
+    dict(group=1, walk_group=1), dict(group=2, walk_group=2), dict(group=4, walk_group=4), dict(group=16, walk_group=16),
+    dict(group=32, walk_group=32), dict(group=64, walk_group=64), dict(group=8, walk_group=0), dict(group=2, walk_group=16),
     dict(deg_wave=0), dict(deg_wave=4), dict(deg_wave=1 << 30),
     dict(walk_mode=1), dict(walk_mode=1, deg_wave=3),
     dict(xcd_chunks=1), dict(xcd_chunks=1, group=4, deg_wave=16),
