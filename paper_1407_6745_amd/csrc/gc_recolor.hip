@@ -38,6 +38,7 @@
 
 #define HIST_LDS 4096       // colors below this use the workgroup-private histogram
 #define HIST_BITS 12
+#define HIST_ITEMS 8        // vertices per thread of one histogram tile
 #define PERM_THREADS 1024
 #define SCATTER_BINS 1024   // segments below this reserve list ranges once per workgroup
 #define SCATTER_ITEMS 4
@@ -63,33 +64,49 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     __syncthreads();
     int32_t mx = 0;
     bool bad = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int64_t v = base + threadIdx.x;
-        int32_t c = 0, bin = 0, d = 0;
-        bool valid = false;
-        if (v < n) {
-            c = Cin[v];
-            mx = max(mx, c);
-            if (c < 1 || c > ccap) bad = true;
-            else {
-                valid = true;
-                int32_t e0, e1;
-                row_range(rp, (int32_t)v, nnz, e0, e1);
-                d = e1 - e0;
-                bin = row_bin(d, deg_wave, deg_split);
+    // tiles of HIST_ITEMS * blockDim vertices; every load of a tile is issued before any is used
+    const int64_t tile_sz = (int64_t)HIST_ITEMS * blockDim.x;
+    for (int64_t tile = (int64_t)blockIdx.x * tile_sz; tile < n; tile += (int64_t)gridDim.x * tile_sz) {
+        int32_t cs[HIST_ITEMS], a0[HIST_ITEMS], a1[HIST_ITEMS];
+#pragma unroll
+        for (int it = 0; it < HIST_ITEMS; it++) {
+            const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
+            const bool in = v < n;
+            const int64_t vv = in ? v : 0;
+            cs[it] = in ? Cin[vv] : 0;
+            a0[it] = rp[vv];
+            a1[it] = rp[vv + 1];
+        }
+#pragma unroll
+        for (int it = 0; it < HIST_ITEMS; it++) {
+            const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
+            const int32_t c = cs[it];
+            int32_t bin = 0, d = 0;
+            bool valid = false;
+            if (v < n) {
+                mx = max(mx, c);
+                if (c < 1 || c > ccap) bad = true;
+                else {
+                    valid = true;
+                    // row_range's clamping, on the preloaded row bounds
+                    int64_t e0 = a0[it], e1 = a1[it];
+                    e0 = e0 < 0 ? 0 : (e0 > nnz ? nnz : e0);
+                    e1 = e1 < e0 ? e0 : (e1 > nnz ? nnz : e1);
+                    d = (int32_t)(e1 - e0);
+                    bin = row_bin(d, deg_wave, deg_split);
+                }
             }
-        }
-        const bool in_lds = valid && c < HIST_LDS;
-        (void)wave_match_reserve_bits(h, c, in_lds, HIST_BITS);
-        (void)wave_match_reserve_bits(hw, c, in_lds && bin == 1, HIST_BITS);
-        if (valid && !in_lds) {
-            atomicAdd(&hist[c], 1);
-            if (bin == 1) atomicAdd(&histw[c], 1);
-        }
-        if (valid && bin == 2) {  // rare: long rows
-            atomicAdd(&hist_s[c], 1);
-            atomicAdd(&hist_sc[c], (d + split_len - 1) / split_len);
+            const bool in_lds = valid && c < HIST_LDS;
+            (void)wave_match_reserve_bits(h, c, in_lds, HIST_BITS);
+            (void)wave_match_reserve_bits(hw, c, in_lds && bin == 1, HIST_BITS);
+            if (valid && !in_lds) {
+                atomicAdd(&hist[c], 1);
+                if (bin == 1) atomicAdd(&histw[c], 1);
+            }
+            if (valid && bin == 2) {  // rare: long rows
+                atomicAdd(&hist_s[c], 1);
+                atomicAdd(&hist_sc[c], (d + split_len - 1) / split_len);
+            }
         }
     }
     const int32_t bmax = block_max_i32(mx, lds);  // synchronizes the block
@@ -195,6 +212,22 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S,
     const int64_t tile = (int64_t)blockIdx.x * blockDim.x * SCATTER_ITEMS;
     int32_t sg[SCATTER_ITEMS], loc[SCATTER_ITEMS];
     int2 rw[SCATTER_ITEMS];
+    // every load of the tile first (colors, row bounds, then ranks), so that
+    // the stores below (Cout may be Cin) do not order them one item at a time
+    int32_t cs[SCATTER_ITEMS], a0[SCATTER_ITEMS], a1[SCATTER_ITEMS], rk[SCATTER_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SCATTER_ITEMS; it++) {
+        const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
+        const int64_t vv = v < n ? v : 0;
+        cs[it] = Cin[vv];
+        a0[it] = rp[vv];
+        a1[it] = rp[vv + 1];
+    }
+#pragma unroll
+    for (int it = 0; it < SCATTER_ITEMS; it++) {
+        const bool ok = cs[it] >= 1 && cs[it] <= ccap;
+        rk[it] = rank[ok ? cs[it] : 0];
+    }
 #pragma unroll
     for (int it = 0; it < SCATTER_ITEMS; it++) {
         const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
@@ -203,14 +236,15 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S,
         rw[it] = make_int2(0, 0);
         int32_t g = -1;
         if (v < n) {
-            const int32_t c = Cin[v];
+            const int32_t c = cs[it];
             if (c >= 1 && c <= ccap && k > 0) {
-                int32_t s = rank[c];
+                int32_t s = rk[it];
                 if ((uint32_t)s >= (uint32_t)k) s = k - 1;  // unreachable for a ranked color; keeps indices in bounds
-                int32_t e0, e1;
-                row_range(rp, (int32_t)v, nnz, e0, e1);
-                rw[it] = make_int2(e0, e1);
-                int b = row_bin(e1 - e0, deg_wave, deg_split);
+                int64_t e0 = a0[it], e1 = a1[it];  // row_range's clamping on the preloaded bounds
+                e0 = e0 < 0 ? 0 : (e0 > nnz ? nnz : e0);
+                e1 = e1 < e0 ? e0 : (e1 > nnz ? nnz : e1);
+                rw[it] = make_int2((int32_t)e0, (int32_t)e1);
+                int b = row_bin((int32_t)(e1 - e0), deg_wave, deg_split);
                 if (b == 2 && s > hub_max_rank) b = 1;
                 g = NSEG_PER_RANK * s + b;
                 sg[it] = g;
@@ -811,7 +845,8 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         status = gc_ensure_hub_slots(ctx, g->nnz, deg_split, s);
         if (status) return status;
     }
-    const int hist_grid = gc_grid(ctx, n, block) < 2 * ctx->num_cu ? gc_grid(ctx, n, block) : 2 * ctx->num_cu;
+    const int64_t hist_tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
+    const int hist_grid = (int)(hist_tiles < 16 * ctx->num_cu ? hist_tiles : 16 * ctx->num_cu);
     GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8, s));
     GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
     GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, deg_split,
