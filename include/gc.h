@@ -145,12 +145,13 @@ gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap);
 
 /*
  * Kernel timing (profiling aid).  When enabled, the library records a pair of
- * HIP events on the launch stream around every kernel it launches and sums
- * the elapsed times per kernel kind.  gc_ctx_get_timing synchronizes the
- * device, fills launches[kind] and ms[kind] for kind < min(cap,
- * GC_KERNEL_KINDS) and returns GC_OK.  Enabling (or re-enabling) clears the
- * sums.  Timing adds event records between launches and should stay off
- * outside measurements.
+ * HIP events on the launch stream around every kernel of the selected kinds
+ * and sums the elapsed times per kind.  enable: 0 = off, -1 = every kind,
+ * otherwise a bit mask (bit k selects kind k).  gc_ctx_get_timing
+ * synchronizes the device, fills launches[kind] and ms[kind] for kind <
+ * min(cap, GC_KERNEL_KINDS) and returns GC_OK.  Enabling (or re-enabling)
+ * clears the sums.  Timing adds event records between launches; select only
+ * the kinds a measurement needs.
  */
 enum {
     GC_K_ROUND0 = 0, GC_K_ASSIGN = 1, GC_K_DETECT = 2, GC_K_HIST = 3, GC_K_ORDER = 4, GC_K_SCATTER = 5,

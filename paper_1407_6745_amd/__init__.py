@@ -168,9 +168,16 @@ class Context:
         self.check(lib().gc_ctx_get_tuning(self.handle, ctypes.byref(t)), "gc_ctx_get_tuning")
         return {f: getattr(t, f) for f in TUNING_FIELDS}
 
-    def set_timing(self, enable: bool):
-        """Turn per-kernel HIP-event timing on (clearing the sums) or off."""
-        self.check(lib().gc_ctx_set_timing(self.handle, 1 if enable else 0), "gc_ctx_set_timing")
+    def set_timing(self, enable: bool, kinds=None):
+        """Turn per-kernel HIP-event timing on (clearing the sums) or off;
+        `kinds` limits it to those kernel kinds (names of KERNEL_KINDS)."""
+        if not enable:
+            arg = 0
+        elif kinds is None:
+            arg = -1
+        else:
+            arg = sum(1 << KERNEL_KINDS.index(k) for k in kinds)
+        self.check(lib().gc_ctx_set_timing(self.handle, arg), "gc_ctx_set_timing")
 
     def timing(self) -> dict:
         """{kind: (launches, total ms)} since timing was enabled (synchronizes the device)."""

@@ -126,6 +126,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
 #define TIMER_PAIRS 4096
 
 struct gc_timer {
+    unsigned mask;  // kernel kinds timed (bit k: kind k)
     hipEvent_t ev[2 * TIMER_PAIRS];
     int kind[TIMER_PAIRS];
     int pending;
@@ -155,7 +156,7 @@ static void timer_free(gc_timer *t) {
 
 void gc_time_begin(gc_ctx *ctx, int kind, hipStream_t s) {
     gc_timer *t = ctx->timer;
-    if (!t) return;
+    if (!t || !((t->mask >> kind) & 1u)) return;
     if (t->pending == TIMER_PAIRS) timer_flush(t);
     t->kind[t->pending] = kind;
     (void)hipEventRecord(t->ev[2 * t->pending], s);
@@ -188,6 +189,7 @@ extern "C" gc_status gc_ctx_set_timing(gc_ctx *ctx, int enable) {
         }
     }
     t->open = -1;
+    t->mask = enable < 0 ? ~0u : (unsigned)enable;
     ctx->timer = t;
     return GC_OK;
 }
