@@ -263,6 +263,32 @@ gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int
 /* seed_g of graph g in a batch (host helper, same formula as above). */
 uint64_t gc_batch_graph_seed(uint64_t base_seed, int32_t g);
 
+/*
+ * Class-order schedules over recoloring iterations (section 4.2.1, the
+ * sequential study of random permutations).  Iteration t counts from 1.
+ *   GC_SCHED_FIXED:       `base` at every iteration;
+ *   GC_SCHED_ND_RAND_X:   RAND when t is a multiple of x (x >= 1), ND otherwise;
+ *   GC_SCHED_ND_RAND_POW2: RAND when t is a power of two >= 2, ND otherwise.
+ * gc_schedule_perm returns the gc_perm of iteration t, or -1 for a bad
+ * argument (unknown schedule, t < 1, base outside gc_perm, x < 1 for
+ * GC_SCHED_ND_RAND_X).  Host only; pass t - 1 as gc_recolor's `pass`.
+ */
+typedef enum gc_schedule { GC_SCHED_FIXED = 0, GC_SCHED_ND_RAND_X = 1, GC_SCHED_ND_RAND_POW2 = 2 } gc_schedule;
+int32_t gc_schedule_perm(int32_t schedule, int32_t base, int32_t x, int32_t t);
+
+/*
+ * Parameter presets (section 4.3): GC_PRESET_SPEED = First Fit initial
+ * coloring, no recoloring; GC_PRESET_QUALITY = Random-X Fit with X = 5 and
+ * one recoloring pass in ND order (pass index 0).  The paper's presets also
+ * fix a processor-local vertex order ("internal first"), a distributed-memory
+ * notion with no counterpart in the single-GPU rounds.  Same arguments,
+ * synchronization and errors as gc_init_color; st (optional) receives the
+ * initial coloring's rounds and the final color counts.
+ */
+typedef enum gc_preset { GC_PRESET_SPEED = 0, GC_PRESET_QUALITY = 1 } gc_preset;
+gc_status gc_color_preset(gc_ctx *ctx, const gc_csr *g, int32_t preset, uint64_t seed, int32_t *colors, gc_stats *st,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

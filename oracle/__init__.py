@@ -72,6 +72,7 @@ def _load():
         "orc_class_order": (i32, [i32, i64p, i32, u64, i32, i32p]),
         "orc_recolor": (ctypes.c_int, [i32, i32p, i32p, i32, u64, i32, i32p, i32p, i32p, i32p,
                                        ctypes.POINTER(Stats)]),
+        "orc_arc_recolor": (ctypes.c_int, [i32, i32p, i32p, i32, u64, i32, i32p, i32p, i32p, ctypes.POINTER(Stats)]),
         "orc_schedule_perm": (i32, [i32, i32, i32, i32]),
         "orc_chromatic": (i32, [i32, i32p, i32p]),
     }
@@ -231,6 +232,23 @@ def recolor(g, colors, perm=PERM_REVERSE, seed=1, pass_=0) -> RecolorResult:
     if rc:
         return RecolorResult(rc, None, None, None)
     return RecolorResult(rc, c_new[:g.n], st.as_dict(), pi[:k.value].copy())
+
+
+def arc_recolor(g, colors, perm=PERM_REVERSE, seed=1, pass_=0) -> RecolorResult:
+    """Asynchronous recoloring aRC: speculative First Fit rounds in which the
+    old class order decides conflicts (section 3)."""
+    rp, col = _csr(g)
+    c_old = np.ascontiguousarray(colors, dtype=np.int32)
+    if c_old.size == 0:
+        c_old = np.zeros(1, np.int32)
+    c_new = np.zeros(max(g.n, 1), np.int32)
+    rounds = ctypes.c_int32()
+    st = Stats()
+    rc = _load().orc_arc_recolor(g.n, _p32(rp), _p32(col), perm, seed, pass_, _p32(c_old), _p32(c_new),
+                                 ctypes.byref(rounds), ctypes.byref(st))
+    if rc:
+        return RecolorResult(rc, None, None, None)
+    return RecolorResult(rc, c_new[:g.n], st.as_dict(), None)
 
 
 def schedule_perm(kind, base, x, t) -> int:

@@ -409,6 +409,96 @@ int orc_recolor(int32_t n, const int32_t *rp, const int32_t *col, int32_t perm, 
 }
 
 /*
+ * Asynchronous recolouring aRC (section 3): the vertex-visit order taken from
+ * the previous colouring (classes in the order pi) drives a second
+ * speculative parallel colouring with conflict-resolution rounds.  Reading
+ * for one device and Jacobi rounds: the visit order acts as the conflict
+ * priority, i.e. of two neighbours with the same tentative colour the one
+ * whose old class comes earlier in pi keeps it (two neighbours always have
+ * different old classes, so this decides every conflict).  Every round,
+ * each vertex still uncoloured takes First Fit over the colours committed
+ * before the round; winners commit, losers go to the next round.
+ *
+ * c_old as for orc_recolor.  rounds_out (may be NULL) receives the rounds.
+ */
+int orc_arc_recolor(int32_t n, const int32_t *rp, const int32_t *col, int32_t perm, uint64_t seed, int32_t pass,
+                    const int32_t *c_old, int32_t *c_new, int32_t *rounds_out, orc_stats *st) {
+    if (n < 0 || perm < 0 || perm > 3) return ORC_ERR_ARG;
+    int32_t maxc = 0;
+    for (int32_t v = 0; v < n; v++) {
+        if (c_old[v] <= 0) return ORC_ERR_COLORING;
+        if (c_old[v] > maxc) maxc = c_old[v];
+    }
+    int64_t conflicts = 0, unc = 0;
+    orc_validate(n, rp, col, c_old, &conflicts, &unc);
+    if (conflicts) return ORC_ERR_COLORING;
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; v++)
+        if (rp[v + 1] - rp[v] > maxd) maxd = rp[v + 1] - rp[v];
+    int64_t *size = (int64_t *)calloc((size_t)maxc + 1, sizeof(int64_t));
+    int32_t *pi = (int32_t *)malloc(((size_t)maxc + 1) * sizeof(int32_t));
+    int32_t *rank = (int32_t *)malloc(((size_t)maxc + 1) * sizeof(int32_t));
+    int32_t *T = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *W = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *L = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *round_of = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int64_t *forbidden = (int64_t *)malloc(((size_t)maxd + 2) * sizeof(int64_t));
+    uint8_t *lost = (uint8_t *)malloc((size_t)n + 1);
+    if (!size || !pi || !rank || !T || !W || !L || !round_of || !forbidden || !lost) {
+        free(size); free(pi); free(rank); free(T); free(W); free(L); free(round_of); free(forbidden); free(lost);
+        return ORC_ERR_OOM;
+    }
+    for (int32_t v = 0; v < n; v++) size[c_old[v]]++;
+    int32_t k = orc_class_order(maxc, size, perm, seed, pass, pi);
+    for (int32_t s = 0; s < k; s++) rank[pi[s]] = s;
+    for (int32_t i = 0; i < maxd + 2; i++) forbidden[i] = -1;
+    for (int32_t v = 0; v < n; v++) { c_new[v] = 0; W[v] = v; round_of[v] = -1; }
+    int32_t nW = n, r = 0;
+    int64_t stamp = 0;
+    while (nW > 0) {
+        /* First Fit from the colours committed before the round */
+        for (int32_t i = 0; i < nW; i++) {
+            int32_t v = W[i];
+            stamp++;
+            for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+                int32_t c = c_new[col[e]];
+                if (c > 0 && c <= maxd + 1) forbidden[c] = stamp;
+            }
+            int32_t c = 1;
+            while (forbidden[c] == stamp) c++;
+            T[v] = c;
+            round_of[v] = r;
+        }
+        /* v loses to a neighbour of this round with the same colour and an earlier old class */
+        int32_t nL = 0;
+        for (int32_t i = 0; i < nW; i++) {
+            int32_t v = W[i];
+            lost[i] = 0;
+            for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+                int32_t w = col[e];
+                if (round_of[w] == r && T[w] == T[v] && rank[c_old[w]] < rank[c_old[v]]) { lost[i] = 1; break; }
+            }
+        }
+        for (int32_t i = 0; i < nW; i++) {
+            int32_t v = W[i];
+            if (lost[i]) L[nL++] = v;
+            else c_new[v] = T[v];
+        }
+        int32_t *tmp = W; W = L; L = tmp;
+        nW = nL;
+        r++;
+    }
+    if (rounds_out) *rounds_out = r;
+    if (st) {
+        st->rounds = r;
+        st->losers_total = 0;
+        orc_count(n, c_new, &st->num_colors, &st->max_color);
+    }
+    free(size); free(pi); free(rank); free(T); free(W); free(L); free(round_of); free(forbidden); free(lost);
+    return ORC_OK;
+}
+
+/*
  * Hybrid class-order schedules (section 4.2.1): iteration t counts from 1.
  *   kind 0: the fixed permutation `base` at every iteration;
  *   kind 1 (ND-RAND%x): RAND when t is a multiple of x, ND otherwise;

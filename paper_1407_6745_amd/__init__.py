@@ -82,6 +82,9 @@ _SIGS = {
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_batch_graph_seed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32]),
+    "gc_schedule_perm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "gc_color_preset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_ctx_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "gc_ctx_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
     "gc_ctx_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
@@ -362,14 +365,33 @@ def batch_color(vtx_off, edge_off, row_ptr, col_idx, select=RANDOM_X, X=4, perm=
     return out, per_graph
 
 
+SCHED_FIXED, SCHED_ND_RAND_X, SCHED_ND_RAND_POW2 = 0, 1, 2
+PRESET_SPEED, PRESET_QUALITY = 0, 1
+
+
 def schedule_perm(kind: int, base: int, x: int, t: int) -> int:
-    """Class order of iteration t (1-based) under a hybrid schedule:
+    """Class order of iteration t (1-based) under a hybrid schedule (gc_schedule_perm):
     kind 0 = `base` every time; 1 = ND-RAND%x; 2 = ND-RAND%2^i (RAND at t = 2, 4, 8, ...)."""
-    if kind == 1:
-        return PERM_RANDOM if x > 0 and t % x == 0 else PERM_NONDEC
-    if kind == 2:
-        return PERM_RANDOM if t >= 2 and (t & (t - 1)) == 0 else PERM_NONDEC
-    return base
+    p = int(lib().gc_schedule_perm(kind, base, x, t))
+    if p < 0:
+        raise ValueError(f"bad schedule arguments ({kind}, {base}, {x}, {t})")
+    return p
+
+
+def color_preset(row_ptr, col_idx, preset=PRESET_QUALITY, seed=1, out=None, stats=True, ctx: Context | None = None,
+                 stream=None):
+    """The paper's "speed" / "quality" parameter presets (gc_color_preset)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.int32, device=row_ptr.device)
+    _check_i32_dev(out, "out", g.n)
+    st = StatsArgs() if stats else None
+    rc = lib().gc_color_preset(ctx.handle, ctypes.byref(g), preset, seed, out.data_ptr() if g.n else None,
+                               ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    ctx.check(rc, "gc_color_preset")
+    return out, (_stats_dict(st) if st is not None else None)
 
 
 def color(row_ptr, col_idx, select=RANDOM_X, X=4, seed=1, perms=(PERM_REVERSE,), ctx=None, stream=None, stats=True):

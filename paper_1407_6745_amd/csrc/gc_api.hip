@@ -580,3 +580,33 @@ gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32
     return GC_OK;
 }
 
+
+extern "C" int32_t gc_schedule_perm(int32_t schedule, int32_t base, int32_t x, int32_t t) {
+    if (t < 1) return -1;
+    switch (schedule) {
+        case GC_SCHED_FIXED: return (base >= GC_PERM_REVERSE && base <= GC_PERM_RANDOM) ? base : -1;
+        case GC_SCHED_ND_RAND_X:
+            if (x < 1) return -1;
+            return t % x == 0 ? GC_PERM_RANDOM : GC_PERM_NONDEC;
+        case GC_SCHED_ND_RAND_POW2: return (t >= 2 && (t & (t - 1)) == 0) ? GC_PERM_RANDOM : GC_PERM_NONDEC;
+        default: return -1;
+    }
+}
+
+extern "C" gc_status gc_color_preset(gc_ctx *ctx, const gc_csr *g, int32_t preset, uint64_t seed, int32_t *colors,
+                                     gc_stats *st, void *stream) {
+    if (!ctx) return GC_ERR_ARG;
+    if (preset == GC_PRESET_SPEED) return gc_init_color(ctx, g, GC_FIRST_FIT, 1, seed, 0, 0, colors, st, stream);
+    if (preset != GC_PRESET_QUALITY) return gc_fail(ctx, GC_ERR_ARG, "unknown preset %d", preset);
+    gc_status s = gc_init_color(ctx, g, GC_RANDOM_X, 5, seed, 0, 0, colors, st, stream);
+    if (s) return s;
+    gc_stats rs{};
+    s = gc_recolor(ctx, g, GC_PERM_NONDEC, seed, 0, colors, colors, st ? &rs : nullptr, stream);
+    if (s) return s;
+    if (st) {
+        st->num_colors = rs.num_colors;
+        st->max_color = rs.max_color;
+        st->k_classes = rs.k_classes;
+    }
+    return GC_OK;
+}

@@ -113,3 +113,18 @@ def test_server_create_rejects_bad_config_without_gpu():
         cfg = gc.ServerConfigArgs(0, 2, 1 << 20, 10, 10)
         rc = gc.lib().gc_server_create(ctypes.byref(cfg), ctypes.byref(h))
         assert rc in (gc.ERR_DEVICE, gc.ERR_OOM) and not h.value
+
+
+def test_schedule_perm_matches_oracle():
+    """The library's schedule helper against the oracle's definition (section 4.2.1)."""
+    import paper_1407_6745_amd as gc
+
+    for t in range(1, 70):
+        for x in range(1, 13):
+            assert gc.schedule_perm(gc.SCHED_ND_RAND_X, 0, x, t) == oracle.schedule_perm(1, 0, x, t)
+        assert gc.schedule_perm(gc.SCHED_ND_RAND_POW2, 0, 0, t) == oracle.schedule_perm(2, 0, 0, t)
+        for base in range(4):
+            assert gc.schedule_perm(gc.SCHED_FIXED, base, 0, t) == oracle.schedule_perm(0, base, 0, t)
+    lib = gc.lib()
+    for bad in ((3, 0, 1, 1), (-1, 0, 1, 1), (0, 4, 0, 1), (0, 0, 0, 0), (1, 0, 0, 5)):
+        assert lib.gc_schedule_perm(*bad) == -1

@@ -302,3 +302,34 @@ def test_init_split_many_colors(gc):
     c, ref = _init_equal(gc, g, gc.FIRST_FIT, 1, 6, ctx=ctx)
     assert ref.stats["rounds"] == 300
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["er", "rmat", "mesh"])
+def test_presets(gc, name):
+    """"speed" = First Fit alone; "quality" = Random-X (X = 5) + one ND pass (section 4.3)."""
+    g = GRAPHS[name]()
+    rp, col = dev(g)
+    c, st = gc.color_preset(rp, col, gc.PRESET_SPEED, 13)
+    ref = oracle.init_color(g, oracle.FIRST_FIT, 1, 13)
+    assert np.array_equal(c.cpu().numpy(), ref.colors) and st["rounds"] == ref.stats["rounds"]
+    c, st = gc.color_preset(rp, col, gc.PRESET_QUALITY, 13)
+    ref = oracle.init_color(g, oracle.RANDOM_X, 5, 13)
+    exp = oracle.recolor(g, ref.colors, oracle.PERM_NONDEC, 13, 0)
+    assert np.array_equal(c.cpu().numpy(), exp.colors)
+    assert st["rounds"] == ref.stats["rounds"] and st["num_colors"] == exp.stats["num_colors"]
+
+
+@pytest.mark.parametrize("kind,x", [(1, 3), (2, 0)])
+def test_hybrid_schedules(gc, kind, x):
+    """ND-RAND%x and ND-RAND%2^i over 9 iterations against the oracle."""
+    g = GRAPHS["rgg"]()
+    rp, col = dev(g)
+    c0 = oracle.init_color(g, oracle.FIRST_FIT, 1, 21).colors
+    cur = torch.from_numpy(c0.copy()).cuda()
+    exp = c0
+    for t in range(1, 10):
+        perm = gc.schedule_perm(kind, 0, x, t)
+        assert perm == oracle.schedule_perm(kind, 0, x, t)
+        cur, _ = gc.recolor(rp, col, cur, perm, 21, t - 1, out=cur)
+        exp = oracle.recolor(g, exp, perm, 21, t - 1).colors
+        assert np.array_equal(cur.cpu().numpy(), exp), t

@@ -417,3 +417,62 @@ def test_schedules():
     assert [oracle.schedule_perm(1, 0, 5, t) for t in range(1, 11)] == [ND] * 4 + [RAND] + [ND] * 4 + [RAND]
     assert [oracle.schedule_perm(2, 0, 0, t) for t in range(1, 10)] == [ND, RAND, ND, RAND, ND, ND, ND, RAND, ND]
     assert oracle.schedule_perm(0, oracle.PERM_NONINC, 0, 3) == oracle.PERM_NONINC
+
+
+# ---- asynchronous recoloring aRC (section 3) ----
+
+def _ranks(colors, perm, seed, pass_):
+    sizes = np.bincount(np.asarray(colors), minlength=int(np.max(colors)) + 1)
+    pi = oracle.class_order(sizes, perm, seed, pass_)
+    return {int(c): s for s, c in enumerate(pi)}
+
+
+def test_arc_closed_forms():
+    """aRC gives rank + 1 when every vertex touches every lower class: K_n
+    from a one-class-per-vertex coloring (one vertex per round), the 3D mesh
+    from its parity coloring, a path from its 2-coloring (section 3; the
+    earlier old class wins every conflict)."""
+    rng = np.random.default_rng(4)
+    cases = [(gen.complete(9), (rng.permutation(9) + 1).astype(np.int32), 9),
+             (gen.mesh27(6), None, 8),
+             (gen.path(11), np.array([1 + (i & 1) for i in range(11)], np.int32), 2)]
+    for g, c0, rounds in cases:
+        if c0 is None:
+            c0 = oracle.greedy_seq(g)  # 1 + (x&1) + 2(y&1) + 4(z&1)
+        for perm, seed in ((oracle.PERM_REVERSE, 1), (oracle.PERM_NONINC, 1), (oracle.PERM_NONDEC, 1),
+                           (oracle.PERM_RANDOM, 7)):
+            r = oracle.arc_recolor(g, c0, perm, seed, 2)
+            rank = _ranks(c0, perm, seed, 2)
+            assert r.colors.tolist() == [rank[int(c)] + 1 for c in c0], (g.name, perm)
+            assert r.stats["rounds"] == rounds
+
+
+def test_arc_invariants():
+    """Proper, every vertex colored, First Fit's Grundy bound C(v) <= deg(v) + 1."""
+    for fam in range(len(FAMILIES)):
+        g = FAMILIES[fam]()
+        c0 = oracle.init_color(g, oracle.RANDOM_X, 3, 5).colors
+        deg = g.degrees
+        for perm in range(4):
+            r = oracle.arc_recolor(g, c0, perm, 5, 1)
+            assert r.status == 0
+            assert oracle.validate(g, r.colors) == (0, 0)
+            assert (r.colors <= deg + 1).all()
+
+
+def test_arc_first_class_keeps_color_one():
+    """Round 0 gives every vertex color 1 tentatively; a vertex of the first
+    class in the order has no earlier neighbor, so it keeps color 1."""
+    g = gen.er(300, 1500, 2)
+    c0 = oracle.init_color(g, oracle.FIRST_FIT, 1, 3).colors
+    for perm in range(4):
+        rank = _ranks(c0, perm, 3, 0)
+        first = [v for v in range(g.n) if rank[int(c0[v])] == 0]
+        r = oracle.arc_recolor(g, c0, perm, 3, 0)
+        assert all(r.colors[v] == 1 for v in first)
+
+
+def test_arc_rejects_bad_input():
+    g = gen.path(4)
+    assert oracle.arc_recolor(g, [1, 0, 1, 2]).status == oracle.ERR_COLORING
+    assert oracle.arc_recolor(g, [1, 1, 2, 1]).status == oracle.ERR_COLORING
