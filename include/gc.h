@@ -206,6 +206,21 @@ gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, 
                      const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
 
 /*
+ * Asynchronous recoloring aRC (section 3): the classes of colors_in, in the
+ * order `perm` picks (as gc_recolor), give each vertex a rank, and a second
+ * speculative coloring runs in rounds with First Fit where, of two neighbors
+ * with the same tentative color, the one of the earlier class keeps it
+ * (the vertex-visit order taken from the previous coloring, read as the
+ * conflict priority of the Jacobi rounds).  Trades color count against the
+ * class-by-class dependency chain of gc_recolor.  colors_in must be a proper
+ * coloring with colors in [1, n + GC_MAX_X] (GC_ERR_COLORING otherwise);
+ * colors_out may equal colors_in.  Synchronizes like gc_init_color;
+ * st->rounds counts its rounds, st->k_classes the input classes.
+ */
+gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                         const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
+
+/*
  * conflict_edges: adjacency entries (u, w) with u < w and colors[u] ==
  * colors[w] > 0 (each undirected edge once); uncolored: vertices with
  * colors[v] <= 0.  Host outputs; synchronizes.  Either pointer may be NULL.

@@ -82,6 +82,8 @@ _SIGS = {
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_batch_graph_seed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32]),
+    "gc_arc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_schedule_perm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "gc_color_preset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -291,6 +293,24 @@ def recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=No
                           out.data_ptr() if g.n else None, ctypes.byref(st) if st is not None else None,
                           _stream_ptr(stream))
     ctx.check(rc, "gc_recolor")
+    return out, (_stats_dict(st) if st is not None else None)
+
+
+def arc_recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,
+                ctx: Context | None = None, stream=None):
+    """Asynchronous recoloring (aRC); `out` may be `colors`.  Returns (colors, stats or None)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty_like(colors)
+    _check_i32_dev(out, "out", g.n)
+    st = StatsArgs() if stats else None
+    rc = lib().gc_arc_recolor(ctx.handle, ctypes.byref(g), perm, seed, pass_, colors.data_ptr() if g.n else None,
+                              out.data_ptr() if g.n else None, ctypes.byref(st) if st is not None else None,
+                              _stream_ptr(stream))
+    ctx.check(rc, "gc_arc_recolor")
     return out, (_stats_dict(st) if st is not None else None)
 
 

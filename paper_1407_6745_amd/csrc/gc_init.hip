@@ -33,13 +33,20 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
     return randx ? (int32_t)gc_pick(s_color, w, X) + 1 : 1;
 }
 
+// Conflict priority of v in a round (larger wins): the hash of (seed, v,
+// round), or, when a per-vertex class rank is given (asynchronous
+// recoloring), the rank reversed so that the earlier class wins.
+__device__ inline uint32_t round_prio(const int32_t *prank, uint32_t s_prio, int32_t v) {
+    return prank ? ~(uint32_t)prank[v] : gc_prio(s_prio, v);
+}
+
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
 template <int G, bool ROUND0, int UNR = GC_UNROLL>
 __device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
                                    const int32_t *C, int32_t n, uint32_t s_prio, uint32_t s_color, uint32_t X,
-                                   bool randx) {
+                                   bool randx, const int32_t *prank) {
     const int l = __lane_id() & (G - 1);
     bool lose = false;
     for (int32_t eb = e0 + l; eb < e1; eb += G * UNR) {
@@ -62,7 +69,7 @@ __device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t 
         }
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            if (t[u] == tv && gc_prio(s_prio, w[u]) > pv) lose = true;
+            if (t[u] == tv && round_prio(prank, s_prio, w[u]) > pv) lose = true;
     }
     return group_any<G>(lose);
 }
@@ -98,7 +105,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, uint32_t s_prio, uint32_t s_color,
-                                                       uint32_t X, int randx) {
+                                                       uint32_t X, int randx, const int32_t *prank) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = in_list ? (int64_t)*in_count : (int64_t)n;
@@ -117,8 +124,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         const bool hub = e1 - e0 > deg_wave;
         if (forward) e1 = e0;
         const int32_t tv = v >= 0 ? round0_color(s_color, v, X, randx != 0) : 0;
-        const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
-        const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0);
+        const uint32_t pv = v >= 0 ? round_prio(prank, s_prio, v) : 0u;
+        const bool lose =
+            group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0, prank);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) C[v] = lose ? -tv : tv;
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
@@ -175,7 +183,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
-                                                       unsigned long long *c_hub, uint32_t s_prio, int32_t skip_len) {
+                                                       unsigned long long *c_hub, uint32_t s_prio, int32_t skip_len,
+                                                       const int32_t *prank) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -190,8 +199,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
             if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
             else t = -C[v];
         }
-        const uint32_t pv = v >= 0 ? gc_prio(s_prio, v) : 0u;
-        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false);
+        const uint32_t pv = v >= 0 ? round_prio(prank, s_prio, v) : 0u;
+        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false, prank);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) C[v] = t;
         const bool hub = e1 - e0 > deg_wave;
@@ -357,7 +366,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              const unsigned long long *__restrict__ plan,
                                                              int32_t split_len, uint32_t s_prio, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
-                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub) {
+                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
+                                                             const int32_t *prank) {
     const int lane = __lane_id();
     const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
     const int wpb = INIT_BLOCK / 64;
@@ -366,8 +376,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
         const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
         unsigned long long *flag = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
         const int32_t t = ROUND0 ? round0_color(s_color, k.v, X, randx != 0) : -C[k.v];
-        const uint32_t pv = gc_prio(s_prio, k.v);
-        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, s_prio, s_color, X, randx != 0);
+        const uint32_t pv = round_prio(prank, s_prio, k.v);
+        const bool lose =
+            group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, s_prio, s_color, X, randx != 0, prank);
         if (lose && lane == 0) atomicOr(flag, 1ull);
         if (split_last(hub_cnt, k.slot, k.nsub)) {
             if (lane == 0) {
@@ -389,9 +400,10 @@ template <int G>
 static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, int32_t skip_len,
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
-                          int32_t *wl_hub, unsigned long long *c_hub, uint32_t sp, uint32_t sc, uint32_t X, int randx) {
+                          int32_t *wl_hub, unsigned long long *c_hub, uint32_t sp, uint32_t sc, uint32_t X, int randx,
+                          const int32_t *prank) {
     k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, skip_len, in_list, in_count, wl_lo,
-                                            c_lo, wl_hub, c_hub, sp, sc, X, randx);
+                                            c_lo, wl_hub, c_hub, sp, sc, X, randx, prank);
 }
 
 template <int G>
@@ -405,9 +417,9 @@ static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <int G>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                          unsigned long long *c_hub, uint32_t sp, int32_t skip_len) {
+                          unsigned long long *c_hub, uint32_t sp, int32_t skip_len, const int32_t *prank) {
     k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, sp, skip_len);
+                                            c_hub, sp, skip_len, prank);
 }
 
 #define GC_DISPATCH_G(G, CALL)                           \
@@ -421,23 +433,15 @@ static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
         default: { constexpr int GG = 64; CALL; } break; \
     }
 
-extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
-                                   int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
-    gc_status status = gc_check_graph_args(ctx, g);
-    if (status) return status;
-    if (select != GC_FIRST_FIT && select != GC_RANDOM_X) return gc_fail(ctx, GC_ERR_ARG, "select must be GC_FIRST_FIT or GC_RANDOM_X");
-    if (select == GC_RANDOM_X && (X < 1 || X > GC_MAX_X)) return gc_fail(ctx, GC_ERR_ARG, "X must be in [1, %d]", GC_MAX_X);
-    if (max_rounds < 0) return gc_fail(ctx, GC_ERR_ARG, "max_rounds must be >= 0");
-    if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+// Speculative rounds over every vertex (arguments already checked, n > 0).
+// prank == NULL: the initial coloring with hash priorities; otherwise a
+// per-vertex class rank that decides conflicts (asynchronous recoloring).
+gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
+                         uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank) {
+    gc_status status = GC_OK;
     if (select == GC_FIRST_FIT) X = 1;
     const int randx = select == GC_RANDOM_X ? 1 : 0;
-    hipStream_t s = (hipStream_t)stream;
-    GC_HIP(hipSetDevice(ctx->device));
     const int32_t n = g->n;
-    if (n == 0) {
-        if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
-        return GC_OK;
-    }
     auto prio_stream = [&](int32_t r) {
         return gc_stream_value(seed, GC_TAG_PRIO, (flags & GC_FLAG_FIXED_PRIORITY) ? 0u : (uint32_t)r);
     };
@@ -479,10 +483,10 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     const uint32_t sp0 = prio_stream(0), sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
     GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
                                                                 nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
-                                                                sc0, (uint32_t)X, randx)));
+                                                                sc0, (uint32_t)X, randx, prank)));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
-                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx));
+                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, prank));
     GC_LAUNCHED();
     if (split) {
         GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3));
@@ -490,7 +494,7 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
-                                     cnt + 1));
+                                     cnt + 1, prank));
         GC_LAUNCHED();
     }
     int32_t r = 1, cur = 0;
@@ -537,18 +541,19 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
         if (nlo) {
             GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
                                                                         c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp, skip)));
+                                                                        sp, skip, prank)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp, skip));
+                                                       c_lo_out, hub_out, c_hub_out, sp, skip, prank));
             GC_LAUNCHED();
         }
         if (split_round) {
             GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
-                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out));
+                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
+                                         prank));
             GC_LAUNCHED();
         }
         cur = nxt;
@@ -573,4 +578,20 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
         if (status == GC_ERR_NOT_CONVERGED) gc_fail(ctx, status, "not converged after %d rounds", max_rounds);
     }
     return status;
+}
+
+extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                                   int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
+    gc_status status = gc_check_graph_args(ctx, g);
+    if (status) return status;
+    if (select != GC_FIRST_FIT && select != GC_RANDOM_X) return gc_fail(ctx, GC_ERR_ARG, "select must be GC_FIRST_FIT or GC_RANDOM_X");
+    if (select == GC_RANDOM_X && (X < 1 || X > GC_MAX_X)) return gc_fail(ctx, GC_ERR_ARG, "X must be in [1, %d]", GC_MAX_X);
+    if (max_rounds < 0) return gc_fail(ctx, GC_ERR_ARG, "max_rounds must be >= 0");
+    if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    GC_HIP(hipSetDevice(ctx->device));
+    if (g->n == 0) {
+        if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
+        return GC_OK;
+    }
+    return gc_spec_rounds(ctx, g, select, X, seed, max_rounds, flags, colors, st, (hipStream_t)stream, nullptr);
 }

@@ -121,6 +121,12 @@ gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s);
 // a new graph.
 gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out);
 
+// Speculative rounds over every vertex of g (arguments checked, n > 0):
+// prank == NULL gives the initial coloring (hash priorities); a per-vertex
+// class rank instead decides conflicts by rank (asynchronous recoloring).
+gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
+                         uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank);
+
 // Lanes per vertex of the recoloring walk: the walk_group knob, or when it is
 // 0, 8 for graphs whose rows are all shorter than 64 entries (full = false)
 // and the group knob otherwise.

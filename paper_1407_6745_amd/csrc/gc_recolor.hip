@@ -900,3 +900,62 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
     }
     return GC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Asynchronous recoloring aRC (section 3): the classes of the input coloring,
+// ordered by `perm`, give every vertex a rank; the speculative rounds of the
+// initial coloring then run with First Fit, and of two neighbors with the
+// same tentative color the one of the earlier class keeps it.
+// ---------------------------------------------------------------------------
+
+__global__ void k_vertex_rank(int32_t n, const int32_t *__restrict__ C, const int32_t *__restrict__ rank, int32_t ccap,
+                              int32_t *__restrict__ prank) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = C[v];
+        prank[v] = (c >= 1 && c <= ccap) ? rank[c] : INT32_MAX;
+    }
+}
+
+extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                    const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    gc_status status = gc_check_graph_args(ctx, g);
+    if (status) return status;
+    if (perm < 0 || perm > 3) return gc_fail(ctx, GC_ERR_ARG, "perm must be in [0, 3]");
+    if (pass < 0) return gc_fail(ctx, GC_ERR_ARG, "pass must be >= 0");
+    if (g->n > 0 && (!colors_in || !colors_out)) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    const int32_t n = g->n;
+    if (n == 0) {
+        if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
+        return GC_OK;
+    }
+    const int block = 256;
+    // class sizes and order (no split bins: only the ranks are used)
+    const int64_t hist_tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
+    const int hist_grid = (int)(hist_tiles < 16 * ctx->num_cu ? hist_tiles : 16 * ctx->num_cu);
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8, s));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
+    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, ctx->tune.deg_wave, 0,
+                                                             ctx->tune.split_len, ctx->ccap, ctx->hist, ctx->histw,
+                                                             ctx->hist_s, ctx->hist_sc, ctx->scal));
+    GC_LAUNCHED();
+    GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
+                                ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 1,
+                                64 * ctx->tune.hub_words - 1, ctx->hist, ctx->histw, ctx->hist_s, ctx->hist_sc,
+                                (int32_t *)ctx->keys, ctx->pi, ctx->rank, ctx->off, ctx->coff, ctx->cursor, ctx->sbase,
+                                ctx->scal));
+    GC_LAUNCHED();
+    int32_t *prank = ctx->list;  // free outside the recoloring walk
+    GC_TIMED(GC_K_OTHER, s, k_vertex_rank<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors_in, ctx->rank, ctx->ccap,
+                                                                                   prank));
+    GC_LAUNCHED();
+    status = gc_sync_scalars(ctx, s);
+    if (status) return status;
+    if (ctx->hscal[S_ERR] & 1) return gc_fail(ctx, GC_ERR_COLORING, "input color outside [1, %d]", ctx->ccap);
+    const int32_t k = (int32_t)ctx->hscal[S_K];
+    status = gc_spec_rounds(ctx, g, GC_FIRST_FIT, 1, seed, 0, 0, colors_out, st, s, prank);
+    if (status) return status;
+    if (st) st->k_classes = k;
+    return GC_OK;
+}

@@ -333,3 +333,32 @@ def test_hybrid_schedules(gc, kind, x):
         cur, _ = gc.recolor(rp, col, cur, perm, 21, t - 1, out=cur)
         exp = oracle.recolor(g, exp, perm, 21, t - 1).colors
         assert np.array_equal(cur.cpu().numpy(), exp), t
+
+
+@pytest.mark.parametrize("name", ["er", "mesh", "grid", "rmat", "rgg", "complete100", "star", "crown", "path", "single"])
+def test_arc_parity(gc, name):
+    """Asynchronous recoloring (aRC) against the oracle, every class order."""
+    g = GRAPHS[name]()
+    rp, col = dev(g)
+    c0 = oracle.init_color(g, oracle.RANDOM_X, 3, 8).colors
+    cin = torch.from_numpy(c0.copy()).cuda()
+    for perm in range(4):
+        c, st = gc.arc_recolor(rp, col, cin, perm, 8, 2)
+        ref = oracle.arc_recolor(g, c0, perm, 8, 2)
+        assert np.array_equal(c.cpu().numpy(), ref.colors), (name, perm)
+        assert st["rounds"] == ref.stats["rounds"] and st["num_colors"] == ref.stats["num_colors"]
+
+
+def test_arc_tunings_and_in_place(gc):
+    g = GRAPHS["rmat"]()
+    rp, col = dev(g)
+    c0 = oracle.init_color(g, oracle.FIRST_FIT, 1, 4).colors
+    ref = oracle.arc_recolor(g, c0, oracle.PERM_RANDOM, 4, 5).colors
+    for t in (dict(), dict(group=1, deg_wave=8), dict(deg_wave=4, deg_split=16, split_len=64),
+              dict(group=64, deg_wave=0)):
+        ctx = gc.Context(g.n, g.nnz)
+        ctx.set_tuning(**t)
+        cur = torch.from_numpy(c0.copy()).cuda()
+        cur, _ = gc.arc_recolor(rp, col, cur, gc.PERM_RANDOM, 4, 5, out=cur, ctx=ctx)
+        assert np.array_equal(cur.cpu().numpy(), ref), t
+        ctx.close()
