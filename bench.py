@@ -74,19 +74,19 @@ def recorded_traffic(workload, tuning):
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(g, select, X, perm, passes, seed, budget_s=12.0):
+def cpu_baseline(g, select, X, perms, passes, seed, method="rc", budget_s=12.0):
     """The oracle (single thread, as it stands) on whole steps of the same workload."""
     import oracle
 
     sel = oracle.FIRST_FIT if select == "FIRST_FIT" else oracle.RANDOM_X
-    pm = {"RV": oracle.PERM_REVERSE, "NI": oracle.PERM_NONINC, "ND": oracle.PERM_NONDEC, "RAND": oracle.PERM_RANDOM}[perm]
+    recolor = oracle.recolor if method == "rc" else oracle.arc_recolor
     t0 = time.perf_counter()
     steps = 0
     while True:
         r = oracle.init_color(g, sel, X, seed)
         c = r.colors
         for p in range(passes):
-            c = oracle.recolor(g, c, pm, seed, p).colors
+            c = recolor(g, c, perms[p], seed, p).colors
         steps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or el / steps * (steps + 1) > 2.5 * budget_s:
@@ -355,6 +355,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="comma list key=value of library tuning knobs")
+    ap.add_argument("--method", default="rc", choices=("rc", "arc"),
+                    help="recoloring: synchronous class walk (rc) or asynchronous speculative rounds (arc)")
+    ap.add_argument("--schedule", default="fixed", choices=("fixed", "ndrand5", "ndrand10", "ndrand2i"),
+                    help="class order per pass: the workload's fixed order, or a hybrid ND/RAND schedule")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -398,11 +402,16 @@ def main():
         ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tune.split(","))})
     stream = torch.cuda.current_stream()
 
+    sched = {"fixed": (gc.SCHED_FIXED, 0), "ndrand5": (gc.SCHED_ND_RAND_X, 5), "ndrand10": (gc.SCHED_ND_RAND_X, 10),
+             "ndrand2i": (gc.SCHED_ND_RAND_POW2, 0)}[args.schedule]
+    perms = [gc.schedule_perm(sched[0], pm, sched[1], p + 1) for p in range(passes)]
+    recolor_fn = gc.recolor if args.method == "rc" else gc.arc_recolor
+
     def step(stats=False):
         c, s0 = gc.init_color(rp, col, sel, X, args.seed, out=colors, stats=stats, ctx=ctx)
         hist = [s0]
         for p in range(passes):
-            c, sp = gc.recolor(rp, col, c, pm, args.seed, p, out=c, stats=stats, ctx=ctx)
+            c, sp = recolor_fn(rp, col, c, perms[p], args.seed, p, out=c, stats=stats, ctx=ctx)
             hist.append(sp)
         return c, hist
 
@@ -425,7 +434,7 @@ def main():
     gc.init_color(rp, col, sel, X, args.seed, out=colors, stats=False, ctx=ctx)
     ev[1].record(stream)
     for p in range(passes):
-        gc.recolor(rp, col, colors, pm, args.seed, p, out=colors, stats=False, ctx=ctx)
+        recolor_fn(rp, col, colors, perms[p], args.seed, p, out=colors, stats=False, ctx=ctx)
         ev[p + 2].record(stream)
     torch.cuda.synchronize()
     t_init = ev[0].elapsed_time(ev[1])
@@ -466,7 +475,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "m": m, "passes": passes, "X": X, "select": select,
-                   "perm": perm, "seed": args.seed, "tuning": ctx.tuning, "launch": ctx.info()},
+                   "perm": perm, "method": args.method, "schedule": args.schedule, "seed": args.seed,
+                   "tuning": ctx.tuning, "launch": ctx.info()},
         "colors": {"init": colors_trace[0], "after_pass": colors_trace[1:]},
         "valid": (conflicts, uncolored) == (0, 0),
         "init": {"rounds": rounds, "round_sizes": round_sizes, "round_degsum": round_degsum, "ms": round(t_init, 4),
@@ -480,7 +490,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cb, cref = cpu_baseline(g, select, X, perm, passes, args.seed)
+        cb, cref = cpu_baseline(g, select, X, perms, passes, args.seed, args.method)
         out["cpu_baseline"] = cb
         import numpy as np
 
