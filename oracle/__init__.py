@@ -21,6 +21,8 @@ OK, ERR_ARG, ERR_GRAPH, ERR_COLORING, ERR_OOM, ERR_NOT_CONVERGED = 0, 1, 2, 3, 4
 FIRST_FIT, RANDOM_X = 0, 1
 PERM_REVERSE, PERM_NONINC, PERM_NONDEC, PERM_RANDOM = 0, 1, 2, 3
 FIXED_PRIORITY = 1
+PRIO_LF = 2
+PRIO_NATURAL = 4
 
 
 class Stats(ctypes.Structure):

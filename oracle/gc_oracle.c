@@ -37,7 +37,7 @@ enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_GRAPH = 2, ORC_ERR_COLORING = 3, ORC
        ORC_ERR_NOT_CONVERGED = 6 };
 enum { ORC_FIRST_FIT = 0, ORC_RANDOM_X = 1 };
 enum { ORC_PERM_REVERSE = 0, ORC_PERM_NONINC = 1, ORC_PERM_NONDEC = 2, ORC_PERM_RANDOM = 3 };
-enum { ORC_FLAG_FIXED_PRIORITY = 1 };
+enum { ORC_FLAG_FIXED_PRIORITY = 1, ORC_FLAG_PRIO_LF = 2, ORC_FLAG_PRIO_NATURAL = 4 };
 enum { ORC_TAG_PRIO = 1, ORC_TAG_COLOR = 2, ORC_TAG_PERM = 3, ORC_TAG_GRAPH = 4 };
 
 typedef struct {
@@ -213,6 +213,21 @@ int orc_check_csr(int32_t n, const int32_t *rp, const int32_t *col) {
 /* ------------------------------------------------------------------ */
 
 /*
+ * Conflict key of v in round r (the larger key keeps its colour):
+ *   default: orc_key(seed, r, v), a random order redrawn every round
+ *            (round 0's order in every round with ORC_FLAG_FIXED_PRIORITY);
+ *   ORC_FLAG_PRIO_LF: Largest First (section 2.1's vertex-visit orderings) --
+ *            larger degree first, ties by round 0's random order;
+ *   ORC_FLAG_PRIO_NATURAL: natural order -- smaller vertex id first.
+ */
+static uint64_t init_key(uint32_t flags, uint64_t seed, uint32_t r, const int32_t *rp, int32_t v) {
+    if (flags & ORC_FLAG_PRIO_LF)
+        return ((uint64_t)(uint32_t)(rp[v + 1] - rp[v]) << 32) | orc_prio(seed, 0u, (uint32_t)v);
+    if (flags & ORC_FLAG_PRIO_NATURAL) return (uint64_t)(0xFFFFFFFFu - (uint32_t)v);
+    return orc_key(seed, (flags & ORC_FLAG_FIXED_PRIORITY) ? 0u : r, (uint32_t)v);
+}
+
+/*
  * Rounds: every uncoloured vertex is tentatively coloured from the colours its
  * neighbours held at the start of the round (all vertices of a round read the
  * same snapshot: one superstep covering every uncoloured vertex).  Then each
@@ -234,6 +249,7 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
                    int64_t *w_sizes, int64_t *w_degsum, int32_t w_cap) {
     if (n < 0 || (sel != ORC_FIRST_FIT && sel != ORC_RANDOM_X) || (sel == ORC_RANDOM_X && X < 1) || max_rounds < 0)
         return ORC_ERR_ARG;
+    if ((flags & ORC_FLAG_PRIO_LF) && (flags & ORC_FLAG_PRIO_NATURAL)) return ORC_ERR_ARG;
     if (sel == ORC_FIRST_FIT) X = 1;
     int32_t maxd = 0;
     for (int32_t v = 0; v < n; v++)
@@ -255,7 +271,6 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
     int32_t nW = n, r = 0, status = ORC_OK;
     while (nW > 0) {
         if (max_rounds > 0 && r == max_rounds) { status = ORC_ERR_NOT_CONVERGED; break; }
-        uint32_t rp_round = (flags & ORC_FLAG_FIXED_PRIORITY) ? 0u : (uint32_t)r;
         int64_t degsum = 0;
         /* tentative colouring from the start-of-round snapshot C (C is not written here) */
         for (int32_t i = 0; i < nW; i++) {
@@ -285,11 +300,11 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
         int32_t nL = 0;
         for (int32_t i = 0; i < nW; i++) {
             int32_t v = W[i];
-            uint64_t kv = orc_key(seed, rp_round, (uint32_t)v);
+            uint64_t kv = init_key(flags, seed, (uint32_t)r, rp, v);
             lost[i] = 0;
             for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
                 int32_t w = col[e];
-                if (inW[w] == r && T[w] == T[v] && orc_key(seed, rp_round, (uint32_t)w) > kv) { lost[i] = 1; break; }
+                if (inW[w] == r && T[w] == T[v] && init_key(flags, seed, (uint32_t)r, rp, w) > kv) { lost[i] = 1; break; }
             }
         }
         /* winners keep their colour, losers form the next round */

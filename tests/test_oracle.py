@@ -476,3 +476,45 @@ def test_arc_rejects_bad_input():
     g = gen.path(4)
     assert oracle.arc_recolor(g, [1, 0, 1, 2]).status == oracle.ERR_COLORING
     assert oracle.arc_recolor(g, [1, 1, 2, 1]).status == oracle.ERR_COLORING
+
+
+# ---- ordering-derived priorities for the initial coloring (Largest First, Natural) ----
+
+def test_priority_orders_closed_forms():
+    FF = oracle.FIRST_FIT
+    # LF: the star's center has the largest degree, so it keeps color 1 in round 0
+    r = oracle.init_color(gen.star(30), FF, 1, 3, flags=oracle.PRIO_LF)
+    assert r.colors.tolist() == [1] + [2] * 30 and r.stats["rounds"] == 2
+    # Natural: K_n colors one vertex per round in id order
+    r = oracle.init_color(gen.complete(10), FF, 1, 3, flags=oracle.PRIO_NATURAL)
+    assert r.colors.tolist() == list(range(1, 11)) and r.stats["rounds"] == 10
+    # Natural on paths, 2D grids and the 3D mesh: the natural-order greedy closed forms
+    assert oracle.init_color(gen.path(13), FF, 1, 5, flags=oracle.PRIO_NATURAL).colors.tolist() == \
+        [1 + (i & 1) for i in range(13)]
+    nx, ny = 9, 7
+    c = oracle.init_color(gen.grid5(nx, ny), FF, 1, 5, flags=oracle.PRIO_NATURAL).colors
+    assert c.tolist() == [1 + ((x + y) & 1) for y in range(ny) for x in range(nx)]
+    N = 5
+    c = oracle.init_color(gen.mesh27(N), FF, 1, 5, flags=oracle.PRIO_NATURAL).colors
+    assert c.tolist() == [1 + (x & 1) + 2 * (y & 1) + 4 * (z & 1) for z in range(N) for y in range(N) for x in range(N)]
+
+
+def test_lf_on_regular_graphs_is_the_fixed_random_order():
+    """All degrees equal: Largest First reduces to round 0's random order."""
+    for g in (gen.complete(11), gen.cycle(20), gen.crown(6)):
+        a = oracle.init_color(g, oracle.FIRST_FIT, 1, 9, flags=oracle.PRIO_LF)
+        b = oracle.init_color(g, oracle.FIRST_FIT, 1, 9, flags=oracle.FIXED_PRIORITY)
+        assert np.array_equal(a.colors, b.colors) and a.stats["rounds"] == b.stats["rounds"]
+
+
+def test_priority_orders_invariants():
+    for fam in range(len(FAMILIES)):
+        g = FAMILIES[fam]()
+        deg = g.degrees
+        for flags in (oracle.PRIO_LF, oracle.PRIO_NATURAL):
+            for sel, X in ((oracle.FIRST_FIT, 1), (oracle.RANDOM_X, 4)):
+                r = oracle.init_color(g, sel, X, 6, flags=flags)
+                assert oracle.validate(g, r.colors) == (0, 0)
+                assert (r.colors <= deg + X).all()
+    with pytest.raises(RuntimeError):  # the two orders exclude each other
+        oracle.init_color(gen.path(3), oracle.FIRST_FIT, 1, 1, flags=oracle.PRIO_LF | oracle.PRIO_NATURAL)
