@@ -66,6 +66,8 @@ typedef enum gc_perm {
 
 /* gc_init_color flags */
 #define GC_FLAG_FIXED_PRIORITY 1u /* one random total order for all rounds (round 0's keys) */
+#define GC_FLAG_PRIO_LF 2u        /* Largest First: larger degree wins a conflict, ties by round 0's keys */
+#define GC_FLAG_PRIO_NATURAL 4u   /* natural order: the smaller vertex id wins a conflict */
 
 /* Largest X accepted by GC_RANDOM_X. */
 #define GC_MAX_X 1024

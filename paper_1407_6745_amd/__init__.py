@@ -19,6 +19,8 @@ FIRST_FIT, RANDOM_X = 0, 1
 PERM_REVERSE, PERM_NONINC, PERM_NONDEC, PERM_RANDOM = 0, 1, 2, 3
 PERM_NAMES = {"RV": PERM_REVERSE, "NI": PERM_NONINC, "ND": PERM_NONDEC, "RAND": PERM_RANDOM}
 FLAG_FIXED_PRIORITY = 1
+FLAG_PRIO_LF = 2
+FLAG_PRIO_NATURAL = 4
 MAX_X = 1024
 
 

@@ -33,20 +33,37 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
     return randx ? (int32_t)gc_pick(s_color, w, X) + 1 : 1;
 }
 
-// Conflict priority of v in a round (larger wins): the hash of (seed, v,
-// round), or, when a per-vertex class rank is given (asynchronous
-// recoloring), the rank reversed so that the earlier class wins.
-__device__ inline uint32_t round_prio(const int32_t *prank, uint32_t s_prio, int32_t v) {
-    return prank ? ~(uint32_t)prank[v] : gc_prio(s_prio, v);
+// Conflict priority of a round (the larger key keeps its color):
+//   PRIO_HASH:    the hash of (seed, v, round) (s_prio holds the round's stream);
+//   PRIO_RANK:    a per-vertex class rank, the earlier class first
+//                 (asynchronous recoloring);
+//   PRIO_LF:      Largest First: larger degree first, ties by round 0's hash;
+//   PRIO_NATURAL: smaller vertex id first.
+enum { PRIO_HASH = 0, PRIO_RANK = 1, PRIO_LF = 2, PRIO_NATURAL = 3 };
+
+struct Prio {
+    int mode;
+    uint32_t s_prio;
+    const int32_t *prank;  // PRIO_RANK
+    const int32_t *rp;     // PRIO_LF: row pointers
+};
+
+__device__ inline uint64_t round_prio(const Prio &p, int32_t v) {
+    switch (p.mode) {
+        case PRIO_RANK: return ~(uint32_t)p.prank[v];
+        case PRIO_LF: return ((uint64_t)(uint32_t)(p.rp[v + 1] - p.rp[v]) << 32) | gc_prio(p.s_prio, v);
+        case PRIO_NATURAL: return 0xFFFFFFFFu - (uint32_t)v;
+        default: return gc_prio(p.s_prio, v);
+    }
 }
 
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
 template <int G, bool ROUND0, int UNR = GC_UNROLL>
-__device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
-                                   const int32_t *C, int32_t n, uint32_t s_prio, uint32_t s_color, uint32_t X,
-                                   bool randx, const int32_t *prank) {
+__device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
+                                   const int32_t *C, int32_t n, const Prio &pr, uint32_t s_color, uint32_t X,
+                                   bool randx) {
     const int l = __lane_id() & (G - 1);
     bool lose = false;
     for (int32_t eb = e0 + l; eb < e1; eb += G * UNR) {
@@ -69,7 +86,7 @@ __device__ inline bool group_loses(int32_t tv, uint32_t pv, int32_t e0, int32_t 
         }
 #pragma unroll
         for (int u = 0; u < UNR; u++)
-            if (t[u] == tv && round_prio(prank, s_prio, w[u]) > pv) lose = true;
+            if (t[u] == tv && round_prio(pr, w[u]) > pv) lose = true;
     }
     return group_any<G>(lose);
 }
@@ -104,8 +121,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
                                                        int32_t skip_len, const int32_t *__restrict__ in_list,
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                                                       unsigned long long *c_hub, uint32_t s_prio, uint32_t s_color,
-                                                       uint32_t X, int randx, const int32_t *prank) {
+                                                       unsigned long long *c_hub, Prio pr, uint32_t s_color,
+                                                       uint32_t X, int randx) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = in_list ? (int64_t)*in_count : (int64_t)n;
@@ -124,9 +141,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         const bool hub = e1 - e0 > deg_wave;
         if (forward) e1 = e0;
         const int32_t tv = v >= 0 ? round0_color(s_color, v, X, randx != 0) : 0;
-        const uint32_t pv = v >= 0 ? round_prio(prank, s_prio, v) : 0u;
-        const bool lose =
-            group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, s_prio, s_color, X, randx != 0, prank);
+        const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
+        const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, pr, s_color, X, randx != 0);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) C[v] = lose ? -tv : tv;
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
@@ -183,8 +199,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
-                                                       unsigned long long *c_hub, uint32_t s_prio, int32_t skip_len,
-                                                       const int32_t *prank) {
+                                                       unsigned long long *c_hub, Prio pr, int32_t skip_len) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -199,8 +214,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
             if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
             else t = -C[v];
         }
-        const uint32_t pv = v >= 0 ? round_prio(prank, s_prio, v) : 0u;
-        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, s_prio, 0u, 1u, false, prank);
+        const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
+        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, pr, 0u, 1u, false);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) C[v] = t;
         const bool hub = e1 - e0 > deg_wave;
@@ -364,10 +379,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              int32_t *C, const int32_t *__restrict__ hub_v,
                                                              const int32_t *__restrict__ hub_first,
                                                              const unsigned long long *__restrict__ plan,
-                                                             int32_t split_len, uint32_t s_prio, uint32_t s_color,
+                                                             int32_t split_len, Prio pr, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
-                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
-                                                             const int32_t *prank) {
+                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub) {
     const int lane = __lane_id();
     const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
     const int wpb = INIT_BLOCK / 64;
@@ -376,9 +390,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
         const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
         unsigned long long *flag = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
         const int32_t t = ROUND0 ? round0_color(s_color, k.v, X, randx != 0) : -C[k.v];
-        const uint32_t pv = round_prio(prank, s_prio, k.v);
-        const bool lose =
-            group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, s_prio, s_color, X, randx != 0, prank);
+        const uint64_t pv = round_prio(pr, k.v);
+        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, pr, s_color, X, randx != 0);
         if (lose && lane == 0) atomicOr(flag, 1ull);
         if (split_last(hub_cnt, k.slot, k.nsub)) {
             if (lane == 0) {
@@ -400,10 +413,9 @@ template <int G>
 static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, int32_t skip_len,
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
-                          int32_t *wl_hub, unsigned long long *c_hub, uint32_t sp, uint32_t sc, uint32_t X, int randx,
-                          const int32_t *prank) {
+                          int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx) {
     k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, skip_len, in_list, in_count, wl_lo,
-                                            c_lo, wl_hub, c_hub, sp, sc, X, randx, prank);
+                                            c_lo, wl_hub, c_hub, pr, sc, X, randx);
 }
 
 template <int G>
@@ -417,9 +429,9 @@ static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <int G>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                          unsigned long long *c_hub, uint32_t sp, int32_t skip_len, const int32_t *prank) {
+                          unsigned long long *c_hub, Prio pr, int32_t skip_len) {
     k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, sp, skip_len, prank);
+                                            c_hub, pr, skip_len);
 }
 
 #define GC_DISPATCH_G(G, CALL)                           \
@@ -442,8 +454,12 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     if (select == GC_FIRST_FIT) X = 1;
     const int randx = select == GC_RANDOM_X ? 1 : 0;
     const int32_t n = g->n;
-    auto prio_stream = [&](int32_t r) {
-        return gc_stream_value(seed, GC_TAG_PRIO, (flags & GC_FLAG_FIXED_PRIORITY) ? 0u : (uint32_t)r);
+    // conflict priority of round r
+    const int pmode = prank ? PRIO_RANK
+                            : (flags & GC_FLAG_PRIO_LF) ? PRIO_LF : (flags & GC_FLAG_PRIO_NATURAL) ? PRIO_NATURAL : PRIO_HASH;
+    auto prio_of = [&](int32_t r) {
+        const bool fixed = (flags & (GC_FLAG_FIXED_PRIORITY | GC_FLAG_PRIO_LF)) != 0;
+        return Prio{pmode, gc_stream_value(seed, GC_TAG_PRIO, fixed ? 0u : (uint32_t)r), prank, g->row_ptr};
     };
     const int G = ctx->tune.group;
     const int32_t deg_wave = ctx->tune.deg_wave;
@@ -480,13 +496,14 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     auto split_plan = [&](const int32_t *list, const unsigned long long *count) {
         k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan);
     };
-    const uint32_t sp0 = prio_stream(0), sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
+    const Prio sp0 = prio_of(0);
+    const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
     GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
                                                                 nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
-                                                                sc0, (uint32_t)X, randx, prank)));
+                                                                sc0, (uint32_t)X, randx)));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
-                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, prank));
+                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx));
     GC_LAUNCHED();
     if (split) {
         GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3));
@@ -494,7 +511,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
-                                     cnt + 1, prank));
+                                     cnt + 1));
         GC_LAUNCHED();
     }
     int32_t r = 1, cur = 0;
@@ -515,7 +532,8 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         unsigned long long *c_lo_out = cnt + 2 * nxt, *c_hub_out = cnt + 2 * nxt + 1;
         GC_HIP(hipMemsetAsync(c_lo_out, 0, 2 * 8, s));
         GC_HIP(hipMemsetAsync(cnt + 4, 0, 8, s));
-        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r), sp = prio_stream(r);
+        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
+        const Prio sp = prio_of(r);
         const bool split_round = split && nhub > 0;
         if (split_round) {
             GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in));
@@ -541,19 +559,18 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (nlo) {
             GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
                                                                         c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp, skip, prank)));
+                                                                        sp, skip)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp, skip, prank));
+                                                       c_lo_out, hub_out, c_hub_out, sp, skip));
             GC_LAUNCHED();
         }
         if (split_round) {
             GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
-                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
-                                         prank));
+                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out));
             GC_LAUNCHED();
         }
         cur = nxt;
@@ -588,6 +605,8 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     if (select == GC_RANDOM_X && (X < 1 || X > GC_MAX_X)) return gc_fail(ctx, GC_ERR_ARG, "X must be in [1, %d]", GC_MAX_X);
     if (max_rounds < 0) return gc_fail(ctx, GC_ERR_ARG, "max_rounds must be >= 0");
     if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    if ((flags & GC_FLAG_PRIO_LF) && (flags & GC_FLAG_PRIO_NATURAL))
+        return gc_fail(ctx, GC_ERR_ARG, "GC_FLAG_PRIO_LF and GC_FLAG_PRIO_NATURAL exclude each other");
     GC_HIP(hipSetDevice(ctx->device));
     if (g->n == 0) {
         if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }

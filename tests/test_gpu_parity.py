@@ -362,3 +362,22 @@ def test_arc_tunings_and_in_place(gc):
         cur, _ = gc.arc_recolor(rp, col, cur, gc.PERM_RANDOM, 4, 5, out=cur, ctx=ctx)
         assert np.array_equal(cur.cpu().numpy(), ref), t
         ctx.close()
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4], ids=["fixed", "lf", "natural"])
+@pytest.mark.parametrize("name", ["er", "mesh", "grid", "rmat", "star", "complete100", "path"])
+def test_init_priority_orders(gc, name, flags):
+    """Initial coloring under the fixed random order, Largest First and the
+    natural order (first fit and Random-X) against the oracle."""
+    g = GRAPHS[name]()
+    for sel, X in ((gc.FIRST_FIT, 1), (gc.RANDOM_X, 4)):
+        _init_equal(gc, g, sel, X, 17, flags=flags)
+
+
+def test_init_priority_orders_split_rows(gc):
+    g = GRAPHS["rmat"]()
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(deg_wave=8, deg_split=64, split_len=64)
+    for flags in (2, 4):
+        _init_equal(gc, g, gc.FIRST_FIT, 1, 19, flags=flags, ctx=ctx)
+    ctx.close()
