@@ -19,9 +19,11 @@
  *
  * A request's result does not depend on what else runs: every slot runs the
  * same kernels as the single-graph calls of gc.h with the request's seed.
- * The recoloring walk of the slots is walk_mode 1 (one launch per class),
- * whose kernels never wait on other workgroups, so concurrent requests can
- * share the device in any proportion.
+ * Initial colorings of different slots overlap on the device; a recoloring
+ * pass (the persistent class walk, which needs all of its workgroups resident
+ * at once) has the device to itself: it waits until the initial colorings in
+ * flight have finished, and new ones wait for it.  Each slot's walk is sized
+ * on the idle device at creation.
  *
  * Threads: gc_server_submit, gc_server_poll and gc_server_stats may be
  * called from any host thread.  gc_server_destroy waits for every submitted

@@ -57,8 +57,8 @@ struct gc_ctx {
     int32_t *hub_v;          // initial coloring: per hub slot, the long row's vertex
     int32_t *hub_first;      // initial coloring: per hub slot, its first chunk
     int64_t hub_cap;         // hub slots allocated
-    int walk_blocks;         // co-resident workgroups of the persistent walk (0 = not computed)
-    int walk_blocks_group;   // walk variant (2 * group + full) the count was computed for
+    int walk_blocks;         // co-resident workgroups of the last persistent walk launched (0 = none yet)
+    int walk_blocks_v[130];  // measured per walk variant (2 * group + full); 0 = not measured
     // longest row of the last graph seen by the recoloring (keyed by its arrays and sizes)
     const void *deg_key_rp, *deg_key_col;
     int64_t deg_key_n, deg_key_nnz;

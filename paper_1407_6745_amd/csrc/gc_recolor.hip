@@ -770,7 +770,7 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     int32_t *hub_cnt = ctx->hub_cnt ? ctx->hub_cnt : (int32_t *)ctx->scal;
     unsigned long long *hub_bits = ctx->hub_bits ? ctx->hub_bits : ctx->scal;
     const int32_t split_len = ctx->tune.split_len;
-    if (ctx->walk_blocks == 0 || ctx->walk_blocks_group != variant) {
+    if (ctx->walk_blocks_v[variant] == 0) {
         // The occupancy query is an upper bound; the walk needs every workgroup
         // resident at once, so measure it: a probe launch (no work) where every
         // workgroup checks in and waits, bounded, for all the others.  Step the
@@ -794,9 +794,9 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
         }
         if (per_cu < 1) return gc_fail(ctx, GC_ERR_DEVICE, "walk kernel: no grid was fully resident");
         GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
-        ctx->walk_blocks = blocks;
-        ctx->walk_blocks_group = variant;
+        ctx->walk_blocks_v[variant] = blocks;
     }
+    ctx->walk_blocks = ctx->walk_blocks_v[variant];
     // An ordinary stream-ordered launch whose grid is what the device holds at
     // once (measured above): the kernel starts after the previous kernel of the
     // stream has finished, so every workgroup is dispatched at once on an

@@ -103,6 +103,15 @@ struct gc_server {
     char *arena_base = nullptr;
     Arena arena;
     std::mutex mu;
+    // Device gate: initial colorings of several slots share the device;
+    // a recoloring pass runs alone.  Its persistent walk needs every one of
+    // its workgroups resident: kernels of other slots could only delay some of
+    // them, but meanwhile the resident ones spin on their dependencies and the
+    // device does little else.  Writers (passes) go first once they wait.
+    std::mutex gate_mu;
+    std::condition_variable gate_cv;
+    int gate_shared = 0, gate_waiting = 0;
+    bool gate_excl = false;
     std::condition_variable cv_work, cv_done;
     std::deque<Waiting> queue;
     std::deque<gc_request_done> done;
@@ -114,6 +123,27 @@ struct gc_server {
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    void enter_shared() {
+        std::unique_lock<std::mutex> lk(gate_mu);
+        gate_cv.wait(lk, [&] { return !gate_excl && gate_waiting == 0; });
+        gate_shared++;
+    }
+    void leave_shared() {
+        std::lock_guard<std::mutex> lk(gate_mu);
+        if (--gate_shared == 0) gate_cv.notify_all();
+    }
+    void enter_excl() {
+        std::unique_lock<std::mutex> lk(gate_mu);
+        gate_waiting++;
+        gate_cv.wait(lk, [&] { return !gate_excl && gate_shared == 0; });
+        gate_waiting--;
+        gate_excl = true;
+    }
+    void leave_excl() {
+        std::lock_guard<std::mutex> lk(gate_mu);
+        gate_excl = false;
+        gate_cv.notify_all();
     }
     void worker(int idx);
     gc_request_done run(int idx, const Waiting &w, int64_t off);
@@ -141,13 +171,21 @@ gc_request_done gc_server::run(int idx, const Waiting &w, int64_t off) {
     if (r.nnz > 0) hip_ok(hipMemcpyAsync(col, r.col_idx, 4 * (size_t)r.nnz, hipMemcpyHostToDevice, sl.stream));
     gc_csr g{r.n, 0, r.nnz, rp, r.nnz > 0 ? col : nullptr};
     gc_stats s0{}, s1{};
-    if (st == GC_OK) st = gc_init_color(sl.ctx, &g, r.select, r.X, r.seed, 0, 0, colors, &s0, sl.stream);
+    if (st == GC_OK) {
+        enter_shared();
+        st = gc_init_color(sl.ctx, &g, r.select, r.X, r.seed, 0, 0, colors, &s0, sl.stream);
+        hip_ok(hipStreamSynchronize(sl.stream));  // its kernels have left the device
+        leave_shared();
+    }
     d.rounds = s0.rounds;
     d.colors_init = s0.num_colors;
     d.colors_final = s0.num_colors;
     for (int32_t p = 0; p < r.passes && st == GC_OK; p++) {
+        enter_excl();
         st = gc_recolor(sl.ctx, &g, r.perm, r.seed, p, colors, colors, p == r.passes - 1 ? &s1 : nullptr, sl.stream);
         if (st == GC_OK && p == r.passes - 1) d.colors_final = s1.num_colors;
+        hip_ok(hipStreamSynchronize(sl.stream));
+        leave_excl();
     }
     if (st == GC_OK && r.n > 0)
         hip_ok(hipMemcpyAsync(r.colors, colors, 4 * (size_t)r.n, hipMemcpyDeviceToHost, sl.stream));
@@ -200,6 +238,47 @@ void gc_server::worker(int idx) {
     }
 }
 
+// Star with `leaves` leaves (center 0) as host CSR.
+static void star_csr(int32_t leaves, std::vector<int32_t> &rp, std::vector<int32_t> &col) {
+    rp.assign(leaves + 2, 0);
+    col.clear();
+    for (int32_t i = 1; i <= leaves; i++) col.push_back(i);
+    rp[1] = leaves;
+    for (int32_t i = 1; i <= leaves; i++) {
+        col.push_back(0);
+        rp[i + 1] = rp[i] + 1;
+    }
+}
+
+static gc_status warm_walks(gc_server *s) {
+    if (s->cfg.max_n < 65 || s->cfg.max_nnz < 128) return GC_OK;  // slots that cannot hold the warm-up graphs
+    int32_t *d = nullptr;
+    const size_t ints = 2 * (66 + 128 + 65);
+    if (hipMalloc((void **)&d, ints * 4) != hipSuccess) return GC_ERR_OOM;
+    gc_status st = GC_OK;
+    for (int32_t leaves : {1, 64}) {
+        std::vector<int32_t> rp, col;
+        star_csr(leaves, rp, col);
+        const int32_t n = leaves + 1;
+        int32_t *drp = d, *dcol = d + rp.size(), *dc = dcol + col.size();
+        if (hipMemcpy(drp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dcol, col.data(), col.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            st = GC_ERR_DEVICE;
+            break;
+        }
+        gc_csr g{n, 0, (int64_t)col.size(), drp, dcol};
+        for (Slot &sl : s->slots) {
+            gc_stats x{};
+            st = gc_init_color(sl.ctx, &g, GC_FIRST_FIT, 1, 1, 0, 0, dc, &x, sl.stream);
+            if (st == GC_OK) st = gc_recolor(sl.ctx, &g, GC_PERM_REVERSE, 1, 0, dc, dc, &x, sl.stream);
+            if (st != GC_OK) break;
+        }
+        if (st != GC_OK) break;
+    }
+    (void)hipFree(d);
+    return st;
+}
+
 static void server_free(gc_server *s) {
     for (Slot &sl : s->slots) {
         if (sl.ev0) (void)hipEventDestroy(sl.ev0);
@@ -239,14 +318,20 @@ extern "C" gc_status gc_server_create(const gc_server_config *cfg, gc_server **o
             server_free(s);
             return st;
         }
-        gc_tuning t;
-        gc_ctx_get_tuning(sl.ctx, &t);
-        t.walk_mode = 1;  // per-class launches: no kernel waits on other workgroups
-        gc_ctx_set_tuning(sl.ctx, &t);
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreate(&sl.ev0) != hipSuccess || hipEventCreate(&sl.ev1) != hipSuccess) {
             server_free(s);
             return GC_ERR_DEVICE;
+        }
+    }
+    // Size every slot's persistent walk on the idle device (the walk measures
+    // how many workgroups are co-resident at its first use): one tiny graph
+    // with short rows and one with a row of 64 entries.
+    {
+        gc_status st = warm_walks(s);
+        if (st != GC_OK) {
+            server_free(s);
+            return st;
         }
     }
     for (int i = 0; i < cfg->slots; i++) s->workers.emplace_back(&gc_server::worker, s, i);
