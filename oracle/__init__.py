@@ -77,6 +77,8 @@ def _load():
         "orc_arc_recolor": (ctypes.c_int, [i32, i32p, i32p, i32, u64, i32, i32p, i32p, i32p, ctypes.POINTER(Stats)]),
         "orc_schedule_perm": (i32, [i32, i32, i32, i32]),
         "orc_chromatic": (i32, [i32, i32p, i32p]),
+        "orc_square_count": (ctypes.c_int64, [i32, i32p, i32p, i32p]),
+        "orc_square_fill": (ctypes.c_int, [i32, i32p, i32p, i32p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -260,6 +262,56 @@ def schedule_perm(kind, base, x, t) -> int:
 def chromatic(g) -> int:
     rp, col = _csr(g)
     return int(_load().orc_chromatic(g.n, _p32(rp), _p32(col)))
+
+
+# ---- distance-2 coloring ----
+class Graph:
+    """A CSR graph produced by the oracle (same fields as the generators' graphs)."""
+
+    def __init__(self, n, row_ptr, col, name=""):
+        self.n, self.row_ptr, self.col, self.name = n, row_ptr, col, name
+
+    @property
+    def nnz(self):
+        return int(self.col.shape[0])
+
+
+def square(g) -> Graph:
+    """The square graph G^2: u != w adjacent iff G joins them by a path of one
+    or two edges (section 1's distance-k condition with k = 2).  Rows sorted,
+    no duplicates."""
+    rp, col = _csr(g)
+    rp2 = np.zeros(g.n + 1, np.int32)
+    nnz2 = int(_load().orc_square_count(g.n, _p32(rp), _p32(col), _p32(rp2)))
+    if nnz2 < 0:
+        raise RuntimeError("orc_square_count: square graph too large")
+    col2 = np.zeros(max(nnz2, 1), np.int32)
+    rc = _load().orc_square_fill(g.n, _p32(rp), _p32(col), _p32(col2))
+    if rc:
+        raise RuntimeError(f"orc_square_fill: {rc}")
+    return Graph(g.n, rp2, col2[:nnz2], getattr(g, "name", "") + "^2")
+
+
+# A distance-2 coloring of G is a distance-1 coloring of G^2 (section 1), so
+# the distance-2 routines are the distance-1 ones applied to the square.
+# Largest First would need degrees in G^2 and is not offered.
+
+def init_color_d2(g, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0, w_cap=None, sq=None) -> InitResult:
+    """Speculative initial distance-2 coloring (w_degsum counts degrees in G^2)."""
+    if flags & PRIO_LF:
+        raise ValueError("Largest First is not defined for distance-2 coloring here")
+    return init_color(square(g) if sq is None else sq, select, X, seed, max_rounds, flags, w_cap)
+
+
+def recolor_d2(g, colors, perm=PERM_REVERSE, seed=1, pass_=0, sq=None) -> RecolorResult:
+    """One recoloring pass of a distance-2 coloring (classes of a distance-2
+    coloring are independent in G^2)."""
+    return recolor(square(g) if sq is None else sq, colors, perm, seed, pass_)
+
+
+def validate_d2(g, colors, sq=None) -> tuple[int, int]:
+    """(pairs u < w at distance 1 or 2 with equal positive colors, uncolored vertices)."""
+    return validate(square(g) if sq is None else sq, colors)
 
 
 def run_pipeline(g, select, X, seed, perm_schedule, max_rounds=0):

@@ -1,6 +1,7 @@
 /*
  * gc_oracle.c - plain, single-threaded CPU oracle for speculative distance-1
- * coloring with iterated (Culberson) recoloring.
+ * coloring with iterated (Culberson) recoloring, and the square graph that
+ * turns distance-2 coloring into distance-1 coloring.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
  * load or call this file: only the test suite, the smoke check and the
@@ -26,7 +27,9 @@
  * speculative initial colouring on general graphs, which have no closed form
  * ("parity unpinned beyond invariants": properness, the Grundy bound, the
  * X = 1 reduction, the K_n / star / edgeless special cases and schedule
- * independence pin it).
+ * independence pin it).  The square graph is pinned against shortest-path
+ * distances from an independent library; the distance-2 colourings built on it
+ * by closed forms (path, star, 27-point mesh), brute force and invariants.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -559,4 +562,62 @@ int32_t orc_chromatic(int32_t n, const int32_t *rp, const int32_t *col) {
     }
     free(c);
     return k;
+}
+
+/* ------------------------------------------------------------------ */
+/* Distance-2 colouring (section 1: the distance-k problem asks that    */
+/* vertices joined by a path of at most k edges get different colours; */
+/* the paper expects its techniques to carry over to such variants).    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The square G^2 of G: u and w (u != w) are adjacent in G^2 iff G joins them
+ * by a path of one or two edges.  A distance-2 colouring of G is by
+ * definition a distance-1 colouring of G^2, so the distance-2 initial
+ * colouring, recolouring and validation are the distance-1 routines above
+ * applied to G^2 (the binding composes them).
+ *
+ * orc_square_count fills rp2[0..n] (rows of G^2, each sorted and free of
+ * duplicates) and returns nnz(G^2), or -1 when it exceeds int32 or memory
+ * runs out; orc_square_fill then writes col2[0..nnz(G^2)).
+ */
+static int64_t square_rows(int32_t n, const int32_t *rp, const int32_t *col, int32_t *rp2, int32_t *col2) {
+    int32_t *mark = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *row = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!mark || !row) { free(mark); free(row); return -1; }
+    for (int32_t v = 0; v < n; v++) mark[v] = -1;
+    int64_t total = 0;
+    if (rp2) rp2[0] = 0;
+    for (int32_t v = 0; v < n; v++) {
+        int32_t len = 0;
+        mark[v] = v; /* v itself is not its own neighbour */
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) {
+            int32_t u = col[e];
+            if (mark[u] != v) { mark[u] = v; row[len++] = u; }
+            for (int32_t f = rp[u]; f < rp[u + 1]; f++) {
+                int32_t w = col[f];
+                if (mark[w] != v) { mark[w] = v; row[len++] = w; }
+            }
+        }
+        if (col2) {
+            qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+            memcpy(col2 + total, row, (size_t)len * sizeof(int32_t));
+        }
+        total += len;
+        if (total > INT32_MAX) { free(mark); free(row); return -1; }
+        if (rp2) rp2[v + 1] = (int32_t)total;
+    }
+    free(mark);
+    free(row);
+    return total;
+}
+
+int64_t orc_square_count(int32_t n, const int32_t *rp, const int32_t *col, int32_t *rp2) {
+    if (n < 0) return -1;
+    return square_rows(n, rp, col, rp2, NULL);
+}
+
+int orc_square_fill(int32_t n, const int32_t *rp, const int32_t *col, int32_t *col2) {
+    if (n < 0) return ORC_ERR_ARG;
+    return square_rows(n, rp, col, NULL, col2) < 0 ? ORC_ERR_OOM : ORC_OK;
 }

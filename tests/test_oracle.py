@@ -518,3 +518,173 @@ def test_priority_orders_invariants():
                 assert (r.colors <= deg + X).all()
     with pytest.raises(RuntimeError):  # the two orders exclude each other
         oracle.init_color(gen.path(3), oracle.FIRST_FIT, 1, 1, flags=oracle.PRIO_LF | oracle.PRIO_NATURAL)
+
+
+# ---------------------------------------------------------------- distance-2 coloring
+
+def _dist2_pairs_scipy(g):
+    """Pairs u != w at graph distance 1 or 2, from scipy's shortest paths (an
+    independent library routine)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+
+    A = csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    D = shortest_path(A, unweighted=True)
+    return (D <= 2) & ~np.eye(g.n, dtype=bool)
+
+
+D2_FAMILIES = [
+    lambda: gen.path(11),
+    lambda: gen.cycle(9),
+    lambda: gen.star(7),
+    lambda: gen.complete(6),
+    lambda: gen.grid5(6, 5),
+    lambda: gen.mesh27(4),
+    lambda: gen.crown(5),
+    lambda: gen.er(60, 130, seed=4),
+    lambda: gen.er(80, 60, seed=5),
+    lambda: gen.rmat(6, 4, seed=2),
+    lambda: gen.empty(5),
+]
+
+
+@pytest.mark.parametrize("fam", range(len(D2_FAMILIES)))
+def test_square_matches_shortest_paths(fam):
+    g = D2_FAMILIES[fam]()
+    s = oracle.square(g)
+    ref = _dist2_pairs_scipy(g)
+    got = np.zeros((g.n, g.n), bool)
+    for v in range(g.n):
+        row = s.col[s.row_ptr[v]:s.row_ptr[v + 1]]
+        assert (np.diff(row) > 0).all(), "rows sorted, no duplicates"
+        got[v, row] = True
+    assert np.array_equal(got, ref)
+
+
+def test_validate_d2_bruteforce_and_injected():
+    rng = np.random.default_rng(8)
+    for fam in range(len(D2_FAMILIES)):
+        g = D2_FAMILIES[fam]()
+        near = _dist2_pairs_scipy(g)
+        c = rng.integers(1, 6, size=g.n).astype(np.int32)
+        c[rng.random(g.n) < 0.1] = 0
+        want = sum(1 for u in range(g.n) for w in range(u + 1, g.n) if near[u, w] and c[u] == c[w] > 0)
+        assert oracle.validate_d2(g, c) == (want, int((c <= 0).sum()))
+    # a proper distance-2 coloring, then one injected conflict at distance exactly 2 (path 0-1-2)
+    g = gen.path(9)
+    c = np.array([1 + i % 3 for i in range(9)], np.int32)
+    assert oracle.validate_d2(g, c) == (0, 0)
+    assert oracle.validate(g, c) == (0, 0)
+    c[0] = c[2]  # vertices 0 and 2 are two edges apart; vertex 1 keeps them distance-1 proper
+    assert oracle.validate_d2(g, c) == (1, 0) and oracle.validate(g, c) == (0, 0)
+
+
+def _structurally_orthogonal(g, c):
+    """Column compression view (sparse Jacobian / Hessian of the pattern A + I):
+    within every row i, the columns {i} and N(i) carry pairwise different colors."""
+    for i in range(g.n):
+        cols = np.concatenate(([i], g.neighbors(i)))
+        if len(set(c[cols].tolist())) != len(cols):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("fam", range(len(D2_FAMILIES)))
+def test_init_d2_invariants(fam):
+    g = D2_FAMILIES[fam]()
+    s = oracle.square(g)
+    d2deg = np.diff(s.row_ptr.astype(np.int64))
+    for flags in (0, oracle.FIXED_PRIORITY, oracle.PRIO_NATURAL):
+        for sel, X in ((oracle.FIRST_FIT, 1), (oracle.RANDOM_X, 3)):
+            r = oracle.init_color_d2(g, sel, X, 7, flags=flags)
+            c = r.colors
+            assert oracle.validate_d2(g, c) == (0, 0)
+            assert _structurally_orthogonal(g, c)
+            # Grundy-type bound over the distance-2 neighborhood
+            assert (c <= d2deg + X).all()
+            # every closed neighborhood is a clique of G^2
+            if g.n:
+                assert r.stats["num_colors"] >= g.max_deg + 1
+        # Random-X with X = 1 is First Fit, rounds included
+        a = oracle.init_color_d2(g, oracle.RANDOM_X, 1, 7, flags=flags)
+        b = oracle.init_color_d2(g, oracle.FIRST_FIT, 1, 7, flags=flags)
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+
+
+def test_init_d2_closed_forms():
+    FF = oracle.FIRST_FIT
+    # star: its square is K_{m+1}; natural order colors one vertex per round
+    r = oracle.init_color_d2(gen.star(9), FF, 1, 2, flags=oracle.PRIO_NATURAL)
+    assert r.colors.tolist() == list(range(1, 11)) and r.rounds == 10
+    # star with random priorities: m + 1 rounds, the largest remaining key takes color r + 1 in round r
+    m, seed = 9, 4
+    r = oracle.init_color_d2(gen.star(m), FF, 1, seed)
+    assert r.rounds == m + 1 and sorted(r.colors.tolist()) == list(range(1, m + 2))
+    left = set(range(m + 1))
+    for rnd in range(m + 1):
+        top = max(left, key=lambda v: oracle.key(seed, rnd, v))
+        assert r.colors[top] == rnd + 1
+        left.remove(top)
+    # path, natural order: colors repeat with period 3
+    assert oracle.init_color_d2(gen.path(14), FF, 1, 3, flags=oracle.PRIO_NATURAL).colors.tolist() == \
+        [1 + i % 3 for i in range(14)]
+    # 27-point mesh: distance 2 is Chebyshev distance <= 2; natural order gives
+    # the product of the path's period-3 pattern over the three axes (27 colors,
+    # the size of a 3x3x3 block, which is a clique of the square)
+    N = 7
+    c = oracle.init_color_d2(gen.mesh27(N), FF, 1, 3, flags=oracle.PRIO_NATURAL).colors
+    assert c.tolist() == [1 + x % 3 + 3 * (y % 3) + 9 * (z % 3) for z in range(N) for y in range(N) for x in range(N)]
+    # edgeless: distance 2 changes nothing
+    r = oracle.init_color_d2(gen.empty(6), FF, 1, 1)
+    assert r.colors.tolist() == [1] * 6 and r.rounds == 1
+    with pytest.raises(ValueError):
+        oracle.init_color_d2(gen.path(3), FF, 1, 1, flags=oracle.PRIO_LF)
+
+
+def test_init_d2_vs_chromatic_exhaustive_small():
+    """Never below the distance-2 chromatic number (brute force on tiny graphs)."""
+    rng = np.random.default_rng(12)
+    for _ in range(25):
+        n = int(rng.integers(3, 9))
+        pairs = [(u, w) for u in range(n) for w in range(u + 1, n) if rng.random() < 0.3]
+        g = gen.from_pairs(n, pairs)
+        near = _dist2_pairs_scipy(g)
+        chi = None
+        for k in range(1, n + 1):  # exhaustive search over all k^n assignments
+            for c in itertools.product(range(k), repeat=n):
+                if all(c[u] != c[w] for u in range(n) for w in range(u + 1, n) if near[u, w]):
+                    chi = k
+                    break
+            if chi:
+                break
+        r = oracle.init_color_d2(g, oracle.FIRST_FIT, 1, int(rng.integers(1, 99)))
+        assert r.stats["num_colors"] >= chi
+
+
+def test_recolor_d2_closed_form_and_invariants():
+    N = 6
+    g = gen.mesh27(N)
+    s = oracle.square(g)
+    c0 = np.array([1 + x % 3 + 3 * (y % 3) + 9 * (z % 3) for z in range(N) for y in range(N) for x in range(N)],
+                  np.int32)
+    assert oracle.validate_d2(g, c0, sq=s) == (0, 0)
+    for perm, seed in ((oracle.PERM_REVERSE, 1), (oracle.PERM_NONINC, 1), (oracle.PERM_RANDOM, 5)):
+        r = oracle.recolor_d2(g, c0, perm, seed, 0, sq=s)
+        rank = {int(c): i for i, c in enumerate(r.pi)}
+        # every distance-2 neighborhood holds a 3x3x3 block, i.e. all 26 other classes
+        assert r.colors.tolist() == [rank[int(c)] + 1 for c in c0]
+    # general graphs: proper, never more colors, rank bound
+    for fam in range(len(D2_FAMILIES)):
+        g = D2_FAMILIES[fam]()
+        c = oracle.init_color_d2(g, oracle.RANDOM_X, 4, 3).colors
+        k0 = oracle.count(c)[0]
+        for p, perm in enumerate((oracle.PERM_REVERSE, oracle.PERM_RANDOM, oracle.PERM_NONINC)):
+            r = oracle.recolor_d2(g, c, perm, 3, p)
+            assert oracle.validate_d2(g, r.colors) == (0, 0)
+            assert r.stats["num_colors"] <= k0
+            rank = {int(cc): i for i, cc in enumerate(r.pi)}
+            assert all(r.colors[v] <= rank[int(c[v])] + 1 for v in range(g.n))
+            c, k0 = r.colors, r.stats["num_colors"]
+    # a distance-1 coloring that is not a distance-2 coloring is rejected
+    g = gen.path(5)
+    assert oracle.recolor_d2(g, np.array([1, 2, 1, 2, 1], np.int32)).status == oracle.ERR_COLORING
