@@ -68,6 +68,7 @@ typedef enum gc_perm {
 #define GC_FLAG_FIXED_PRIORITY 1u /* one random total order for all rounds (round 0's keys) */
 #define GC_FLAG_PRIO_LF 2u        /* Largest First: larger degree wins a conflict, ties by round 0's keys */
 #define GC_FLAG_PRIO_NATURAL 4u   /* natural order: the smaller vertex id wins a conflict */
+#define GC_FLAG_DISTANCE2 8u      /* distance-2 coloring: neighborhoods are the vertices within two edges */
 
 /* Largest X accepted by GC_RANDOM_X. */
 #define GC_MAX_X 1024
@@ -187,6 +188,17 @@ gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream);
  * returns GC_ERR_NOT_CONVERGED after that many rounds, with the vertices
  * still uncolored at <= 0.  X must be in [1, GC_MAX_X] for GC_RANDOM_X and is
  * ignored for GC_FIRST_FIT.
+ *
+ * flags: GC_FLAG_FIXED_PRIORITY keeps round 0's keys in every round (the
+ * paper's fixed random order); GC_FLAG_PRIO_LF (Largest First: the larger
+ * degree wins, ties by round 0's keys) and GC_FLAG_PRIO_NATURAL (the smaller
+ * id wins) use those vertex-visit orders of section 2.1 as the conflict
+ * priority and exclude each other.  GC_FLAG_DISTANCE2 computes a distance-2
+ * coloring (section 1's distance-k problem with k = 2: vertices joined by a
+ * path of one or two edges differ), the same rounds with N(v) read as
+ * N(v) u N(N(v)) minus v; it takes rows shorter than 2^25 entries, and not
+ * GC_FLAG_PRIO_LF; st->round_degsum is left at 0 for it.  Unknown flags give
+ * GC_ERR_ARG.
  */
 gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
                         int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream);
@@ -206,6 +218,19 @@ gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X,
  */
 gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                      const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
+
+/*
+ * gc_recolor for a distance-2 coloring: the same class order, and every
+ * vertex of the current class takes the smallest positive color not held by
+ * a vertex within two edges recolored earlier in this pass.  colors_in must
+ * be a distance-2 coloring (vertices of one class are then never within two
+ * edges, so a class is recolored at once); any other input leaves
+ * colors_out unspecified (color range errors as gc_recolor).  Rows shorter
+ * than 2^25 entries (GC_ERR_ARG otherwise).  Synchronizes the stream once
+ * per pass to size the per-class launches.
+ */
+gc_status gc_recolor_d2(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                        const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
 
 /*
  * Asynchronous recoloring aRC (section 3): the classes of colors_in, in the
@@ -229,6 +254,16 @@ gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t se
  */
 gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
                       int64_t *uncolored, void *stream);
+
+/*
+ * Distance-2 check (section 1 with k = 2).  conflict_vertices: vertices v
+ * with colors[v] > 0 shared by some vertex within two edges of v;
+ * uncolored: vertices with colors[v] <= 0.  colors is a distance-2 coloring
+ * iff both are 0.  Rows shorter than 2^25 entries.  Host outputs;
+ * synchronizes.  Either pointer may be NULL.
+ */
+gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_vertices,
+                         int64_t *uncolored, void *stream);
 
 /*
  * num_colors: distinct positive values in colors[0..n); max_color: the

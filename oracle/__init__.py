@@ -310,8 +310,16 @@ def recolor_d2(g, colors, perm=PERM_REVERSE, seed=1, pass_=0, sq=None) -> Recolo
 
 
 def validate_d2(g, colors, sq=None) -> tuple[int, int]:
-    """(pairs u < w at distance 1 or 2 with equal positive colors, uncolored vertices)."""
-    return validate(square(g) if sq is None else sq, colors)
+    """(vertices sharing their positive color with some vertex at distance 1 or
+    2, vertices with color <= 0): a coloring is a distance-2 coloring iff both
+    are 0."""
+    s = square(g) if sq is None else sq
+    c = np.ascontiguousarray(colors, dtype=np.int64)[:g.n]
+    src = np.repeat(np.arange(g.n), np.diff(s.row_ptr.astype(np.int64)))
+    same = (c[src] == c[s.col]) & (c[src] > 0)
+    bad = np.zeros(g.n, bool)
+    bad[src[same]] = True
+    return int(bad.sum()), int((c <= 0).sum())
 
 
 def run_pipeline(g, select, X, seed, perm_schedule, max_rounds=0):

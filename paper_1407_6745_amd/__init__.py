@@ -21,6 +21,7 @@ PERM_NAMES = {"RV": PERM_REVERSE, "NI": PERM_NONINC, "ND": PERM_NONDEC, "RAND": 
 FLAG_FIXED_PRIORITY = 1
 FLAG_PRIO_LF = 2
 FLAG_PRIO_NATURAL = 4
+FLAG_DISTANCE2 = 8
 MAX_X = 1024
 
 
@@ -76,8 +77,13 @@ _SIGS = {
     "gc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
                                   ctypes.c_void_p]),
+    "gc_recolor_d2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
+                                     ctypes.c_void_p]),
     "gc_validate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_void_p,
                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "gc_validate_d2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "gc_count_colors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "gc_batch_color": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchArgs), ctypes.c_int32, ctypes.c_int32,
@@ -298,6 +304,25 @@ def recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=No
     return out, (_stats_dict(st) if st is not None else None)
 
 
+def recolor_d2(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,
+               ctx: Context | None = None, stream=None):
+    """One recoloring pass of a distance-2 coloring; `out` may be `colors`.
+    Returns (colors, stats or None)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty_like(colors)
+    _check_i32_dev(out, "out", g.n)
+    st = StatsArgs() if stats else None
+    rc = lib().gc_recolor_d2(ctx.handle, ctypes.byref(g), perm, seed, pass_, colors.data_ptr() if g.n else None,
+                             out.data_ptr() if g.n else None, ctypes.byref(st) if st is not None else None,
+                             _stream_ptr(stream))
+    ctx.check(rc, "gc_recolor_d2")
+    return out, (_stats_dict(st) if st is not None else None)
+
+
 def arc_recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,
                 ctx: Context | None = None, stream=None):
     """Asynchronous recoloring (aRC); `out` may be `colors`.  Returns (colors, stats or None)."""
@@ -325,6 +350,18 @@ def validate(row_ptr, col_idx, colors, ctx: Context | None = None, stream=None):
     rc = lib().gc_validate(ctx.handle, ctypes.byref(g), colors.data_ptr() if g.n else None, ctypes.byref(cf),
                            ctypes.byref(un), _stream_ptr(stream))
     ctx.check(rc, "gc_validate")
+    return cf.value, un.value
+
+
+def validate_d2(row_ptr, col_idx, colors, ctx: Context | None = None, stream=None):
+    """(vertices sharing their color with a vertex within two edges, uncolored vertices)."""
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    cf, un = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().gc_validate_d2(ctx.handle, ctypes.byref(g), colors.data_ptr() if g.n else None, ctypes.byref(cf),
+                              ctypes.byref(un), _stream_ptr(stream))
+    ctx.check(rc, "gc_validate_d2")
     return cf.value, un.value
 
 

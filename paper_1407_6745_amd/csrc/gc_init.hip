@@ -33,30 +33,6 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
     return randx ? (int32_t)gc_pick(s_color, w, X) + 1 : 1;
 }
 
-// Conflict priority of a round (the larger key keeps its color):
-//   PRIO_HASH:    the hash of (seed, v, round) (s_prio holds the round's stream);
-//   PRIO_RANK:    a per-vertex class rank, the earlier class first
-//                 (asynchronous recoloring);
-//   PRIO_LF:      Largest First: larger degree first, ties by round 0's hash;
-//   PRIO_NATURAL: smaller vertex id first.
-enum { PRIO_HASH = 0, PRIO_RANK = 1, PRIO_LF = 2, PRIO_NATURAL = 3 };
-
-struct Prio {
-    int mode;
-    uint32_t s_prio;
-    const int32_t *prank;  // PRIO_RANK
-    const int32_t *rp;     // PRIO_LF: row pointers
-};
-
-__device__ inline uint64_t round_prio(const Prio &p, int32_t v) {
-    switch (p.mode) {
-        case PRIO_RANK: return ~(uint32_t)p.prank[v];
-        case PRIO_LF: return ((uint64_t)(uint32_t)(p.rp[v + 1] - p.rp[v]) << 32) | gc_prio(p.s_prio, v);
-        case PRIO_NATURAL: return 0xFFFFFFFFu - (uint32_t)v;
-        default: return gc_prio(p.s_prio, v);
-    }
-}
-
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
@@ -607,10 +583,23 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
     if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
     if ((flags & GC_FLAG_PRIO_LF) && (flags & GC_FLAG_PRIO_NATURAL))
         return gc_fail(ctx, GC_ERR_ARG, "GC_FLAG_PRIO_LF and GC_FLAG_PRIO_NATURAL exclude each other");
+    const bool d2 = (flags & GC_FLAG_DISTANCE2) != 0;
+    if (d2 && (flags & GC_FLAG_PRIO_LF))
+        return gc_fail(ctx, GC_ERR_ARG, "GC_FLAG_PRIO_LF is not available with GC_FLAG_DISTANCE2");
+    if (flags & ~(GC_FLAG_FIXED_PRIORITY | GC_FLAG_PRIO_LF | GC_FLAG_PRIO_NATURAL | GC_FLAG_DISTANCE2))
+        return gc_fail(ctx, GC_ERR_ARG, "unknown flags 0x%x", flags);
     GC_HIP(hipSetDevice(ctx->device));
     if (g->n == 0) {
         if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
         return GC_OK;
+    }
+    if (d2) {
+        int32_t maxdeg = 0;
+        status = gc_graph_max_degree(ctx, g, (hipStream_t)stream, &maxdeg);
+        if (status) return status;
+        if (maxdeg >= GC_D2_MAX_DEGREE)
+            return gc_fail(ctx, GC_ERR_ARG, "distance-2 coloring takes rows below %d entries", GC_D2_MAX_DEGREE);
+        return gc_spec_rounds_d2(ctx, g, select, X, seed, max_rounds, flags, colors, st, (hipStream_t)stream);
     }
     return gc_spec_rounds(ctx, g, select, X, seed, max_rounds, flags, colors, st, (hipStream_t)stream, nullptr);
 }

@@ -127,6 +127,17 @@ gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32
 gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
                          uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank);
 
+// Distance-2 coloring (gc_d2.hip): the speculative rounds over distance-2
+// neighborhoods (arguments checked, n > 0), and the classes of one
+// recoloring pass, class r being list[off_host[spr * r], off_host[spr * r + spr]).
+gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
+                            uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s);
+gc_status gc_d2_classes(gc_ctx *ctx, const gc_csr *g, int32_t *C, int32_t k, const int32_t *off_host, int spr,
+                        hipStream_t s);
+// Longest row accepted by the distance-2 calls: 64 rows of this length still
+// sum below 2^31 entries.
+#define GC_D2_MAX_DEGREE (1 << 25)
+
 // Lanes per vertex of the recoloring walk: the walk_group knob, or when it is
 // 0, 8 for graphs whose rows are all shorter than 64 entries (full = false)
 // and the group knob otherwise.
@@ -180,6 +191,30 @@ __device__ inline uint32_t gc_prio(uint32_t s, int32_t v) { return gc_fmix32(s ^
 // Random-X offset in [0, X): multiply-shift of the vertex hash
 __device__ inline uint32_t gc_pick(uint32_t s, int32_t v, uint32_t X) {
     return (uint32_t)(((uint64_t)gc_fmix32(s ^ (uint32_t)v) * X) >> 32);
+}
+
+// Conflict priority of a round (the larger key keeps its color):
+//   PRIO_HASH:    the hash of (seed, v, round) (s_prio holds the round's stream);
+//   PRIO_RANK:    a per-vertex class rank, the earlier class first
+//                 (asynchronous recoloring);
+//   PRIO_LF:      Largest First: larger degree first, ties by round 0's hash;
+//   PRIO_NATURAL: smaller vertex id first.
+enum { PRIO_HASH = 0, PRIO_RANK = 1, PRIO_LF = 2, PRIO_NATURAL = 3 };
+
+struct Prio {
+    int mode;
+    uint32_t s_prio;
+    const int32_t *prank;  // PRIO_RANK
+    const int32_t *rp;     // PRIO_LF: row pointers
+};
+
+__device__ inline uint64_t round_prio(const Prio &p, int32_t v) {
+    switch (p.mode) {
+        case PRIO_RANK: return ~(uint32_t)p.prank[v];
+        case PRIO_LF: return ((uint64_t)(uint32_t)(p.rp[v + 1] - p.rp[v]) << 32) | gc_prio(p.s_prio, v);
+        case PRIO_NATURAL: return 0xFFFFFFFFu - (uint32_t)v;
+        default: return gc_prio(p.s_prio, v);
+    }
 }
 
 // ---------------------------------------------------------------------------

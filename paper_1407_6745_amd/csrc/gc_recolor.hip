@@ -36,6 +36,8 @@
 // coherent wait loop.
 #include "gc_internal.h"
 
+#include <vector>
+
 #define HIST_LDS 4096       // colors below this use the workgroup-private histogram
 #define HIST_BITS 12
 #define HIST_ITEMS 8        // vertices per thread of one histogram tile
@@ -813,8 +815,10 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     return GC_OK;
 }
 
-extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
-                                const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+// One pass; dist 2 recolors a distance-2 coloring (one launch per class over
+// the distance-2 neighborhoods).
+static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                              const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream, int dist) {
     gc_status status = gc_check_graph_args(ctx, g);
     if (status) return status;
     if (perm < 0 || perm > 3) return gc_fail(ctx, GC_ERR_ARG, "perm must be in [0, 3]");
@@ -827,11 +831,19 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
         return GC_OK;
     }
+    if (dist == 2) {
+        int32_t maxdeg = 0;
+        status = gc_graph_max_degree(ctx, g, s, &maxdeg);
+        if (status) return status;
+        if (maxdeg >= GC_D2_MAX_DEGREE)
+            return gc_fail(ctx, GC_ERR_ARG, "distance-2 recoloring takes rows below %d entries", GC_D2_MAX_DEGREE);
+    }
     const int block = 256;
     const int32_t deg_wave = ctx->tune.deg_wave;
     // the split bin exists in the persistent walk only
+    const bool flow = ctx->tune.walk_mode == 0 && dist == 1;
     bool full = false;
-    if (ctx->tune.walk_mode == 0) {
+    if (flow) {
         int32_t maxdeg = 0;
         status = gc_graph_max_degree(ctx, g, s, &maxdeg);
         if (status) return status;
@@ -868,8 +880,18 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         GC_TIMED(GC_K_SCATTER, s, k_split_prefix<<<4, 256, 0, s>>>(ctx->off, ctx->rows, split_len, ctx->hsub, ctx->scal));
         GC_LAUNCHED();
     }
-    if (ctx->tune.walk_mode == 0) {
+    if (flow) {
         status = launch_walk_flow(ctx, g, colors_out, full, s);
+        if (status) return status;
+    } else if (dist == 2) {
+        status = gc_sync_scalars(ctx, s);
+        if (status) return status;
+        if (ctx->hscal[S_ERR] & 1) return gc_fail(ctx, GC_ERR_COLORING, "input color outside [1, %d]", ctx->ccap);
+        const int32_t k = (int32_t)ctx->hscal[S_K];
+        std::vector<int32_t> off((size_t)NSEG_PER_RANK * k + 1);
+        GC_HIP(hipMemcpyAsync(off.data(), ctx->off, off.size() * 4, hipMemcpyDeviceToHost, s));
+        GC_HIP(hipStreamSynchronize(s));
+        status = gc_d2_classes(ctx, g, colors_out, k, off.data(), NSEG_PER_RANK, s);
         if (status) return status;
     } else {
         status = gc_sync_scalars(ctx, s);
@@ -899,6 +921,16 @@ extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint
         st->max_color = (int32_t)ctx->hscal[S_MAXC];
     }
     return GC_OK;
+}
+
+extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    return recolor_pass(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream, 1);
+}
+
+extern "C" gc_status gc_recolor_d2(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                   const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    return recolor_pass(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream, 2);
 }
 
 // ---------------------------------------------------------------------------
