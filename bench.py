@@ -208,6 +208,97 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_d2(args):
+    """Distance-2 coloring of the 27-point mesh 128^3 (the column coloring that
+    compresses a sparse Jacobian or Hessian with that stencil pattern)."""
+    import torch
+
+    import gen
+    import paper_1407_6745_amd as gc
+
+    X, passes, perm = 4, 5, gc.PERM_NONINC
+    t0 = time.perf_counter()
+    g = gen.mesh27(128)
+    deg = g.degrees
+    two_hop = int(deg.sum() + (deg[g.col].astype(np.int64)).sum())  # entries one sweep over N2 visits
+    log(f"[bench] mesh27_128 distance-2: n={g.n} nnz={g.nnz} two-hop entries per sweep={two_hop} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    colors = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ctx = gc.Context(g.n, g.nnz)
+    flags = gc.FLAG_DISTANCE2
+
+    def step(stats=False):
+        c, s0 = gc.init_color(rp, col, gc.RANDOM_X, X, args.seed, flags=flags, out=colors, stats=stats, ctx=ctx)
+        hist = [s0]
+        for p in range(passes):
+            c, sp = gc.recolor_d2(rp, col, c, perm, args.seed, p, out=c, stats=stats, ctx=ctx)
+            hist.append(sp)
+        return c, hist
+
+    c, hist = step(stats=True)
+    conflicts, uncolored = gc.validate_d2(rp, col, c, ctx=ctx)
+    colors_trace = [h["num_colors"] for h in hist]
+    rounds, round_sizes = hist[0]["rounds"], hist[0]["round_sizes"]
+    log(f"[bench] colors {colors_trace} rounds={rounds} valid={(conflicts, uncolored) == (0, 0)}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(passes + 2)]
+    ev[0].record(stream)
+    gc.init_color(rp, col, gc.RANDOM_X, X, args.seed, flags=flags, out=colors, stats=False, ctx=ctx)
+    ev[1].record(stream)
+    for p in range(passes):
+        gc.recolor_d2(rp, col, colors, perm, args.seed, p, out=colors, stats=False, ctx=ctx)
+        ev[p + 2].record(stream)
+    torch.cuda.synchronize()
+    t_init = ev[0].elapsed_time(ev[1])
+    t_pass = [ev[p + 1].elapsed_time(ev[p + 2]) for p in range(passes)]
+
+    ctx.set_timing(True, kinds=["walk"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt_walk = ctx.timing()
+    ctx.set_timing(True)
+    step()
+    kt = ctx.timing()
+    ctx.set_timing(False)
+    ms_step = el / args.steps * 1e3
+    m = g.nnz // 2
+    value = m * (passes + 1) / (ms_step / 1e3) / 1e9
+    # the class kernels of one pass sweep N2 once: two_hop entries, each a
+    # col_idx word and a color word, plus one row-pointer pair per neighbor slot
+    launches, walk_ms = kt_walk["walk"]
+    sweep_ms = walk_ms / (args.steps * passes)
+    sweep_bytes = 8 * two_hop + 8 * g.nnz + 8 * g.n
+    out = {
+        "metric": "GTEPS/pass", "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "3D 27-point mesh 128^3, distance-2 coloring: Random-X (X=4) initial coloring + "
+                               "5 NI recoloring passes", "n": g.n, "nnz": g.nnz, "m": m, "passes": passes,
+                   "two_hop_entries_per_sweep": two_hop, "seed": args.seed},
+        "colors": {"init": colors_trace[0], "after_pass": colors_trace[1:]},
+        "valid_distance2": (conflicts, uncolored) == (0, 0),
+        "init": {"rounds": rounds, "round_sizes": round_sizes, "ms": round(t_init, 4)},
+        "recolor_pass": {"ms": [round(t, 4) for t in t_pass], "mean_ms": round(sum(t_pass) / passes, 4),
+                         "class_kernels_ms": round(sweep_ms, 4),
+                         "two_hop_entries_per_s": round(two_hop / (sweep_ms / 1e3), 1),
+                         "gather_bytes": sweep_bytes,
+                         "gather_gbs": round(sweep_bytes / (sweep_ms / 1e3) / 1e9, 1)},
+        "kernel_ms_one_step": {k: {"launches": v[0], "total_ms": round(v[1], 4)} for k, v in kt.items() if v[0]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
@@ -344,7 +435,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mesh128", choices=sorted(WORKLOADS) + ["batch4096", "serve"])
+    ap.add_argument("--workload", default="mesh128", choices=sorted(WORKLOADS) + ["batch4096", "serve", "mesh128d2"])
     ap.add_argument("--graphs", type=int, default=4096, help="batch4096: number of graphs")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the arrival trace")
     ap.add_argument("--pool", type=int, default=48, help="serve: distinct request graphs")
@@ -381,6 +472,8 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "mesh128d2":
+        return run_d2(args)
 
     import torch
 

@@ -27,12 +27,13 @@
 #define D2_BLOCK 256
 #define D2_WORDS 64                // color-window bitmap words per wavefront (one per lane)
 #define D2_WINDOW (32 * D2_WORDS)  // colors per window
+#define D2_UNROLL 4
 
 // Calls f(w) for every w in N2(v) (repeats allowed), v's row being
 // col[e0, e1).  All 64 lanes must call it with the same v, e0, e1.  f returns
-// true to stop; the visit then ends after the current batch of 64 and the
-// call returns true (uniform over the wavefront).  Ids outside [0, n) are
-// skipped.
+// true to stop; the visit then ends after the current step (v's own chunk of
+// neighbors, or D2_UNROLL batches of 64 two-hop entries) and the call returns
+// true (uniform over the wavefront).  Ids outside [0, n) are skipped.
 template <class F>
 __device__ inline bool d2_visit(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz,
                                 int32_t n, int32_t v, int32_t e0, int32_t e1, F &&f) {
@@ -58,21 +59,26 @@ __device__ inline bool d2_visit(const int32_t *__restrict__ rp, const int32_t *_
         }
         const int32_t excl = incl - len;
         const int32_t total = __shfl(incl, 63);
-        for (int32_t t0 = 0; t0 < total; t0 += 64) {
-            const int32_t t = t0 + lane;
-            // last neighbor slot i < m whose range starts at or before t
-            int32_t lo = 0, hi = m - 1;
+        // D2_UNROLL batches of 64 entries per step: their loads are in flight together
+        for (int32_t t0 = 0; t0 < total; t0 += 64 * D2_UNROLL) {
+            int32_t w[D2_UNROLL];
 #pragma unroll
-            for (int step = 0; step < 6; step++) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (__shfl(excl, mid) <= t) lo = mid;
-                else hi = mid - 1;
+            for (int k = 0; k < D2_UNROLL; k++) {
+                const int32_t t = t0 + 64 * k + lane;
+                // last neighbor slot i < m whose range starts at or before t
+                int32_t lo = 0, hi = m - 1;
+#pragma unroll
+                for (int step = 0; step < 6; step++) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (__shfl(excl, mid) <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int32_t ra = __shfl(a, lo), rx = __shfl(excl, lo);
+                w[k] = t < total ? col[ra + (t - rx)] : v;
             }
-            const int32_t ra = __shfl(a, lo), rx = __shfl(excl, lo);
-            if (t < total) {
-                const int32_t w = col[ra + (t - rx)];
-                if (w != v && (uint32_t)w < (uint32_t)n) stop = f(w);
-            }
+#pragma unroll
+            for (int k = 0; k < D2_UNROLL; k++)
+                if (w[k] != v && (uint32_t)w[k] < (uint32_t)n) stop |= f(w[k]);
             if (__ballot(stop)) return true;
         }
     }
