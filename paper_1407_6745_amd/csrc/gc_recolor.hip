@@ -42,6 +42,7 @@
 #define HIST_BITS 12
 #define HIST_ITEMS 8        // vertices per thread of one histogram tile
 #define PERM_THREADS 1024
+#define ORDER_LDS 2048      // colors up to this run the class order on LDS copies
 #define SCATTER_BINS 1024   // segments below this reserve list ranges once per workgroup
 #define SCATTER_ITEMS 4
 #define WALK_BLOCK 256
@@ -135,9 +136,30 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
                                                                int32_t *cursor, int32_t *sbase,
                                                                unsigned long long *scal) {
     __shared__ int32_t lds[32];
+    // up to ORDER_LDS colors every step below runs on LDS copies of the class
+    // counts (one workgroup: global round trips would dominate)
+    __shared__ int32_t l_h[ORDER_LDS + 1], l_hw[ORDER_LDS + 1], l_hs[ORDER_LDS + 1], l_hsc[ORDER_LDS + 1];
+    __shared__ int32_t l_cls[ORDER_LDS + 1], l_pi[ORDER_LDS + 1];
     int32_t maxc = (int32_t)scal[S_MAXC];
     if (maxc > ccap) maxc = ccap;
-    const int32_t k = block_class_order(maxc, perm, s_perm, hist, cls, pi, rank, nullptr, nullptr, lds);
+    int32_t *H = hist, *HW = histw, *HS = hist_s, *HSC = hist_sc, *CL = cls, *PI = pi;
+    const bool local = maxc <= ORDER_LDS;
+    if (local) {
+        for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) {
+            l_h[c] = hist[c];
+            l_hw[c] = histw[c];
+            l_hs[c] = hist_s[c];
+            l_hsc[c] = hist_sc[c];
+        }
+        __syncthreads();
+        H = l_h;
+        HW = l_hw;
+        HS = l_hs;
+        HSC = l_hsc;
+        CL = l_cls;
+        PI = l_pi;
+    }
+    const int32_t k = block_class_order(maxc, perm, s_perm, H, CL, PI, rank, nullptr, nullptr, lds);
     const int32_t nseg = NSEG_PER_RANK * k;
     int32_t acc = 0, cacc = 0;
     for (int32_t base = 0; base < nseg; base += blockDim.x) {
@@ -145,17 +167,17 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
         int32_t sz = 0, ch = 0;
         if (g < nseg) {
             const int32_t s = g / NSEG_PER_RANK, b = g % NSEG_PER_RANK;
-            const int32_t c = pi[s];
+            const int32_t c = PI[s];
             const bool split = s <= hub_max_rank;
             if (b == 0) {
-                sz = hist[c] - histw[c] - hist_s[c];
+                sz = H[c] - HW[c] - HS[c];
                 ch = (sz + vpc - 1) / vpc;
             } else if (b == 1) {
-                sz = histw[c] + (split ? 0 : hist_s[c]);
+                sz = HW[c] + (split ? 0 : HS[c]);
                 ch = sz;
             } else if (split) {
-                sz = hist_s[c];
-                ch = hist_sc[c];
+                sz = HS[c];
+                ch = HSC[c];
             }
         }
         int32_t tot, ctot;
@@ -174,7 +196,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
     for (int32_t base = 0; base < k; base += blockDim.x) {
         const int32_t s = base + (int32_t)threadIdx.x;
         int32_t sz = 0;
-        if (s < k && s <= hub_max_rank) sz = hist_s[pi[s]];
+        if (s < k && s <= hub_max_rank) sz = HS[PI[s]];
         int32_t tot;
         const int32_t ex = block_exclusive_scan(sz, &tot, lds);
         if (s < k) sbase[s] = hacc + ex;
@@ -185,6 +207,8 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
         coff[nseg] = cacc;
         scal[S_K] = (unsigned long long)k;
     }
+    if (local)
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) pi[i] = l_pi[i];
     __syncthreads();
     for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) {
         hist[c] = 0;
