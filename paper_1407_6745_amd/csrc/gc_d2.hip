@@ -15,6 +15,17 @@
 // which changes no result: colors go into a bitmap, and a conflict is "some
 // neighbor".
 //
+// Color masks.  M[u] (D2_MW words) holds the colors 1 .. D2_MCOLORS settled
+// in N(u) u {u}: colors committed by the rounds so far, or the new colors of
+// the recoloring pass so far.  The OR of M[u] over u in N(v) is then exactly
+// the set of settled colors of N2(v) in that range, so the selections read
+// deg(v) masks instead of the sum of the neighbors' degrees; a vertex that
+// settles ORs its color into the masks of N(v) u {v}.  Selections run with
+// G lanes per vertex; a vertex whose (j+1)-th free color lies above
+// D2_MCOLORS scans N2(v) itself, window by window.  In a recoloring pass
+// two vertices of one class are never within two edges, so no vertex reads
+// a mask that another vertex of its class is writing.
+//
 // Encoding of C during the rounds is the distance-1 one: C[v] > 0 committed,
 // C[v] < 0 tentative (or a loser waiting for the next round).  A tentative
 // color T_v avoids every color committed in N2(v) before the round, so a w in
@@ -25,9 +36,9 @@
 #include <vector>
 
 #define D2_BLOCK 256
-#define D2_WORDS 64                // color-window bitmap words per wavefront (one per lane)
-#define D2_WINDOW (32 * D2_WORDS)  // colors per window
 #define D2_UNROLL 4
+#define D2_MW 2                    // mask words per vertex
+#define D2_MCOLORS (64 * D2_MW)    // colors tracked by the masks
 
 // Calls f(w) for every w in N2(v) (repeats allowed), v's row being
 // col[e0, e1).  All 64 lanes must call it with the same v, e0, e1.  f returns
@@ -85,49 +96,6 @@ __device__ inline bool d2_visit(const int32_t *__restrict__ rp, const int32_t *_
     return false;
 }
 
-// (j+1)-th smallest positive color held by no w in N2(v) as a positive value
-// of C.  bits: the wavefront's D2_WORDS words of LDS.  Windows of D2_WINDOW
-// colors; a window without enough free colors rescans N2(v) for the next.
-__device__ inline int32_t d2_select(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz,
-                                    int32_t n, const int32_t *C, int32_t v, int32_t e0, int32_t e1, uint32_t j,
-                                    uint32_t *bits) {
-    const int lane = __lane_id();
-    uint32_t base = 1;
-    for (;;) {
-        bits[lane] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        d2_visit(rp, col, nnz, n, v, e0, e1, [&](int32_t w) {
-            const int32_t c = C[w];
-            const uint32_t d = (uint32_t)c - base;  // colors below the window wrap to large values
-            if (c > 0 && d < (uint32_t)D2_WINDOW) atomicOr(&bits[d >> 5], 1u << (d & 31));
-            return false;
-        });
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t fw = ~bits[lane];
-        const uint32_t f = (uint32_t)__popc(fw);
-        uint32_t incl = f;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        const uint32_t tot = __shfl(incl, 63);
-        if (j < tot) {
-            const uint32_t ex = incl - f;
-            const bool mine = ex <= j && j < incl;
-            const unsigned long long b = __ballot(mine);
-            const int src = __ffsll((long long)b) - 1;
-            uint32_t pos = 0;
-            if (mine) pos = nth_set_bit((uint64_t)fw, j - ex);
-            pos = __shfl(pos, src);
-            return (int32_t)(base + 32u * (uint32_t)src + pos);
-        }
-        j -= tot;
-        base += (uint32_t)D2_WINDOW;
-    }
-}
-
 // Per-wavefront queue of losers in LDS: one global atomic per 64 entries.
 struct WaveQueue {
     int32_t *q;  // 64 LDS slots of the wavefront
@@ -153,6 +121,90 @@ struct WaveQueue {
     }
 };
 
+// ORs color c into M[u] for u in N(v) u {v} (colors above D2_MCOLORS are
+// not tracked).  G lanes, gl = lane in the group.  ATOMIC = false when no
+// other vertex can write the same masks during the launch: in a recoloring
+// pass, N(u) u {u} holds at most one vertex of each class of the (distance-2)
+// input coloring, so one class launch has a single writer per mask.
+template <int G, bool ATOMIC>
+__device__ inline void d2_publish(const int32_t *__restrict__ col, int32_t e0, int32_t e1, int32_t n,
+                                  unsigned long long *M, int32_t v, int32_t c, int gl) {
+    if (c < 1 || c > D2_MCOLORS) return;
+    const unsigned long long bit = 1ull << ((c - 1) & 63);
+    const int w = (c - 1) >> 6;
+    auto put = [&](int32_t u) {
+        unsigned long long *p = &M[(size_t)D2_MW * u + w];
+        if (ATOMIC) atomicOr(p, bit);
+        else *p |= bit;
+    };
+    if (gl == 0) put(v);
+    for (int32_t e = e0 + gl; e < e1; e += G) {
+        const int32_t u = col[e];
+        if ((uint32_t)u < (uint32_t)n) put(u);
+    }
+}
+
+// (j+1)-th smallest color free in the OR of M[u] over u in N(v), among
+// 1 .. D2_MCOLORS; 0 when there are not that many (then *jrem = j minus the
+// free colors of that range).  G lanes, same result in each.
+template <int G>
+__device__ inline int32_t d2_mask_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, int32_t n,
+                                         const unsigned long long *__restrict__ M, uint32_t j, int gl,
+                                         uint32_t *jrem) {
+    static_assert(D2_MW == 2, "two mask words");
+    unsigned long long f0 = 0, f1 = 0;
+#pragma unroll 4
+    for (int32_t e = e0 + gl; e < e1; e += G) {
+        const int32_t u = col[e];
+        if ((uint32_t)u < (uint32_t)n) {
+            const ulonglong2 m = *reinterpret_cast<const ulonglong2 *>(M + (size_t)D2_MW * u);
+            f0 |= m.x;
+            f1 |= m.y;
+        }
+    }
+    f0 = ~group_or_u64<G>(f0);
+    f1 = ~group_or_u64<G>(f1);
+    const uint32_t c0 = (uint32_t)__popcll(f0);
+    if (j < c0) return 1 + (int32_t)nth_set_bit(f0, j);
+    j -= c0;
+    const uint32_t c1 = (uint32_t)__popcll(f1);
+    if (j < c1) return 65 + (int32_t)nth_set_bit(f1, j);
+    *jrem = j - c1;
+    return 0;
+}
+
+// (j+1)-th smallest color >= base held by no w in N2(v) as a positive value
+// of C, by scanning N2(v) (each lane walks the rows of its neighbors), 64
+// colors per window.  G lanes, same result in each.
+template <int G>
+__device__ inline int32_t d2_scan_select(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz,
+                                         int32_t n, const int32_t *C, int32_t v, int32_t e0, int32_t e1,
+                                         uint32_t base, uint32_t j, int gl) {
+    auto mark = [&](unsigned long long &m, int32_t c) {
+        const uint32_t d = (uint32_t)c - base;
+        if (c > 0 && d < 64u) m |= 1ull << d;
+    };
+    for (;;) {
+        unsigned long long m = 0;
+        for (int32_t e = e0 + gl; e < e1; e += G) {
+            const int32_t u = col[e];
+            if ((uint32_t)u >= (uint32_t)n) continue;
+            mark(m, C[u]);
+            int32_t a, b;
+            row_range(rp, u, nnz, a, b);
+            for (int32_t f = a; f < b; f++) {
+                const int32_t w = col[f];
+                if (w != v && (uint32_t)w < (uint32_t)n) mark(m, C[w]);
+            }
+        }
+        const unsigned long long fr = ~group_or_u64<G>(m);
+        const uint32_t cnt = (uint32_t)__popcll(fr);
+        if (j < cnt) return (int32_t)(base + nth_set_bit(fr, j));
+        j -= cnt;
+        base += 64u;
+    }
+}
+
 __device__ inline int32_t d2_round0_color(uint32_t s_color, int32_t w, uint32_t X, int randx) {
     return randx ? (int32_t)gc_pick(s_color, w, X) + 1 : 1;
 }
@@ -162,8 +214,9 @@ __device__ inline int32_t d2_round0_color(uint32_t s_color, int32_t w, uint32_t 
 // vertex of N2(v) with the same T has a larger key.
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_round0(const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                                                        int32_t *C, Prio pr, uint32_t s_color, uint32_t X, int randx,
-                                                        int32_t *wl_out, unsigned long long *c_out) {
+                                                        int32_t *C, unsigned long long *M, Prio pr, uint32_t s_color,
+                                                        uint32_t X, int randx, int32_t *wl_out,
+                                                        unsigned long long *c_out) {
     __shared__ int32_t qs[D2_BLOCK];
     const int wpb = D2_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -178,29 +231,33 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_round0(const int32_t *__restric
         });
         if (__lane_id() == 0) C[v] = lose ? -T : T;
         if (lose) lq.push(v, wl_out, c_out);
+        else d2_publish<64, true>(col, e0, e1, n, M, v, T, __lane_id());
     }
     lq.flush(wl_out, c_out);
 }
 
 // Rounds >= 1, assign step: every vertex of the worklist takes the (j+1)-th
-// smallest color free in N2(v) among the colors committed before the round.
+// smallest color free in N2(v) among the colors committed before the round
+// (G lanes per vertex, from the masks).
+template <int G>
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_assign(const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                                                        int32_t *C, const int32_t *__restrict__ wl,
+                                                        int32_t *C, const unsigned long long *__restrict__ M,
+                                                        const int32_t *__restrict__ wl,
                                                         const unsigned long long *__restrict__ wc, uint32_t s_color,
                                                         uint32_t X, int randx) {
-    __shared__ uint32_t bits_all[D2_BLOCK / 64 * D2_WORDS];
-    const int wpb = D2_BLOCK / 64;
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint32_t *bits = bits_all + wib * D2_WORDS;
+    const int gpb = D2_BLOCK / G;
+    const int gl = threadIdx.x & (G - 1);
     const int64_t cnt = (int64_t)*wc;
-    for (int64_t i = (int64_t)blockIdx.x * wpb + wib; i < cnt; i += (int64_t)gridDim.x * wpb) {
-        const int32_t v = __builtin_amdgcn_readfirstlane(wl[i]);
+    for (int64_t i = (int64_t)blockIdx.x * gpb + threadIdx.x / G; i < cnt; i += (int64_t)gridDim.x * gpb) {
+        const int32_t v = wl[i];
         int32_t e0, e1;
         row_range(rp, v, nnz, e0, e1);
         const uint32_t j = randx ? gc_pick(s_color, v, X) : 0u;
-        const int32_t c = d2_select(rp, col, nnz, n, C, v, e0, e1, j, bits);
-        if (__lane_id() == 0) C[v] = -c;
+        uint32_t jr = 0;
+        int32_t c = d2_mask_select<G>(col, e0, e1, n, M, j, gl, &jr);
+        if (c == 0) c = d2_scan_select<G>(rp, col, nnz, n, C, v, e0, e1, D2_MCOLORS + 1, jr, gl);
+        if (gl == 0) C[v] = -c;
     }
 }
 
@@ -209,8 +266,9 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_assign(const int32_t *__restric
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_detect(const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, int64_t nnz, int32_t n,
                                                         int32_t *C, const int32_t *__restrict__ wl,
-                                                        const unsigned long long *__restrict__ wc, Prio pr,
-                                                        int32_t *wl_out, unsigned long long *c_out) {
+                                                        const unsigned long long *__restrict__ wc,
+                                                        unsigned long long *M, Prio pr, int32_t *wl_out,
+                                                        unsigned long long *c_out) {
     __shared__ int32_t qs[D2_BLOCK];
     const int wpb = D2_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -228,25 +286,29 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_detect(const int32_t *__restric
         });
         if (!lose && __lane_id() == 0) C[v] = T;
         if (lose) lq.push(v, wl_out, c_out);
+        else d2_publish<64, true>(col, e0, e1, n, M, v, T, __lane_id());
     }
     lq.flush(wl_out, c_out);
 }
 
-// One class of a recoloring pass: every vertex of rank s takes the smallest
-// color free among the new colors (positive values) of N2(v).
+// One class of a recoloring pass: every vertex of the class takes the
+// smallest color free among the new colors of N2(v) (G lanes per vertex, from
+// the masks) and publishes it.
+template <int G>
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_class(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C,
+                                                       int64_t nnz, int32_t n, int32_t *C, unsigned long long *M,
                                                        const int32_t *__restrict__ list, int32_t a, int32_t b) {
-    __shared__ uint32_t bits_all[D2_BLOCK / 64 * D2_WORDS];
-    const int wpb = D2_BLOCK / 64;
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint32_t *bits = bits_all + wib * D2_WORDS;
-    for (int32_t i = a + blockIdx.x * wpb + wib; i < b; i += gridDim.x * wpb) {
-        const int32_t v = __builtin_amdgcn_readfirstlane(list[i]);
+    const int gpb = D2_BLOCK / G;
+    const int gl = threadIdx.x & (G - 1);
+    for (int32_t i = a + blockIdx.x * gpb + (int32_t)threadIdx.x / G; i < b; i += gridDim.x * gpb) {
+        const int32_t v = list[i];
         int32_t e0, e1;
         row_range(rp, v, nnz, e0, e1);
-        const int32_t c = d2_select(rp, col, nnz, n, C, v, e0, e1, 0u, bits);
-        if (__lane_id() == 0) C[v] = c;
+        uint32_t jr = 0;
+        int32_t c = d2_mask_select<G>(col, e0, e1, n, M, 0u, gl, &jr);
+        if (c == 0) c = d2_scan_select<G>(rp, col, nnz, n, C, v, e0, e1, D2_MCOLORS + 1, jr, gl);
+        if (gl == 0) C[v] = c;
+        d2_publish<G, false>(col, e0, e1, n, M, v, c, gl);
     }
 }
 
@@ -275,10 +337,28 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_validate(const int32_t *__restr
     }
 }
 
-static int d2_grid(const gc_ctx *ctx, int64_t items) {
+// workgroups for `items` vertices at `per_vertex` lanes each
+static int d2_grid(const gc_ctx *ctx, int64_t items, int per_vertex = 64) {
     const int64_t cap = (int64_t)ctx->num_cu * ctx->tune.grid_per_cu;
-    const int64_t want = (items + D2_BLOCK / 64 - 1) / (D2_BLOCK / 64);
+    const int64_t per = D2_BLOCK / per_vertex;
+    const int64_t want = (items + per - 1) / per;
     return (int)(want < 1 ? 1 : (want > cap ? cap : want));
+}
+
+// Lanes per vertex of the mask selections: 8, or a wavefront when some row is
+// longer than 64 entries.
+static int d2_group(int32_t maxdeg) { return maxdeg > 64 ? 64 : 8; }
+
+static gc_status d2_masks(gc_ctx *ctx, int32_t n, hipStream_t s) {
+    if (!ctx->d2mask) {
+        GC_HIP(hipStreamSynchronize(s));
+        if (hipMalloc((void **)&ctx->d2mask, (size_t)ctx->max_n * D2_MW * 8 + 256) != hipSuccess) {
+            ctx->d2mask = nullptr;
+            return gc_fail(ctx, GC_ERR_OOM, "distance-2 color masks (%lld vertices)", (long long)ctx->max_n);
+        }
+    }
+    GC_HIP(hipMemsetAsync(ctx->d2mask, 0, (size_t)n * D2_MW * 8, s));
+    return GC_OK;
 }
 
 gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
@@ -296,9 +376,16 @@ gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_
     unsigned long long *cnt = ctx->scal + S_WL;
     std::vector<int64_t> sizes;
     sizes.push_back(n);
+    int32_t maxdeg = 0;
+    status = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (status) return status;
+    const int G = d2_group(maxdeg);
+    status = d2_masks(ctx, n, s);
+    if (status) return status;
+    unsigned long long *M = ctx->d2mask;
     GC_HIP(hipMemsetAsync(cnt, 0, 2 * 8, s));
     GC_TIMED(GC_K_ROUND0, s, k_d2_round0<<<d2_grid(ctx, n), D2_BLOCK, 0, s>>>(
-                                 g->row_ptr, g->col_idx, g->nnz, n, colors, prio_of(0),
+                                 g->row_ptr, g->col_idx, g->nnz, n, colors, M, prio_of(0),
                                  gc_stream_value(seed, GC_TAG_COLOR, 0), (uint32_t)X, randx, ctx->wl[0], cnt));
     GC_LAUNCHED();
     int32_t r = 1, cur = 0;
@@ -312,15 +399,19 @@ gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_
         sizes.push_back(tot);
         const int nxt = cur ^ 1;
         GC_HIP(hipMemsetAsync(cnt + nxt, 0, 8, s));
-        const int grid = d2_grid(ctx, tot);
-        GC_TIMED(GC_K_ASSIGN, s, k_d2_assign<<<grid, D2_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
-                                                                       ctx->wl[cur], cnt + cur,
-                                                                       gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r),
-                                                                       (uint32_t)X, randx));
+        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
+        if (G == 8)
+            GC_TIMED(GC_K_ASSIGN, s, k_d2_assign<8><<<d2_grid(ctx, tot, 8), D2_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, M, ctx->wl[cur], cnt + cur, sc,
+                                         (uint32_t)X, randx));
+        else
+            GC_TIMED(GC_K_ASSIGN, s, k_d2_assign<64><<<d2_grid(ctx, tot, 64), D2_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, M, ctx->wl[cur], cnt + cur, sc,
+                                         (uint32_t)X, randx));
         GC_LAUNCHED();
-        GC_TIMED(GC_K_DETECT, s, k_d2_detect<<<grid, D2_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
-                                                                       ctx->wl[cur], cnt + cur, prio_of(r),
-                                                                       ctx->wl[nxt], cnt + nxt));
+        GC_TIMED(GC_K_DETECT, s, k_d2_detect<<<d2_grid(ctx, tot), D2_BLOCK, 0, s>>>(
+                                     g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[cur], cnt + cur, M,
+                                     prio_of(r), ctx->wl[nxt], cnt + nxt));
         GC_LAUNCHED();
         cur = nxt;
         r++;
@@ -348,11 +439,22 @@ gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_
 
 gc_status gc_d2_classes(gc_ctx *ctx, const gc_csr *g, int32_t *C, int32_t k, const int32_t *off_host, int seg_per_rank,
                         hipStream_t s) {
+    int32_t maxdeg = 0;
+    gc_status status = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (status) return status;
+    const int G = d2_group(maxdeg);
+    status = d2_masks(ctx, g->n, s);
+    if (status) return status;
+    unsigned long long *M = ctx->d2mask;
     for (int32_t r = 0; r < k; r++) {
         const int32_t a = off_host[seg_per_rank * r], b = off_host[seg_per_rank * r + seg_per_rank];
         if (b <= a) continue;
-        GC_TIMED(GC_K_WALK, s, k_d2_class<<<d2_grid(ctx, b - a), D2_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
-                                                                                   g->n, C, ctx->list, a, b));
+        if (G == 8)
+            GC_TIMED(GC_K_WALK, s, k_d2_class<8><<<d2_grid(ctx, b - a, 8), D2_BLOCK, 0, s>>>(
+                                       g->row_ptr, g->col_idx, g->nnz, g->n, C, M, ctx->list, a, b));
+        else
+            GC_TIMED(GC_K_WALK, s, k_d2_class<64><<<d2_grid(ctx, b - a, 64), D2_BLOCK, 0, s>>>(
+                                       g->row_ptr, g->col_idx, g->nnz, g->n, C, M, ctx->list, a, b));
         GC_LAUNCHED();
     }
     return GC_OK;

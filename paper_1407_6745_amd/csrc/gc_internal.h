@@ -74,6 +74,7 @@ struct gc_ctx {
     unsigned long long *scal;  // S_COUNT device scalars
     unsigned long long *hscal; // pinned host mirror
     struct gc_timer *timer;  // kernel timing (NULL when off)
+    unsigned long long *d2mask;  // distance-2 coloring: per-vertex color masks (allocated on first use, max_n * 2 words)
     int32_t *bws;            // batched coloring: per-workgroup workspace (grown on demand)
     int64_t bws_bytes;
     char err[512];

@@ -89,11 +89,35 @@ def test_d2_mesh_natural_closed_form(gc):
     assert c.cpu().numpy().tolist() == want and st["num_colors"] == 27
 
 
+def _recolor_equal(gc, name, g, c, rc, passes, seed=3):
+    rp, col = dev(g)
+    for p, perm in enumerate([gc.PERM_REVERSE, gc.PERM_RANDOM, gc.PERM_NONINC][:passes]):
+        c, st = gc.recolor_d2(rp, col, c, perm, seed, p, out=c)
+        r = oracle.recolor_d2(g, rc, perm, seed, p, sq=square(name, g))
+        got = c.cpu().numpy()
+        assert np.array_equal(got, r.colors), f"{name} pass {p}: {int((got != r.colors).sum())} differ"
+        rc = r.colors
+    return rc
+
+
 def test_d2_beyond_one_window(gc):
-    """Random-X with X = 1024 on RMAT: colors past 2048, the span of one selection window."""
+    """Random-X with X = 1024 on RMAT (rows past 64 entries: a wavefront per
+    vertex): colors far past the masks' range, in the rounds and the passes."""
     g = gen.rmat(11, 16, seed=5)
-    _, ref = _init_equal(gc, "rmat16", g, gc.RANDOM_X, 1024, 3)
-    assert ref.stats["max_color"] > 2048
+    c, ref = _init_equal(gc, "rmat16", g, gc.RANDOM_X, 1024, 3)
+    assert ref.stats["max_color"] > 2048 and g.max_deg > 64
+    rc = _recolor_equal(gc, "rmat16", g, c, ref.colors, 3)
+    assert rc.max() > 128
+
+
+def test_d2_beyond_masks_short_rows(gc):
+    """Rows of at most 64 entries (8 lanes per vertex) with colors above the
+    masks' 128: the in-group scan of the distance-2 neighborhood."""
+    g = gen.rgg(3000, 0.06, 2)
+    assert g.max_deg <= 64
+    c, ref = _init_equal(gc, "rgg64", g, gc.RANDOM_X, 64, 3)
+    assert ref.stats["max_color"] > 128
+    _recolor_equal(gc, "rgg64", g, c, ref.colors, 3)
 
 
 def test_d2_small_grid(gc):
