@@ -228,6 +228,8 @@ def run_d2(args):
     col = torch.from_numpy(g.col).to(dev)
     colors = torch.empty(g.n, dtype=torch.int32, device=dev)
     ctx = gc.Context(g.n, g.nnz)
+    if args.tune:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tune.split(","))})
     flags = gc.FLAG_DISTANCE2
 
     def step(stats=False):
@@ -284,7 +286,7 @@ def run_d2(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "3D 27-point mesh 128^3, distance-2 coloring: Random-X (X=4) initial coloring + "
                                "5 NI recoloring passes", "n": g.n, "nnz": g.nnz, "m": m, "passes": passes,
-                   "two_hop_entries_per_sweep": two_hop, "seed": args.seed},
+                   "two_hop_entries_per_sweep": two_hop, "seed": args.seed, "tuning": ctx.tuning},
         "colors": {"init": colors_trace[0], "after_pass": colors_trace[1:]},
         "valid_distance2": (conflicts, uncolored) == (0, 0),
         "init": {"rounds": rounds, "round_sizes": round_sizes, "ms": round(t_init, 4)},

@@ -122,7 +122,10 @@ typedef struct gc_tuning {
                               64 * hub_words and above keep their long rows on one wavefront */
     int32_t walk_group;    /* lanes per vertex in the recoloring walk (power of two, 1..64); 0 = automatic:
                               8 when every row is shorter than 64 entries, else `group` */
-    int32_t reserved;
+    int32_t d2_star;       /* distance-2 detect step: 0 = automatic (per-neighborhood marking for rounds
+                              of more than n / 8 vertices when no row exceeds 64 entries, else a scan of
+                              each vertex's distance-2 neighborhood), 1 = marking in every round, -1 = the
+                              scan in every round; results are the same */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);

@@ -48,10 +48,10 @@ class Tuning(ctypes.Structure):
                 ("grid_per_cu", ctypes.c_int32), ("walk_mode", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
                 ("check_resident", ctypes.c_int32), ("deg_split", ctypes.c_int32), ("split_len", ctypes.c_int32),
                 ("hub_words", ctypes.c_int32), ("walk_group", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("d2_star", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
-                 "split_len", "hub_words", "walk_group")
+                 "split_len", "hub_words", "walk_group", "d2_star")
 
 
 class BatchArgs(ctypes.Structure):

@@ -79,6 +79,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.split_len = 1024;
     ctx->tune.hub_words = GC_HUB_WORDS;
     ctx->tune.walk_group = 0;
+    ctx->tune.d2_star = 0;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -239,8 +240,8 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->grid_per_cu < 1 || t->grid_per_cu > 64) return gc_fail(ctx, GC_ERR_ARG, "grid_per_cu must be in [1, 64]");
     if (t->walk_group < 0 || t->walk_group > 64 || (t->walk_group & (t->walk_group - 1)))
         return gc_fail(ctx, GC_ERR_ARG, "walk_group must be 0 or a power of two in [1, 64]");
+    if (t->d2_star < -1 || t->d2_star > 1) return gc_fail(ctx, GC_ERR_ARG, "d2_star must be -1, 0 or 1");
     ctx->tune = *t;
-    ctx->tune.reserved = 0;
     return GC_OK;
 }
 

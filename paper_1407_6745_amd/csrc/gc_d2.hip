@@ -96,7 +96,10 @@ __device__ inline bool d2_visit(const int32_t *__restrict__ rp, const int32_t *_
     return false;
 }
 
-// Per-wavefront queue of losers in LDS: one global atomic per 64 entries.
+// Losers of a round collect in LDS and go to the next worklist with one
+// global atomic per flush: per wavefront (64 slots) in the wavefront-per-vertex
+// kernels, whose vertices finish at different times; per workgroup in the
+// group kernels (loops workgroup-uniform around the push and flush calls).
 struct WaveQueue {
     int32_t *q;  // 64 LDS slots of the wavefront
     int32_t len = 0;
@@ -119,6 +122,11 @@ struct WaveQueue {
         __builtin_amdgcn_wave_barrier();
         if (++len == 64) flush(wl, count);
     }
+};
+
+struct LoserQueue {
+    int32_t buf[GC_QCAP];
+    int32_t cnt, base;
 };
 
 // ORs color c into M[u] for u in N(v) u {v} (colors above D2_MCOLORS are
@@ -312,6 +320,133 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_class(const int32_t *__restrict
     }
 }
 
+// Detect step of a large round (rows of at most D2_STAR_ROW entries), in two
+// launches.  v loses iff, for some u in N(v) u {v}, another member of
+// S(u) = N(u) u {u} holds v's tentative color with a larger key (every w of
+// N2(v) lies in such an S(u) together with v).  k_d2_mark: one group per
+// vertex u stages (color, key) of the tentative members of S(u) in LDS and
+// marks the members so dominated (1).  A row longer than D2_STAR_ROW does
+// not fit the stage: its tentative members are marked for a recheck (2)
+// instead.  k_d2_commit: unmarked vertices of the round commit and publish,
+// marked ones clear the mark and go to the next round, and those marked for
+// a recheck scan N2(v) themselves.  Marks may overwrite each other: a 1 is
+// only ever written for a vertex that loses, and a 2 leads to the exact scan.
+#define D2_STAR_ROW 64
+
+// Does some w in N2(v) hold |C[w]| = T with a larger key than pv?  Each lane
+// walks the rows of its neighbors; G lanes, same result in each.
+template <int G>
+__device__ inline bool d2_scan_conflict(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz,
+                                        int32_t n, const int32_t *C, const Prio &pr, int32_t v, int32_t e0,
+                                        int32_t e1, int32_t T, uint64_t pv, int gl) {
+    auto hit = [&](int32_t w) {
+        const int32_t c = C[w];
+        return (c == T || c == -T) && round_prio(pr, w) > pv;
+    };
+    bool found = false;
+    for (int32_t e = e0 + gl; e < e1 && !found; e += G) {
+        const int32_t u = col[e];
+        if ((uint32_t)u >= (uint32_t)n) continue;
+        found = hit(u);
+        int32_t a, b;
+        row_range(rp, u, nnz, a, b);
+        for (int32_t f = a; f < b && !found; f++) {
+            const int32_t w = col[f];
+            if (w != v && (uint32_t)w < (uint32_t)n) found = hit(w);
+        }
+    }
+    return group_or_u64<G>(found ? 1ull : 0ull) != 0;
+}
+
+template <int G>
+__global__ void __launch_bounds__(D2_BLOCK) k_d2_mark(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                      int64_t nnz, int32_t n, const int32_t *__restrict__ C, Prio pr,
+                                                      uint8_t *lost) {
+    __shared__ unsigned long long tab[D2_BLOCK / G][D2_STAR_ROW + 1];
+    const int gpb = D2_BLOCK / G;
+    const int gid = threadIdx.x / G, gl = threadIdx.x & (G - 1);
+    unsigned long long *t = tab[gid];
+    for (int32_t u = blockIdx.x * gpb + gid; u < n; u += gridDim.x * gpb) {
+        int32_t e0, e1;
+        row_range(rp, u, nnz, e0, e1);
+        if (e1 - e0 > D2_STAR_ROW) {
+            for (int32_t i = gl; i <= e1 - e0; i += G) {
+                const int32_t x = i == 0 ? u : col[e0 + i - 1];
+                if ((uint32_t)x < (uint32_t)n && C[x] < 0) lost[x] = 2;
+            }
+            continue;
+        }
+        const int32_t sz = e1 - e0 + 1;
+        for (int32_t i = gl; i < sz; i += G) {
+            const int32_t x = i == 0 ? u : col[e0 + i - 1];
+            uint32_t T = 0, key = 0;  // T = 0: not tentative (never matches)
+            if ((uint32_t)x < (uint32_t)n) {
+                const int32_t c = C[x];
+                if (c < 0) {
+                    T = (uint32_t)(-c);
+                    key = (uint32_t)round_prio(pr, x);
+                }
+            }
+            t[i] = ((unsigned long long)T << 32) | key;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int32_t i = gl; i < sz; i += G) {
+            const unsigned long long me = t[i];
+            const uint32_t T = (uint32_t)(me >> 32);
+            if (T == 0) continue;
+            bool dom = false;
+            for (int32_t q = 0; q < sz; q++) {
+                const unsigned long long o = t[q];
+                dom |= (uint32_t)(o >> 32) == T && (uint32_t)o > (uint32_t)me;
+            }
+            if (dom) lost[i == 0 ? u : col[e0 + i - 1]] = 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(D2_BLOCK) k_d2_commit(const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                                                        int32_t *C, unsigned long long *M, uint8_t *lost, Prio pr,
+                                                        const int32_t *__restrict__ wl,
+                                                        const unsigned long long *__restrict__ wc, int32_t *wl_out,
+                                                        unsigned long long *c_out) {
+    __shared__ LoserQueue q;
+    if (threadIdx.x == 0) q.cnt = 0;
+    __syncthreads();
+    const int gpb = D2_BLOCK / G;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t cnt = (int64_t)*wc;
+    for (int64_t b = (int64_t)blockIdx.x * gpb; b < cnt; b += (int64_t)gridDim.x * gpb) {
+        const int64_t i = b + threadIdx.x / G;
+        bool lose = false;
+        int32_t v = -1;
+        if (i < cnt) {
+            v = wl[i];
+            const int32_t T = -C[v];
+            int32_t e0, e1;
+            row_range(rp, v, nnz, e0, e1);
+            const uint8_t mark = lost[v];
+            lose = mark == 1;
+            if (mark == 2) lose = d2_scan_conflict<G>(rp, col, nnz, n, C, pr, v, e0, e1, T, round_prio(pr, v), gl);
+            if (mark && gl == 0) lost[v] = 0;
+            if (!lose) {
+                if (gl == 0) C[v] = T;
+                d2_publish<G, true>(col, e0, e1, n, M, v, T, gl);
+            }
+        }
+        bq_push(q.buf, &q.cnt, lose && gl == 0, v);
+        __syncthreads();
+        bq_flush(q.buf, &q.cnt, &q.base, wl_out, c_out, false);
+    }
+    __syncthreads();
+    bq_flush(q.buf, &q.cnt, &q.base, wl_out, c_out, true);
+}
+
 // Vertices sharing their positive color with a vertex of N2(v), and vertices
 // with color <= 0.
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_validate(const int32_t *__restrict__ rp,
@@ -349,10 +484,13 @@ static int d2_grid(const gc_ctx *ctx, int64_t items, int per_vertex = 64) {
 // longer than 64 entries.
 static int d2_group(int32_t maxdeg) { return maxdeg > 64 ? 64 : 8; }
 
+// The masks (max_n * D2_MW words) followed by the detect marks (max_n bytes).
+static uint8_t *d2_lost(gc_ctx *ctx) { return (uint8_t *)(ctx->d2mask + (size_t)ctx->max_n * D2_MW); }
+
 static gc_status d2_masks(gc_ctx *ctx, int32_t n, hipStream_t s) {
     if (!ctx->d2mask) {
         GC_HIP(hipStreamSynchronize(s));
-        if (hipMalloc((void **)&ctx->d2mask, (size_t)ctx->max_n * D2_MW * 8 + 256) != hipSuccess) {
+        if (hipMalloc((void **)&ctx->d2mask, (size_t)ctx->max_n * (D2_MW * 8 + 1) + 256) != hipSuccess) {
             ctx->d2mask = nullptr;
             return gc_fail(ctx, GC_ERR_OOM, "distance-2 color masks (%lld vertices)", (long long)ctx->max_n);
         }
@@ -383,6 +521,8 @@ gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_
     status = d2_masks(ctx, n, s);
     if (status) return status;
     unsigned long long *M = ctx->d2mask;
+    uint8_t *lost = d2_lost(ctx);
+    GC_HIP(hipMemsetAsync(lost, 0, (size_t)n, s));
     GC_HIP(hipMemsetAsync(cnt, 0, 2 * 8, s));
     GC_TIMED(GC_K_ROUND0, s, k_d2_round0<<<d2_grid(ctx, n), D2_BLOCK, 0, s>>>(
                                  g->row_ptr, g->col_idx, g->nnz, n, colors, M, prio_of(0),
@@ -409,9 +549,20 @@ gc_status gc_spec_rounds_d2(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, M, ctx->wl[cur], cnt + cur, sc,
                                          (uint32_t)X, randx));
         GC_LAUNCHED();
-        GC_TIMED(GC_K_DETECT, s, k_d2_detect<<<d2_grid(ctx, tot), D2_BLOCK, 0, s>>>(
-                                     g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[cur], cnt + cur, M,
-                                     prio_of(r), ctx->wl[nxt], cnt + nxt));
+        const int star = ctx->tune.d2_star;  // the marking kernels stay exact for any row length
+        if (star == 1 || (star == 0 && maxdeg <= D2_STAR_ROW && tot > n / 8)) {
+            // large round: star marking over every vertex, then commit
+            GC_TIMED(GC_K_DETECT, s, k_d2_mark<8><<<d2_grid(ctx, n, 8), D2_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, prio_of(r), lost));
+            GC_LAUNCHED();
+            GC_TIMED(GC_K_DETECT, s, k_d2_commit<8><<<d2_grid(ctx, tot, 8), D2_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, M, lost, prio_of(r),
+                                         ctx->wl[cur], cnt + cur, ctx->wl[nxt], cnt + nxt));
+        } else {
+            GC_TIMED(GC_K_DETECT, s, k_d2_detect<<<d2_grid(ctx, tot), D2_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->wl[cur], cnt + cur, M,
+                                         prio_of(r), ctx->wl[nxt], cnt + nxt));
+        }
         GC_LAUNCHED();
         cur = nxt;
         r++;

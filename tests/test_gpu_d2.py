@@ -120,6 +120,20 @@ def test_d2_beyond_masks_short_rows(gc):
     _recolor_equal(gc, "rgg64", g, c, ref.colors, 3)
 
 
+@pytest.mark.parametrize("star", [1, -1])
+@pytest.mark.parametrize("name", ["er", "mesh", "rmat", "star", "grid", "path"])
+def test_d2_detect_modes(gc, name, star):
+    """Per-neighborhood marking in every round (rows past 64 entries take the
+    marked-for-recheck path) and the distance-2 scan in every round."""
+    g = GRAPHS[name]()
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(d2_star=star)
+    for sel, X in ((gc.FIRST_FIT, 1), (gc.RANDOM_X, 4)):
+        _init_equal(gc, name, g, sel, X, 13, ctx=ctx)
+    _init_equal(gc, name, g, gc.FIRST_FIT, 1, 13, flags=gc.FLAG_PRIO_NATURAL, ctx=ctx)
+    ctx.close()
+
+
 def test_d2_small_grid(gc):
     """One workgroup per CU: every kernel walks its worklist in grid strides."""
     g = GRAPHS["mesh"]()
