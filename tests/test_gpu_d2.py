@@ -204,3 +204,45 @@ def test_d2_arguments(gc):
     c, st = gc.init_color(e, e[:0], gc.FIRST_FIT, 1, 1, flags=gc.FLAG_DISTANCE2)
     assert c.numel() == 0 and st["rounds"] == 0
     assert gc.validate_d2(e, e[:0], c) == (0, 0)
+
+
+def test_d2_full_size_mesh(gc):
+    """The 128^3 mesh of the distance-2 benchmark, at full size.  Natural order:
+    the closed form 1 + x%3 + 3(y%3) + 9(z%3) for every one of the 2,097,152
+    vertices, and recoloring it gives rank + 1.  The benchmark's own
+    configuration (Random-X X=4 + 5 NI passes): valid at distance 2, colors
+    within |N2(v)| + X, passes never above rank + 1 nor above the input's
+    class count."""
+    N = 128
+    g = gen.mesh27(N)
+    rp, col = dev(g)
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    want = (1 + x % 3 + 3 * (y % 3) + 9 * (z % 3)).astype(np.int32).ravel()
+    c, st = gc.init_color(rp, col, gc.FIRST_FIT, 1, 7, flags=gc.FLAG_DISTANCE2 | gc.FLAG_PRIO_NATURAL)
+    assert np.array_equal(c.cpu().numpy(), want) and st["num_colors"] == 27
+    for perm, seed in ((gc.PERM_NONINC, 1), (gc.PERM_RANDOM, 9)):
+        out, _ = gc.recolor_d2(rp, col, c, perm, seed, 0)
+        pi = oracle.class_order(np.bincount(want, minlength=28), perm, seed, 0)
+        rank = np.zeros(28, np.int32)
+        rank[pi] = np.arange(len(pi), dtype=np.int32)
+        assert np.array_equal(out.cpu().numpy(), rank[want] + 1)
+    # the benchmark configuration
+    c, st = gc.init_color(rp, col, gc.RANDOM_X, 4, 1, flags=gc.FLAG_DISTANCE2)
+    assert gc.validate_d2(rp, col, c) == (0, 0)
+    h = c.cpu().numpy()
+    nx = np.minimum(x + 2, N - 1) - np.maximum(x - 2, 0) + 1
+    ny = np.minimum(y + 2, N - 1) - np.maximum(y - 2, 0) + 1
+    nz = np.minimum(z + 2, N - 1) - np.maximum(z - 2, 0) + 1
+    n2 = (nx * ny * nz - 1).ravel()  # |N2(v)|: the Chebyshev ball of radius 2 minus v
+    assert (h <= n2 + 4).all()
+    k = st["num_colors"]
+    for p in range(5):
+        sizes = np.bincount(h, minlength=h.max() + 1)
+        pi = oracle.class_order(sizes, gc.PERM_NONINC, 1, p)
+        rank = np.zeros(h.max() + 1, np.int64)
+        rank[pi] = np.arange(len(pi))
+        c, sp = gc.recolor_d2(rp, col, c, gc.PERM_NONINC, 1, p, out=c)
+        new = c.cpu().numpy()
+        assert (new <= rank[h] + 1).all() and sp["num_colors"] <= k
+        assert gc.validate_d2(rp, col, c) == (0, 0)
+        h, k = new, sp["num_colors"]
