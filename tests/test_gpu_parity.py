@@ -381,3 +381,22 @@ def test_init_priority_orders_split_rows(gc):
     for flags in (2, 4):
         _init_equal(gc, g, gc.FIRST_FIT, 1, 19, flags=flags, ctx=ctx)
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["mesh", "grid", "er", "path"])
+def test_recolor_unaligned_col(gc, name):
+    """col_idx that starts 4 bytes past a 16-byte boundary (a view into a
+    larger buffer): same colors as the oracle."""
+    g = GRAPHS[name]()
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(d)
+    big = torch.zeros(g.nnz + 4, dtype=torch.int32, device=d)
+    big[1:1 + g.nnz] = torch.from_numpy(np.ascontiguousarray(g.col)).to(d)
+    col = big[1:1 + g.nnz]
+    assert col.data_ptr() % 16 == 4
+    ref = oracle.init_color(g, oracle.RANDOM_X, 3, 5).colors
+    c = torch.from_numpy(ref.copy()).to(d)
+    for p, perm in enumerate((gc.PERM_REVERSE, gc.PERM_NONINC, gc.PERM_RANDOM)):
+        c, _ = gc.recolor(rp, col, c, perm, 5, p, out=c)
+        ref = oracle.recolor(g, ref, perm, 5, p).colors
+        assert np.array_equal(c.cpu().numpy(), ref), f"{name} pass {p}"
