@@ -549,7 +549,22 @@ def main():
     ctx.set_timing(True)
     step()
     kt = ctx.timing()
+    # passes after a 1 GiB scrub write (L2 and Infinity Cache hold other data
+    # when each pass starts): pass time and walk time, outside the timed region
+    scrub = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+    ctx.set_timing(True, kinds=["walk"])
+    cold = []
+    for p in range(min(passes, 5)):
+        scrub.fill_(p + 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        recolor_fn(rp, col, colors, perms[p], args.seed, p, out=colors, stats=False, ctx=ctx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    kt_cold = ctx.timing()
     ctx.set_timing(False)
+    del scrub
     ms_step = el / args.steps * 1e3
     m = g.nnz // 2
     value = m * (passes + 1) / (ms_step / 1e3) / 1e9
@@ -578,8 +593,14 @@ def main():
                  "gteps": round(m / (t_init / 1e3) / 1e9, 3)},
         "recolor_pass": {"ms": [round(t, 4) for t in t_pass], "mean_ms": round(sum(t_pass) / passes, 4),
                          "gteps": round(m / (sum(t_pass) / passes / 1e3) / 1e9, 3),
+                         "entries_per_s": round(g.nnz / (sum(t_pass) / passes / 1e3), 1),
                          "algorithmic_bytes": pass_bytes,
                          "gbs": round(pass_bytes / (sum(t_pass) / passes / 1e3) / 1e9, 1)},
+        "recolor_pass_after_scrub": {
+            "scrub_bytes": 1 << 30, "passes": len(cold), "mean_ms": round(sum(cold) / len(cold), 4),
+            "walk_avg_ms": round(kt_cold["walk"][1] / max(kt_cold["walk"][0], 1), 5),
+            "walk_gbs": round(walk_bytes / (kt_cold["walk"][1] / max(kt_cold["walk"][0], 1) / 1e3) / 1e9, 1)
+            if kt_cold["walk"][0] else None},
         "kernel_ms_one_step": {k: {"launches": v[0], "total_ms": round(v[1], 4)} for k, v in kt.items() if v[0]},
         "roofline": roofline,
     }
