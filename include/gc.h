@@ -126,6 +126,9 @@ typedef struct gc_tuning {
                               of more than n / 8 vertices when no row exceeds 64 entries, else a scan of
                               each vertex's distance-2 neighborhood), 1 = marking in every round, -1 = the
                               scan in every round; results are the same */
+    int32_t batch_wg_per_cu; /* gc_batch_color: workgroups per compute unit (0 = 4; at most 5 fit) */
+    int32_t batch_order;   /* gc_batch_color: 0 = graphs taken in id order, 1 = largest (most entries) first
+                              (batches of at most 8192 graphs; larger ones keep id order) */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);
@@ -269,6 +272,22 @@ gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, in
                          int64_t *uncolored, void *stream);
 
 /*
+ * Autotuning.  The knobs of gc_tuning change how the work is scheduled,
+ * never a color.  gc_autotune runs the initial coloring and `passes`
+ * recoloring passes on g (arguments as gc_init_color / gc_recolor) under
+ * candidate settings of deg_wave, group, walk_group, deg_split and
+ * grid_per_cu, one knob at a time with the others held at the best so far,
+ * timing each with HIP events (best of two runs).  It checks that every
+ * candidate gives the same colors (a 64-bit checksum of the (vertex, color)
+ * pairs; GC_ERR_DEVICE if one differs) and leaves the fastest setting in ctx.
+ * colors (device, n) receives the coloring; *best (may be NULL) the setting
+ * and *best_ms (may be NULL) its time.  Synchronizes the stream often; runs
+ * the method roughly 40 times.
+ */
+gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, int32_t perm, int32_t passes,
+                      uint64_t seed, int32_t *colors, gc_tuning *best, double *best_ms, void *stream);
+
+/*
  * num_colors: distinct positive values in colors[0..n); max_color: the
  * largest (0 if none).  Host outputs; synchronizes.
  */
@@ -317,6 +336,19 @@ gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int
 
 /* seed_g of graph g in a batch (host helper, same formula as above). */
 uint64_t gc_batch_graph_seed(uint64_t base_seed, int32_t g);
+
+/*
+ * gc_autotune for gc_batch_color (arguments as there): tries every
+ * combination of batch_order (0, 1) and batch_wg_per_cu (1..5) on the batch,
+ * once each after a warm-up run with the current setting, checks that every
+ * one gives the same colors and per-graph statistics, and leaves the fastest
+ * in ctx.  Batches of at least one graph.
+ */
+gc_status gc_autotune_batch(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+                            int32_t passes, uint64_t base_seed, int32_t max_rounds, int32_t max_vertices_per_graph,
+                            int32_t *colors, gc_graph_stats *per_graph, gc_tuning *best, double *best_ms,
+                            void *stream);
+
 
 /*
  * Class-order schedules over recoloring iterations (section 4.2.1, the

@@ -48,10 +48,10 @@ class Tuning(ctypes.Structure):
                 ("grid_per_cu", ctypes.c_int32), ("walk_mode", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
                 ("check_resident", ctypes.c_int32), ("deg_split", ctypes.c_int32), ("split_len", ctypes.c_int32),
                 ("hub_words", ctypes.c_int32), ("walk_group", ctypes.c_int32),
-                ("d2_star", ctypes.c_int32)]
+                ("d2_star", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32), ("batch_order", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
-                 "split_len", "hub_words", "walk_group", "d2_star")
+                 "split_len", "hub_words", "walk_group", "d2_star", "batch_wg_per_cu", "batch_order")
 
 
 class BatchArgs(ctypes.Structure):
@@ -90,6 +90,13 @@ _SIGS = {
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_batch_graph_seed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32]),
+    "gc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "gc_autotune_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchArgs), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "gc_arc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gc_schedule_perm": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -422,6 +429,55 @@ def batch_color(vtx_off, edge_off, row_ptr, col_idx, select=RANDOM_X, X=4, perm=
                               per_graph.data_ptr() if G > 0 else None, _stream_ptr(stream))
     ctx.check(rc, "gc_batch_color")
     return out, per_graph
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def autotune(row_ptr, col_idx, select=RANDOM_X, X=4, perm=PERM_NONINC, passes=3, seed=1, out=None,
+             ctx: Context | None = None, stream=None):
+    """Pick the fastest scheduling knobs for this graph and method (colors are
+    checked identical under every candidate); the setting stays in ctx.
+    Returns (tuning dict, ms of one run, colors)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.int32, device=row_ptr.device)
+    _check_i32_dev(out, "out", g.n)
+    best, ms = Tuning(), ctypes.c_double()
+    rc = lib().gc_autotune(ctx.handle, ctypes.byref(g), select, X, perm, passes, seed, out.data_ptr() if g.n else None,
+                           ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream))
+    ctx.check(rc, "gc_autotune")
+    return _tuning_dict(best), ms.value, out
+
+
+def autotune_batch(vtx_off, edge_off, row_ptr, col_idx, select=RANDOM_X, X=4, perm=PERM_REVERSE, passes=5,
+                   base_seed=1, max_rounds=0, max_vertices_per_graph=None, out=None, per_graph=None,
+                   ctx: Context | None = None, stream=None):
+    """Pick batch_order and batch_wg_per_cu for gc_batch_color on this batch
+    (colors and per-graph statistics checked identical under every candidate);
+    the setting stays in ctx.  Returns (tuning dict, ms of one launch, colors, per_graph)."""
+    torch = _torch()
+    G = vtx_off.numel() - 1
+    total_v = row_ptr.numel() - G
+    if max_vertices_per_graph is None:
+        max_vertices_per_graph = int((vtx_off[1:] - vtx_off[:-1]).max().item()) if G > 0 else 0
+    ctx = ctx or default_context(max(max_vertices_per_graph, 1))
+    if out is None:
+        out = torch.empty(max(total_v, 0), dtype=torch.int32, device=row_ptr.device)
+    if per_graph is None:
+        per_graph = torch.empty((max(G, 0), 4), dtype=torch.int32, device=row_ptr.device)
+    b = BatchArgs(G, 0, vtx_off.data_ptr(), edge_off.data_ptr(), row_ptr.data_ptr(),
+                  col_idx.data_ptr() if col_idx.numel() else None)
+    best, ms = Tuning(), ctypes.c_double()
+    rc = lib().gc_autotune_batch(ctx.handle, ctypes.byref(b), select, X, perm, passes, base_seed, max_rounds,
+                                 int(max_vertices_per_graph), out.data_ptr() if out.numel() else None,
+                                 per_graph.data_ptr() if G > 0 else None, ctypes.byref(best), ctypes.byref(ms),
+                                 _stream_ptr(stream))
+    ctx.check(rc, "gc_autotune_batch")
+    return _tuning_dict(best), ms.value, out, per_graph
 
 
 SCHED_FIXED, SCHED_ND_RAND_X, SCHED_ND_RAND_POW2 = 0, 1, 2

@@ -53,7 +53,7 @@ static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
-                    c->d2mask};
+                    c->d2mask, c->border};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -241,6 +241,9 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->walk_group < 0 || t->walk_group > 64 || (t->walk_group & (t->walk_group - 1)))
         return gc_fail(ctx, GC_ERR_ARG, "walk_group must be 0 or a power of two in [1, 64]");
     if (t->d2_star < -1 || t->d2_star > 1) return gc_fail(ctx, GC_ERR_ARG, "d2_star must be -1, 0 or 1");
+    if (t->batch_wg_per_cu < 0 || t->batch_wg_per_cu > 5)
+        return gc_fail(ctx, GC_ERR_ARG, "batch_wg_per_cu must be in [0, 5]");
+    if (t->batch_order < 0 || t->batch_order > 1) return gc_fail(ctx, GC_ERR_ARG, "batch_order must be 0 or 1");
     ctx->tune = *t;
     return GC_OK;
 }

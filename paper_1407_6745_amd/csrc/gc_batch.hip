@@ -200,7 +200,8 @@ __global__ void __launch_bounds__(BT) k_batch(int32_t G, const int64_t *__restri
                                               const int32_t *__restrict__ col_idx, int32_t randx, uint32_t X,
                                               int32_t perm, int32_t passes, uint64_t base_seed, int32_t max_rounds,
                                               int32_t V, int32_t *colors, gc_graph_stats *per_graph, int32_t *ws_all,
-                                              int64_t ws_ints, unsigned long long *ticket) {
+                                              int64_t ws_ints, unsigned long long *ticket,
+                                              const int32_t *__restrict__ order) {
     __shared__ int32_t sh[4];
     __shared__ int32_t lds[32];
     __shared__ int32_t l_hist[BK + 1], l_rank[BK + 1], l_pi[BK + 1], l_cls[BK + 1], l_off[BK + 2], l_cursor[BK + 1];
@@ -210,7 +211,10 @@ __global__ void __launch_bounds__(BT) k_batch(int32_t G, const int64_t *__restri
     const BatchSlice ws = batch_slice(ws_all + (int64_t)blockIdx.x * ws_ints, V, (int32_t)X);
     __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) sh[0] = (int32_t)atomicAdd(ticket, 1ull);
+        if (threadIdx.x == 0) {
+            const int32_t t = (int32_t)atomicAdd(ticket, 1ull);
+            sh[0] = (t < G && order) ? order[t] : t;  // the graph of ticket t
+        }
         __syncthreads();
         const int32_t g = sh[0];
         __syncthreads();
@@ -251,6 +255,44 @@ __global__ void __launch_bounds__(BT) k_batch(int32_t G, const int64_t *__restri
     }
 }
 
+// Graph order for the tickets: graphs by decreasing entry count, ties by
+// increasing id (one workgroup, bitonic sort of G <= ORDER_MAX keys in LDS).
+// Only the schedule changes: every graph's colors are the same in any order.
+#define ORDER_MAX 8192
+__global__ void __launch_bounds__(1024) k_batch_order(int32_t G, const int64_t *__restrict__ edge_off,
+                                                      int32_t *__restrict__ order) {
+    __shared__ unsigned long long key[ORDER_MAX];
+    int32_t P = 1;
+    while (P < G) P <<= 1;
+    for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        if (i < G) {
+            int64_t e = edge_off[i + 1] - edge_off[i];
+            e = e < 0 ? 0 : (e > 0x7FFFFFFF ? 0x7FFFFFFF : e);
+            key[i] = ((unsigned long long)(0x7FFFFFFFu - (uint32_t)e) << 32) | (uint32_t)i;  // ascending = largest first
+        } else {
+            key[i] = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int32_t k = 2; k <= P; k <<= 1) {
+        for (int32_t j = k >> 1; j > 0; j >>= 1) {
+            for (int32_t i = threadIdx.x; i < P; i += blockDim.x) {
+                const int32_t l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], c = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) {
+                        key[i] = c;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int32_t i = threadIdx.x; i < G; i += blockDim.x) order[i] = (int32_t)(uint32_t)key[i];
+}
+
 extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
                                     int32_t passes, uint64_t base_seed, int32_t max_rounds, int32_t max_vertices_per_graph,
                                     int32_t *colors, gc_graph_stats *per_graph, void *stream) {
@@ -270,8 +312,21 @@ extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t 
     GC_HIP(hipSetDevice(ctx->device));
     const int32_t V = max_vertices_per_graph > 0 ? max_vertices_per_graph : 1;
     const int64_t slice = batch_slice_ints(V, X);
-    int grid = ctx->num_cu * (ctx->tune.grid_per_cu > 0 ? (ctx->tune.grid_per_cu < 4 ? ctx->tune.grid_per_cu : 4) : 4);
+    int grid = ctx->num_cu * (ctx->tune.batch_wg_per_cu > 0 ? ctx->tune.batch_wg_per_cu : 4);
     if (grid > b->num_graphs) grid = b->num_graphs;
+    const int32_t *order = nullptr;
+    if (ctx->tune.batch_order == 1 && b->num_graphs <= ORDER_MAX) {
+        if (b->num_graphs > ctx->border_cap) {
+            GC_HIP(hipStreamSynchronize(s));
+            if (ctx->border) { GC_HIP(hipFree(ctx->border)); ctx->border = nullptr; ctx->border_cap = 0; }
+            if (hipMalloc((void **)&ctx->border, (size_t)ORDER_MAX * 4) != hipSuccess)
+                return gc_fail(ctx, GC_ERR_OOM, "batch graph order");
+            ctx->border_cap = ORDER_MAX;
+        }
+        GC_TIMED(GC_K_OTHER, s, k_batch_order<<<1, 1024, 0, s>>>(b->num_graphs, b->edge_off, ctx->border));
+        GC_LAUNCHED();
+        order = ctx->border;
+    }
     const int64_t need = slice * 4 * grid;
     if (need > ctx->bws_bytes) {
         GC_HIP(hipStreamSynchronize(s));
@@ -284,7 +339,7 @@ extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t 
     GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
     GC_TIMED(GC_K_BATCH, s, k_batch<<<grid, BT, 0, s>>>(b->num_graphs, b->vtx_off, b->edge_off, b->row_ptr, b->col_idx, select == GC_RANDOM_X,
                                 (uint32_t)X, perm, passes, base_seed, max_rounds, V, colors, per_graph, ctx->bws, slice,
-                                ctx->scal + S_TICKET));
+                                ctx->scal + S_TICKET, order));
     GC_LAUNCHED();
     return GC_OK;
 }
