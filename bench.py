@@ -148,6 +148,17 @@ def run_batch(args):
         gc.batch_color(vo, eo, rp, col, gc.RANDOM_X, X, gc.PERM_REVERSE, passes, args.seed,
                        max_vertices_per_graph=max_n, out=colors, per_graph=per, ctx=ctx)
 
+    # the autotuner picks the graph order and workgroups per CU on this batch
+    # (every candidate checked to give the same colors), unless --tune fixes them
+    tuned = None
+    if not args.tune and not args.no_autotune:
+        t0 = time.perf_counter()
+        best, best_ms, _, _ = gc.autotune_batch(vo, eo, rp, col, gc.RANDOM_X, X, gc.PERM_REVERSE, passes, args.seed,
+                                                max_vertices_per_graph=max_n, out=colors, per_graph=per, ctx=ctx)
+        tuned = {"batch_order": best["batch_order"], "batch_wg_per_cu": best["batch_wg_per_cu"],
+                 "launch_ms": round(best_ms, 3), "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] autotuned: {tuned}")
+
     for _ in range(args.warmup):
         batched()
     torch.cuda.synchronize()
@@ -189,7 +200,8 @@ def run_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"{G} random geometric graphs, n uniform in [500, 50000], target degree uniform in "
                                f"[8, 40], Random-X (X=4) + {passes} reverse-order recoloring passes each",
-                   "graphs": G, "n": n_tot, "nnz": nnz_tot, "m": m_tot, "seed": args.seed, "tuning": ctx.tuning},
+                   "graphs": G, "n": n_tot, "nnz": nnz_tot, "m": m_tot, "seed": args.seed, "tuning": ctx.tuning,
+                   "autotuned": tuned},
         "gteps_batched": round(m_tot * (passes + 1) / t_b / 1e9, 3),
         "plain": {"graphs_per_s": round(G / t_p, 2), "seconds": round(t_p, 3),
                   "gteps": round(m_tot * (passes + 1) / t_p / 1e9, 3)},
@@ -448,6 +460,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="comma list key=value of library tuning knobs")
+    ap.add_argument("--no-autotune", action="store_true", help="batch4096: keep the default batch tuning")
     ap.add_argument("--method", default="rc", choices=("rc", "arc"),
                     help="recoloring: synchronous class walk (rc) or asynchronous speculative rounds (arc)")
     ap.add_argument("--schedule", default="fixed", choices=("fixed", "ndrand5", "ndrand10", "ndrand2i"),
