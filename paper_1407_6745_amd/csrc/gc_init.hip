@@ -67,6 +67,50 @@ __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t 
     return group_any<G>(lose);
 }
 
+// Committed-color masks of the long rows (more than deg_wave entries): for a
+// long row x, fm[longidx[x]] holds which of the colors 1 .. FM_COLORS its
+// neighbors have committed so far.  Every vertex that commits ORs its color
+// into the masks of its long neighbors, so the assign step of a long row
+// reads FM_WORDS words instead of its row (the row is scanned only for colors
+// above FM_COLORS).  The masks are off (idx == NULL) for graphs without long
+// rows.
+#define FM_WORDS 8
+#define FM_COLORS (64 * FM_WORDS)
+
+struct LongMasks {
+    const int32_t *idx;
+    unsigned long long *fm;
+};
+
+// Called by the G lanes of the group that committed color c for a row col[e0, e1).
+template <int G>
+__device__ inline void publish_long(const LongMasks &lm, const int32_t *__restrict__ col, int32_t e0, int32_t e1,
+                                   int32_t n, int32_t c) {
+    if (!lm.idx || c < 1 || c > FM_COLORS) return;
+    const unsigned long long bit = 1ull << ((c - 1) & 63);
+    const int w = (c - 1) >> 6;
+    for (int32_t e = e0 + (int32_t)(__lane_id() & (G - 1)); e < e1; e += G) {
+        const int32_t x = col[e];
+        if ((uint32_t)x < (uint32_t)n) {
+            const int32_t li = lm.idx[x];
+            if (li >= 0) atomicOr(&lm.fm[(size_t)li * FM_WORDS + w], bit);
+        }
+    }
+}
+
+// (j+1)-th smallest color free in a long row's mask, else past FM_COLORS by a
+// scan of the row (a wavefront per row).
+__device__ inline int32_t fm_select(const unsigned long long *__restrict__ m, uint32_t j,
+                                    const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+                                    int32_t n) {
+    const int lane = __lane_id();
+    const uint64_t word = lane < FM_WORDS ? m[lane] : ~0ull;
+    const uint32_t t = wave_nth_free(word, j);
+    if (t) return (int32_t)t;
+    const uint32_t freec = (uint32_t)wave_sum_u64((unsigned long long)__popcll(~word));
+    return group_select<64>(col, e0, e1, C, n, j - freec, FM_COLORS);
+}
+
 // LDS state of a kernel that appends to two worklists.
 struct InitQueues {
     int32_t buf[2][GC_QCAP];
@@ -98,7 +142,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, Prio pr, uint32_t s_color,
-                                                       uint32_t X, int randx) {
+                                                       uint32_t X, int randx, LongMasks lm) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = in_list ? (int64_t)*in_count : (int64_t)n;
@@ -121,6 +165,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, pr, s_color, X, randx != 0);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) C[v] = lose ? -tv : tv;
+        if (v >= 0 && !forward && !lose) publish_long<G>(lm, col, e0, e1, n, tv);
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && (forward || (lose && hub)), v);
         queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
@@ -135,7 +180,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
                                                        uint32_t X, int randx, unsigned long long *degsum,
-                                                       int32_t skip_len) {
+                                                       int32_t skip_len, LongMasks lm) {
     __shared__ unsigned long long sdeg;
     __shared__ unsigned long long lmask[INIT_BLOCK];
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
@@ -154,7 +199,10 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
             if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
         }
         const uint32_t j = (v >= 0 && randx) ? gc_pick(s_color, v, X) : 0u;
-        const int32_t t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, C, n, j, lw);
+        int32_t t;
+        const int32_t li = (G == 64 && lm.idx && v >= 0) ? lm.idx[v] : -1;  // one row per wavefront: uniform
+        if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
+        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, C, n, j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
             degs += (unsigned long long)(e1 - e0);
@@ -175,7 +223,8 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
-                                                       unsigned long long *c_hub, Prio pr, int32_t skip_len) {
+                                                       unsigned long long *c_hub, Prio pr, int32_t skip_len,
+                                                       LongMasks lm) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -194,6 +243,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, pr, 0u, 1u, false);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) C[v] = t;
+        if (v >= 0 && !lose) publish_long<G>(lm, col, e0, e1, n, t);
         const bool hub = e1 - e0 > deg_wave;
         bq_push(q.buf[0], &q.cnt[0], leader && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && lose && hub, v);
@@ -381,6 +431,43 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
     }
 }
 
+// After a long-row detect step: every long row of the plan that committed
+// publishes its color, each chunk for its own entries.
+__global__ void __launch_bounds__(INIT_BLOCK) k_split_publish(const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ col, int64_t nnz, int32_t n,
+                                                              const int32_t *C, const int32_t *__restrict__ hub_v,
+                                                              const int32_t *__restrict__ hub_first,
+                                                              const unsigned long long *__restrict__ plan,
+                                                              int32_t split_len, LongMasks lm) {
+    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int wpb = INIT_BLOCK / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
+        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        const int32_t cv = __builtin_amdgcn_readfirstlane(C[k.v]);
+        if (cv > 0) publish_long<64>(lm, col, k.a, k.b, n, cv);
+    }
+}
+
+// Mask index of every long row (rows of more than deg_wave entries), -1 for
+// the others.  Indexes stop at cap (only reachable with overlapping rows;
+// such rows then simply scan their row in the assign step).
+__global__ void k_long_index(const int32_t *__restrict__ rp, int32_t n, int64_t nnz, int32_t deg_wave, int64_t cap,
+                             int32_t *__restrict__ idx, unsigned long long *count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e0, e1;
+        row_range(rp, (int32_t)i, nnz, e0, e1);
+        const bool lg = e1 - e0 > deg_wave;
+        const unsigned long long b = __ballot(lg);
+        unsigned int base = 0;
+        const int leader = b ? __ffsll((long long)b) - 1 : 0;
+        if (b && __lane_id() == leader) base = (unsigned int)atomicAdd(count, (unsigned long long)__popcll(b));
+        base = __shfl(base, leader);
+        const int64_t k = (int64_t)base + __popcll(b & ((1ull << __lane_id()) - 1ull));
+        idx[i] = (lg && k < cap) ? (int32_t)k : -1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -389,25 +476,26 @@ template <int G>
 static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, int32_t skip_len,
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
-                          int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx) {
+                          int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx,
+                          LongMasks lm) {
     k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, skip_len, in_list, in_count, wl_lo,
-                                            c_lo, wl_hub, c_hub, pr, sc, X, randx);
+                                            c_lo, wl_hub, c_hub, pr, sc, X, randx, lm);
 }
 
 template <int G>
 static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
                           const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
-                          int32_t skip_len) {
+                          int32_t skip_len, LongMasks lm) {
     k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum,
-                                            skip_len);
+                                            skip_len, lm);
 }
 
 template <int G>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                          unsigned long long *c_hub, Prio pr, int32_t skip_len) {
+                          unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm) {
     k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, pr, skip_len);
+                                            c_hub, pr, skip_len, lm);
 }
 
 #define GC_DISPATCH_G(G, CALL)                           \
@@ -468,6 +556,32 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         status = gc_ensure_hub_slots(ctx, g->nnz, ctx->tune.deg_split, s);
         if (status) return status;
     }
+    // committed-color masks for the long rows (graphs that have any)
+    LongMasks lm{nullptr, nullptr};
+    if (maxdeg > deg_wave) {
+        const int64_t fm_need = g->nnz / ((int64_t)deg_wave + 1) + 1;  // long rows are at most this many
+        if (fm_need * FM_WORDS * 8 <= (2LL << 30)) {
+            if (!ctx->longidx && hipMalloc((void **)&ctx->longidx, (size_t)ctx->max_n * 4) != hipSuccess) {
+                ctx->longidx = nullptr;
+                return gc_fail(ctx, GC_ERR_OOM, "long-row mask index");
+            }
+            if (fm_need > ctx->fm_cap) {
+                GC_HIP(hipStreamSynchronize(s));
+                if (ctx->fm) { GC_HIP(hipFree(ctx->fm)); ctx->fm = nullptr; ctx->fm_cap = 0; }
+                if (hipMalloc((void **)&ctx->fm, (size_t)fm_need * FM_WORDS * 8) != hipSuccess)
+                    return gc_fail(ctx, GC_ERR_OOM, "long-row masks (%lld)", (long long)fm_need);
+                ctx->fm_cap = fm_need;
+            }
+            GC_HIP(hipMemsetAsync(ctx->fm, 0, (size_t)fm_need * FM_WORDS * 8, s));
+            GC_HIP(hipMemsetAsync(ctx->scal + S_NLONG, 0, 8, s));
+            GC_TIMED(GC_K_OTHER, s, k_long_index<<<gc_grid(ctx, n, 256), 256, 0, s>>>(g->row_ptr, n, g->nnz, deg_wave,
+                                                                                    fm_need, ctx->longidx,
+                                                                                    ctx->scal + S_NLONG));
+            GC_LAUNCHED();
+            lm = LongMasks{ctx->longidx, ctx->fm};
+        }
+    }
+    const bool masks = lm.idx != nullptr;
     unsigned long long *plan = ctx->scal + S_PLAN;
     auto split_plan = [&](const int32_t *list, const unsigned long long *count) {
         k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan);
@@ -476,10 +590,10 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
     GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
                                                                 nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
-                                                                sc0, (uint32_t)X, randx)));
+                                                                sc0, (uint32_t)X, randx, lm)));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
-                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx));
+                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, lm));
     GC_LAUNCHED();
     if (split) {
         GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3));
@@ -489,6 +603,12 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
                                      cnt + 1));
         GC_LAUNCHED();
+        if (masks) {
+            GC_TIMED(GC_K_ROUND0, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
+                                                                              ctx->hub_v, ctx->hub_first, plan,
+                                                                              split_len, lm));
+            GC_LAUNCHED();
+        }
     }
     int32_t r = 1, cur = 0;
     for (;;) {
@@ -517,15 +637,16 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         }
         if (nlo) {
             GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
-                                                                        sc, (uint32_t)X, randx, cnt + 4, skip)));
+                                                                        sc, (uint32_t)X, randx, cnt + 4, skip, lm)));
             GC_LAUNCHED();
         }
         if (nhub) {
+            // with the masks, long rows of every length take their color here
             GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
-                                                       randx, cnt + 4, skip));
+                                                       randx, cnt + 4, masks ? INT32_MAX : skip, lm));
             GC_LAUNCHED();
         }
-        if (split_round) {
+        if (split_round && !masks) {
             GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                          split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
@@ -535,12 +656,12 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (nlo) {
             GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
                                                                         c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp, skip)));
+                                                                        sp, skip, lm)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp, skip));
+                                                       c_lo_out, hub_out, c_hub_out, sp, skip, lm));
             GC_LAUNCHED();
         }
         if (split_round) {
@@ -548,6 +669,12 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                          split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out));
             GC_LAUNCHED();
+            if (masks) {
+                GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
+                                                                                  colors, ctx->hub_v, ctx->hub_first,
+                                                                                  plan, split_len, lm));
+                GC_LAUNCHED();
+            }
         }
         cur = nxt;
         r++;

@@ -31,6 +31,7 @@ enum {
     S_PLAN = 13,     // split plan of the initial coloring: long rows (13), their chunks (14)
     S_WL = 16,       // initial coloring: 4 worklist counts + the round's degree sum (16..20)
     S_SUM = 24,      // checksum of a color array (autotuning)
+    S_NLONG = 25,    // long rows of the initial coloring's masks
     S_COUNT = 64
 };
 
@@ -77,6 +78,9 @@ struct gc_ctx {
     struct gc_timer *timer;  // kernel timing (NULL when off)
     unsigned long long *d2mask;  // distance-2 coloring: per-vertex color masks (allocated on first use, max_n * 2 words)
     int32_t *bws;            // batched coloring: per-workgroup workspace (grown on demand)
+    int32_t *longidx;        // initial coloring: index of each long row's mask (-1: short row), max_n
+    unsigned long long *fm;  // initial coloring: committed-color masks of the long rows, grown on demand
+    int64_t fm_cap;          // masks allocated
     int32_t *border;         // batched coloring: graph order (largest first), grown on demand
     int64_t border_cap;
     int64_t bws_bytes;
