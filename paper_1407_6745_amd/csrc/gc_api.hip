@@ -53,7 +53,7 @@ static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
-                    c->d2mask, c->border, c->longidx, c->fm};
+                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);

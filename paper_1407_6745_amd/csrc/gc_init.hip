@@ -111,6 +111,22 @@ __device__ inline int32_t fm_select(const unsigned long long *__restrict__ m, ui
     return group_select<64>(col, e0, e1, C, n, j - freec, FM_COLORS);
 }
 
+// Active lists of the split rows (rows handled in chunks): from the second
+// round on, a split row's detect step reads only the neighbors that were
+// still uncolored when the row was last scanned.  Each detect step of a
+// split row also writes the entries it finds uncolored into the other buffer
+// (same offsets as col, order free), for the next round.  len[li] < 0: the
+// row has no list yet (read col).  Committed neighbors leave the lists, so a
+// row that stays uncolored for many rounds (the dense core of a skewed graph)
+// scans fewer and fewer entries; the assign step never needs them (masks).
+struct ActiveLists {
+    const int32_t *idx;  // longidx (NULL: lists off)
+    const int32_t *cur;  // this round's lists
+    const int32_t *len;  // their lengths by long-row index
+    int32_t *next;       // next round's lists (written by the detect step)
+    int32_t *len_next;
+};
+
 // LDS state of a kernel that appends to two worklists.
 struct InitQueues {
     int32_t buf[2][GC_QCAP];
@@ -265,7 +281,8 @@ __global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__
                                                      const int32_t *__restrict__ in_list,
                                                      const unsigned long long *__restrict__ in_count, int32_t thresh,
                                                      int32_t split_len, int32_t *__restrict__ hub_v,
-                                                     int32_t *__restrict__ hub_first, unsigned long long *plan) {
+                                                     int32_t *__restrict__ hub_first, unsigned long long *plan,
+                                                     ActiveLists al) {
     __shared__ int32_t lds[32];
     const int64_t cnt = (int64_t)*in_count;
     int32_t nrow = 0, nch = 0;
@@ -278,10 +295,19 @@ __global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__
             row_range(rp, v, nnz, e0, e1);
             len = e1 - e0;
         }
-        const bool lg = v >= 0 && len > thresh;
+        const bool lg = v >= 0 && len > thresh;  // split rows by their full length
+        int32_t clen = len;                       // the entries the row's chunks cover this round
+        if (lg && al.idx) {
+            const int32_t li = al.idx[v];
+            if (li >= 0) {
+                if (al.len[li] >= 0) clen = min(al.len[li], len);
+                if (al.len_next) al.len_next[li] = 0;
+            }
+        }
+        const int32_t nsub = clen > 0 ? (clen + split_len - 1) / split_len : 1;  // at least one chunk decides the row
         int32_t tr, tc;
         const int32_t er = block_exclusive_scan(lg ? 1 : 0, &tr, lds);
-        const int32_t ec = block_exclusive_scan(lg ? (len + split_len - 1) / split_len : 0, &tc, lds);
+        const int32_t ec = block_exclusive_scan(lg ? nsub : 0, &tc, lds);
         if (lg) {
             hub_v[nrow + er] = v;
             hub_first[nrow + er] = nch + ec;
@@ -297,13 +323,18 @@ __global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__
 
 // Chunk c of the plan: its row's slot, vertex, row range and chunk range.
 
+// Chunk c of the plan: its row's slot, vertex, the entries [e0, e1) the row's
+// chunks cover this round (its active list when it has one: act = true, read
+// from the lists' buffer at the same offsets), the chunk's [a, b), and the
+// row's chunk count.
 struct SplitChunk {
-    int32_t slot, v, e0, e1, a, b, nsub;
+    int32_t slot, v, e0, e1, a, b, nsub, li;
+    bool act;
 };
 
-__device__ inline SplitChunk split_chunk(int32_t c, int32_t nrow, const int32_t *__restrict__ hub_v,
+__device__ inline SplitChunk split_chunk(int32_t c, int32_t nrow, int32_t nch, const int32_t *__restrict__ hub_v,
                                          const int32_t *__restrict__ hub_first, const int32_t *__restrict__ rp,
-                                         int64_t nnz, int32_t split_len) {
+                                         int64_t nnz, int32_t split_len, const ActiveLists &al) {
     int32_t lo = 0, hi = nrow - 1;  // last slot whose first chunk is <= c
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -314,7 +345,10 @@ __device__ inline SplitChunk split_chunk(int32_t c, int32_t nrow, const int32_t 
     k.slot = lo;
     k.v = hub_v[lo];
     row_range(rp, k.v, nnz, k.e0, k.e1);
-    k.nsub = (k.e1 - k.e0 + split_len - 1) / split_len;
+    k.li = al.idx ? al.idx[k.v] : -1;
+    k.act = k.li >= 0 && al.len[k.li] >= 0;
+    if (k.act) k.e1 = k.e0 + min(al.len[k.li], k.e1 - k.e0);
+    k.nsub = (lo + 1 < nrow ? hub_first[lo + 1] : nch) - hub_first[lo];
     k.a = k.e0 + (c - hub_first[lo]) * split_len;
     k.b = min(k.e1, k.a + split_len);
     return k;
@@ -344,13 +378,14 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_assign(const int32_t *__re
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
                                                              int32_t *hub_cnt, unsigned long long *degsum) {
     __shared__ unsigned long long lmask[INIT_BLOCK];
+    const ActiveLists al{nullptr, nullptr, nullptr, nullptr, nullptr};  // whole rows (no masks on this path)
     const int lane = __lane_id();
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
     const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
-        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        const SplitChunk k = split_chunk(c, nrow, nch, hub_v, hub_first, rp, nnz, split_len, al);
         unsigned long long *bits = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
         lw[lane] = 0ull;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -407,17 +442,33 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              const unsigned long long *__restrict__ plan,
                                                              int32_t split_len, Prio pr, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
-                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub) {
+                                                             int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
+                                                             ActiveLists al) {
     const int lane = __lane_id();
     const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
-        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        const SplitChunk k = split_chunk(c, nrow, nch, hub_v, hub_first, rp, nnz, split_len, al);
         unsigned long long *flag = hub_bits + (int64_t)k.slot * GC_HUB_WORDS;
         const int32_t t = ROUND0 ? round0_color(s_color, k.v, X, randx != 0) : -C[k.v];
         const uint64_t pv = round_prio(pr, k.v);
-        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, col, C, n, pr, s_color, X, randx != 0);
+        const int32_t *src = k.act ? al.cur : col;
+        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, src, C, n, pr, s_color, X, randx != 0);
+        if (!ROUND0 && al.next && k.li >= 0) {
+            // the chunk's entries still uncolored go to the row's list for the next round
+            for (int32_t eb = k.a; eb < k.b; eb += 64) {
+                const int32_t e = eb + lane;
+                const int32_t w = e < k.b ? src[e] : -1;
+                const bool keep = (uint32_t)w < (uint32_t)n && C[w] <= 0;
+                const unsigned long long bm = __ballot(keep);
+                if (!bm) continue;
+                int32_t base = 0;
+                if (lane == 0) base = atomicAdd(&al.len_next[k.li], (int32_t)__popcll(bm));
+                base = __shfl(base, 0);
+                if (keep) al.next[k.e0 + base + __popcll(bm & ((1ull << lane) - 1ull))] = w;
+            }
+        }
         if (lose && lane == 0) atomicOr(flag, 1ull);
         if (split_last(hub_cnt, k.slot, k.nsub)) {
             if (lane == 0) {
@@ -438,14 +489,14 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_publish(const int32_t *__r
                                                               const int32_t *C, const int32_t *__restrict__ hub_v,
                                                               const int32_t *__restrict__ hub_first,
                                                               const unsigned long long *__restrict__ plan,
-                                                              int32_t split_len, LongMasks lm) {
+                                                              int32_t split_len, LongMasks lm, ActiveLists al) {
     const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
-        const SplitChunk k = split_chunk(c, nrow, hub_v, hub_first, rp, nnz, split_len);
+        const SplitChunk k = split_chunk(c, nrow, nch, hub_v, hub_first, rp, nnz, split_len, al);
         const int32_t cv = __builtin_amdgcn_readfirstlane(C[k.v]);
-        if (cv > 0) publish_long<64>(lm, col, k.a, k.b, n, cv);
+        if (cv > 0) publish_long<64>(lm, k.act ? al.cur : col, k.a, k.b, n, cv);
     }
 }
 
@@ -582,9 +633,35 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         }
     }
     const bool masks = lm.idx != nullptr;
+    // active lists of the split rows (with the masks): two buffers, swapped
+    // after every round that has split rows
+    const bool lists = masks && split;
+    int acur = 0;
+    if (lists) {
+        const int64_t fm_need = g->nnz / ((int64_t)deg_wave + 1) + 1;
+        if (2 * g->nnz > ctx->act_cap || 2 * fm_need > ctx->alen_cap) {
+            GC_HIP(hipStreamSynchronize(s));
+            if (ctx->act) { GC_HIP(hipFree(ctx->act)); ctx->act = nullptr; ctx->act_cap = 0; }
+            if (ctx->alen) { GC_HIP(hipFree(ctx->alen)); ctx->alen = nullptr; ctx->alen_cap = 0; }
+            if (hipMalloc((void **)&ctx->act, (size_t)(2 * g->nnz) * 4) != hipSuccess ||
+                hipMalloc((void **)&ctx->alen, (size_t)(2 * fm_need) * 4) != hipSuccess)
+                return gc_fail(ctx, GC_ERR_OOM, "split-row active lists (%lld entries)", (long long)g->nnz);
+            ctx->act_cap = 2 * g->nnz;
+            ctx->alen_cap = 2 * fm_need;
+        }
+        GC_HIP(hipMemsetAsync(ctx->alen, 0xFF, (size_t)(ctx->alen_cap / 2) * 4, s));  // no lists yet: -1
+    }
+    auto lists_of = [&](bool with_next) {
+        if (!lists) return ActiveLists{nullptr, nullptr, nullptr, nullptr, nullptr};
+        const int64_t half_a = ctx->act_cap / 2, half_l = ctx->alen_cap / 2;
+        int32_t *a0 = ctx->act + acur * half_a, *a1 = ctx->act + (acur ^ 1) * half_a;
+        int32_t *l0 = ctx->alen + acur * half_l, *l1 = ctx->alen + (acur ^ 1) * half_l;
+        return ActiveLists{ctx->longidx, a0, l0, with_next ? a1 : nullptr, with_next ? l1 : nullptr};
+    };
     unsigned long long *plan = ctx->scal + S_PLAN;
-    auto split_plan = [&](const int32_t *list, const unsigned long long *count) {
-        k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan);
+    auto split_plan = [&](const int32_t *list, const unsigned long long *count, const ActiveLists &al) {
+        k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan,
+                                        al);
     };
     const Prio sp0 = prio_of(0);
     const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
@@ -596,17 +673,18 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                                                ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, lm));
     GC_LAUNCHED();
     if (split) {
-        GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3));
+        const ActiveLists al0 = lists_of(false);  // round 0 reads whole rows and writes no lists
+        GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3, al0));
         GC_LAUNCHED();
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
-                                     cnt + 1));
+                                     cnt + 1, al0));
         GC_LAUNCHED();
         if (masks) {
             GC_TIMED(GC_K_ROUND0, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
                                                                               ctx->hub_v, ctx->hub_first, plan,
-                                                                              split_len, lm));
+                                                                              split_len, lm, al0));
             GC_LAUNCHED();
         }
     }
@@ -631,8 +709,9 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
         const Prio sp = prio_of(r);
         const bool split_round = split && nhub > 0;
+        const ActiveLists al = lists_of(true);
         if (split_round) {
-            GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in));
+            GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in, al));
             GC_LAUNCHED();
         }
         if (nlo) {
@@ -667,14 +746,16 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (split_round) {
             GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
-                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out));
+                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
+                                         al));
             GC_LAUNCHED();
             if (masks) {
                 GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
                                                                                   colors, ctx->hub_v, ctx->hub_first,
-                                                                                  plan, split_len, lm));
+                                                                                  plan, split_len, lm, al));
                 GC_LAUNCHED();
             }
+            if (lists) acur ^= 1;  // this round's surviving entries are the next round's lists
         }
         cur = nxt;
         r++;

@@ -81,6 +81,10 @@ struct gc_ctx {
     int32_t *longidx;        // initial coloring: index of each long row's mask (-1: short row), max_n
     unsigned long long *fm;  // initial coloring: committed-color masks of the long rows, grown on demand
     int64_t fm_cap;          // masks allocated
+    int32_t *act;            // initial coloring: active lists of the split rows, two buffers of act_cap entries
+    int64_t act_cap;
+    int32_t *alen;           // their lengths, two arrays of alen_cap (by long-row index)
+    int64_t alen_cap;
     int32_t *border;         // batched coloring: graph order (largest first), grown on demand
     int64_t border_cap;
     int64_t bws_bytes;
