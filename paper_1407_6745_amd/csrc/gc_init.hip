@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, Prio pr, int32_t skip_len,
-                                                       LongMasks lm) {
+                                                       LongMasks lm, ActiveLists al) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -248,19 +248,42 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
     const int gi = threadIdx.x / G;
     for (int64_t base = (int64_t)blockIdx.x * vpi; base < cnt; base += (int64_t)gridDim.x * vpi) {
         const int64_t i = base + gi;
-        int32_t v = -1, e0 = 0, e1 = 0, t = 0;
+        int32_t v = -1, e0 = 0, e1 = 0, t = 0, full = 0, li = -1;
+        bool act = false;
         if (i < cnt) {
             v = wl[i];
             row_range(rp, v, nnz, e0, e1);
-            if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }
+            full = e1 - e0;
+            if (G == 64 && al.idx) {  // a long row reads its active list when it has one
+                li = al.idx[v];
+                if (li >= 0 && al.len[li] >= 0) {
+                    act = true;
+                    e1 = e0 + min(al.len[li], full);
+                }
+            }
+            if (e1 - e0 > skip_len) { v = -1; e0 = e1 = 0; }  // long enough for the split kernels
             else t = -C[v];
         }
+        const int32_t *src = act ? al.cur : col;
         const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
-        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, col, C, n, pr, 0u, 1u, false);
+        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src, C, n, pr, 0u, 1u, false);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) C[v] = t;
-        if (v >= 0 && !lose) publish_long<G>(lm, col, e0, e1, n, t);
-        const bool hub = e1 - e0 > deg_wave;
+        if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
+        if (G == 64 && al.next && v >= 0 && li >= 0) {
+            // the entries still uncolored: the row's list for the next round (one wavefront, in order)
+            int32_t kept = 0;
+            for (int32_t eb = e0; eb < e1; eb += 64) {
+                const int32_t e = eb + __lane_id();
+                const int32_t w = e < e1 ? src[e] : -1;
+                const bool keep = (uint32_t)w < (uint32_t)n && C[w] <= 0;
+                const unsigned long long bm = __ballot(keep);
+                if (keep) al.next[e0 + kept + __popcll(bm & ((1ull << __lane_id()) - 1ull))] = w;
+                kept += (int32_t)__popcll(bm);
+            }
+            if (__lane_id() == 0) al.len_next[li] = kept;
+        }
+        const bool hub = full > deg_wave;  // worklist bins by the full row length
         bq_push(q.buf[0], &q.cnt[0], leader && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && lose && hub, v);
         queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
@@ -295,15 +318,14 @@ __global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__
             row_range(rp, v, nnz, e0, e1);
             len = e1 - e0;
         }
-        const bool lg = v >= 0 && len > thresh;  // split rows by their full length
-        int32_t clen = len;                       // the entries the row's chunks cover this round
-        if (lg && al.idx) {
-            const int32_t li = al.idx[v];
-            if (li >= 0) {
-                if (al.len[li] >= 0) clen = min(al.len[li], len);
-                if (al.len_next) al.len_next[li] = 0;
-            }
+        // the entries the row's chunks would cover this round: its active list when it has one
+        int32_t clen = len, li = -1;
+        if (v >= 0 && al.idx) {
+            li = al.idx[v];
+            if (li >= 0 && al.len[li] >= 0) clen = min(al.len[li], len);
         }
+        const bool lg = v >= 0 && clen > thresh;  // longer rows take the split kernels, the others k_detect
+        if (lg && li >= 0 && al.len_next) al.len_next[li] = 0;
         const int32_t nsub = clen > 0 ? (clen + split_len - 1) / split_len : 1;  // at least one chunk decides the row
         int32_t tr, tc;
         const int32_t er = block_exclusive_scan(lg ? 1 : 0, &tr, lds);
@@ -544,9 +566,10 @@ static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <int G>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
-                          unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm) {
+                          unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
+                          ActiveLists al) {
     k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, pr, skip_len, lm);
+                                            c_hub, pr, skip_len, lm, al);
 }
 
 #define GC_DISPATCH_G(G, CALL)                           \
@@ -635,7 +658,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     const bool masks = lm.idx != nullptr;
     // active lists of the split rows (with the masks): two buffers, swapped
     // after every round that has split rows
-    const bool lists = masks && split;
+    const bool lists = masks;
     int acur = 0;
     if (lists) {
         const int64_t fm_need = g->nnz / ((int64_t)deg_wave + 1) + 1;
@@ -735,12 +758,12 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (nlo) {
             GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
                                                                         c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp, skip, lm)));
+                                                                        sp, skip, lm, al)));
             GC_LAUNCHED();
         }
         if (nhub) {
             GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp, skip, lm));
+                                                       c_lo_out, hub_out, c_hub_out, sp, skip, lm, al));
             GC_LAUNCHED();
         }
         if (split_round) {
@@ -755,8 +778,8 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                                                                                   plan, split_len, lm, al));
                 GC_LAUNCHED();
             }
-            if (lists) acur ^= 1;  // this round's surviving entries are the next round's lists
         }
+        if (lists && nhub > 0) acur ^= 1;  // this round's surviving entries are the next round's lists
         cur = nxt;
         r++;
     }
