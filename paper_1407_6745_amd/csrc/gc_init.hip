@@ -712,9 +712,14 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         }
     }
     int32_t r = 1, cur = 0;
+    // Split rows stay on the split path while their active list is longer than
+    // the threshold; lists only shrink, so once a round plans no split row the
+    // later rounds skip the split kernels.
+    bool split_live = split, planned = split;
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
         if (ss) return ss;
+        if (planned && lists && ctx->hscal[S_PLAN] == 0) split_live = false;
         const int64_t nlo = (int64_t)ctx->hscal[S_WL + 2 * cur], nhub = (int64_t)ctx->hscal[S_WL + 2 * cur + 1];
         if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4]);
         const int64_t tot = nlo + nhub;
@@ -731,7 +736,8 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         GC_HIP(hipMemsetAsync(cnt + 4, 0, 8, s));
         const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
         const Prio sp = prio_of(r);
-        const bool split_round = split && nhub > 0;
+        const bool split_round = split_live && nhub > 0;
+        planned = split_round;
         const ActiveLists al = lists_of(true);
         if (split_round) {
             GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in, al));
