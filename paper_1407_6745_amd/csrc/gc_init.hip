@@ -196,11 +196,19 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
                                                        uint32_t X, int randx, unsigned long long *degsum,
-                                                       int32_t skip_len, LongMasks lm) {
+                                                       int32_t skip_len, LongMasks lm, unsigned long long *zero2,
+                                                       unsigned long long *zero1) {
     __shared__ unsigned long long sdeg;
     __shared__ unsigned long long lmask[INIT_BLOCK];
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
     if (threadIdx.x == 0) sdeg = 0;
+    // counters the detect step appends to next, and the degree sum of the next
+    // round (neither is touched by this launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        zero2[0] = 0;
+        zero2[1] = 0;
+        *zero1 = 0;
+    }
     __syncthreads();
     const int64_t cnt = (int64_t)*wcount;
     const int vpi = INIT_BLOCK / G;
@@ -558,9 +566,9 @@ static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <int G>
 static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
                           const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
-                          int32_t skip_len, LongMasks lm) {
+                          int32_t skip_len, LongMasks lm, unsigned long long *zero2, unsigned long long *zero1) {
     k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum,
-                                            skip_len, lm);
+                                            skip_len, lm, zero2, zero1);
 }
 
 template <int G>
@@ -608,14 +616,14 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         return (int)(want < 1 ? 1 : (want > cap ? cap : want));
     };
     // Worklists wl[2 * buf + bin] (bin 0: lane groups, bin 1: wavefronts),
-    // counts in scal[S_WL + 2 * buf + bin]; scal[S_WL + 4] holds the degree
-    // sum of the current round.  Round 0 uses wl[3] for the long rows it
+    // counts in scal[S_WL + 2 * buf + bin]; scal[S_WL + 4 + (r & 1)] holds the
+    // degree sum of round r.  Round 0 uses wl[3] for the long rows it
     // forwards to its second launch.
     unsigned long long *cnt = ctx->scal + S_WL;
     std::vector<int64_t> sizes, degsum;
     sizes.push_back(n);
     degsum.push_back(g->nnz);
-    GC_HIP(hipMemsetAsync(cnt, 0, 5 * 8, s));
+    GC_HIP(hipMemsetAsync(cnt, 0, 6 * 8, s));
     // Long rows (longer than deg_wave and deg_split) go to the split kernels;
     // the others skip them.
     int32_t maxdeg = 0;
@@ -721,7 +729,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (ss) return ss;
         if (planned && lists && ctx->hscal[S_PLAN] == 0) split_live = false;
         const int64_t nlo = (int64_t)ctx->hscal[S_WL + 2 * cur], nhub = (int64_t)ctx->hscal[S_WL + 2 * cur + 1];
-        if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4]);
+        if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4 + ((r - 1) & 1)]);
         const int64_t tot = nlo + nhub;
         if (tot == 0) break;
         if (max_rounds > 0 && r == max_rounds) { status = GC_ERR_NOT_CONVERGED; break; }
@@ -732,8 +740,9 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         int32_t *lo_out = ctx->wl[2 * nxt], *hub_out = ctx->wl[2 * nxt + 1];
         unsigned long long *c_lo_in = cnt + 2 * cur, *c_hub_in = cnt + 2 * cur + 1;
         unsigned long long *c_lo_out = cnt + 2 * nxt, *c_hub_out = cnt + 2 * nxt + 1;
-        GC_HIP(hipMemsetAsync(c_lo_out, 0, 2 * 8, s));
-        GC_HIP(hipMemsetAsync(cnt + 4, 0, 8, s));
+        // this round's degree sum goes to slot 4 + (r & 1); the assign launches
+        // clear c_*_out and the other slot (no memset launches per round)
+        unsigned long long *dsum = cnt + 4 + (r & 1), *dsum_next = cnt + 4 + ((r + 1) & 1);
         const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
         const Prio sp = prio_of(r);
         const bool split_round = split_live && nhub > 0;
@@ -745,20 +754,21 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         }
         if (nlo) {
             GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
-                                                                        sc, (uint32_t)X, randx, cnt + 4, skip, lm)));
+                                                                        sc, (uint32_t)X, randx, dsum, skip, lm, c_lo_out,
+                                                                        dsum_next)));
             GC_LAUNCHED();
         }
         if (nhub) {
             // with the masks, long rows of every length take their color here
             GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
-                                                       randx, cnt + 4, masks ? INT32_MAX : skip, lm));
+                                                       randx, dsum, masks ? INT32_MAX : skip, lm, c_lo_out, dsum_next));
             GC_LAUNCHED();
         }
         if (split_round && !masks) {
             GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
                                          g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                          split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
-                                         ctx->hub_cnt, cnt + 4));
+                                         ctx->hub_cnt, dsum));
             GC_LAUNCHED();
         }
         if (nlo) {

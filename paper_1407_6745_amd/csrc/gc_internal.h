@@ -29,7 +29,7 @@ enum {
     S_DONE = 11,
     S_MAXDEG = 12,   // longest row of the graph
     S_PLAN = 13,     // split plan of the initial coloring: long rows (13), their chunks (14)
-    S_WL = 16,       // initial coloring: 4 worklist counts + the round's degree sum (16..20)
+    S_WL = 16,       // initial coloring: 4 worklist counts + two degree-sum slots (16..21)
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
     S_COUNT = 64
