@@ -128,3 +128,43 @@ def test_schedule_perm_matches_oracle():
     lib = gc.lib()
     for bad in ((3, 0, 1, 1), (-1, 0, 1, 1), (0, 4, 0, 1), (0, 0, 0, 0), (1, 0, 0, 5)):
         assert lib.gc_schedule_perm(*bad) == -1
+
+
+def _struct_members(header, name):
+    """Member names, in order, of `typedef struct name { ... } name;` in a header."""
+    src = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), src, flags=re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        for part in decl.split(","):  # the last identifier of each declarator is the member
+            ids = re.findall(r"[A-Za-z_]\w*", part.split("[")[0])
+            if ids:
+                names.append(ids[-1])
+    return names
+
+
+def test_tuning_struct_matches_header():
+    """The binding's gc_tuning mirror has the header's members in the header's
+    order (all int32), and every knob is one the binding can set by name."""
+    import paper_1407_6745_amd as gc
+
+    members = _struct_members(HEADERS[0], "gc_tuning")
+    assert [f[0] for f in gc.Tuning._fields_] == members
+    assert all(t is ctypes.c_int32 for _, t in gc.Tuning._fields_)
+    assert ctypes.sizeof(gc.Tuning) == 4 * len(members)
+    assert list(gc.TUNING_FIELDS) == members
+
+
+def test_stats_and_batch_structs_match_header():
+    import paper_1407_6745_amd as gc
+
+    assert [f[0] for f in gc.CSRArgs._fields_] == _struct_members(HEADERS[0], "gc_csr")
+    assert [f[0] for f in gc.BatchArgs._fields_] == _struct_members(HEADERS[0], "gc_batch_csr")
+
+
+def test_server_structs_match_header():
+    import paper_1407_6745_amd as gc
+
+    for cls, name in ((gc.ServerConfigArgs, "gc_server_config"), (gc.RequestArgs, "gc_request"),
+                      (gc.RequestDoneArgs, "gc_request_done"), (gc.ServerStatsArgs, "gc_server_stats")):
+        assert [f[0] for f in cls._fields_] == _struct_members(HEADERS[1], name), name
