@@ -308,17 +308,26 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
 // last completes the row and clears the slot.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__ rp, int64_t nnz,
-                                                     const int32_t *__restrict__ in_list,
-                                                     const unsigned long long *__restrict__ in_count, int32_t thresh,
-                                                     int32_t split_len, int32_t *__restrict__ hub_v,
-                                                     int32_t *__restrict__ hub_first, unsigned long long *plan,
-                                                     ActiveLists al) {
-    __shared__ int32_t lds[32];
+// The plan of a round's split rows: slot i holds row hub_v[i], whose chunks
+// start at hub_first[i] (increasing with i).  Any number of workgroups: each
+// wavefront reserves its rows' slots and chunks with one 64-bit atomic on the
+// packed total (rows << 32 | chunks), so slots and first chunks grow in the
+// same order.  `next` (the other round's total) is cleared for the next round.
+__device__ inline int32_t plan_rows(const unsigned long long *plan) { return (int32_t)(*plan >> 32); }
+__device__ inline int32_t plan_chunks(const unsigned long long *plan) { return (int32_t)(*plan & 0xFFFFFFFFull); }
+
+__global__ void __launch_bounds__(256) k_split_plan(const int32_t *__restrict__ rp, int64_t nnz,
+                                                    const int32_t *__restrict__ in_list,
+                                                    const unsigned long long *__restrict__ in_count, int32_t thresh,
+                                                    int32_t split_len, int32_t *__restrict__ hub_v,
+                                                    int32_t *__restrict__ hub_first, unsigned long long *plan,
+                                                    unsigned long long *next, ActiveLists al) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next = 0;
     const int64_t cnt = (int64_t)*in_count;
-    int32_t nrow = 0, nch = 0;
-    for (int64_t base = 0; base < cnt; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
+    const int lane = __lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < cnt; base += stride) {
+        const int64_t i = base + lane;
         int32_t v = -1, len = 0;
         if (i < cnt) {
             v = in_list[i];
@@ -334,20 +343,23 @@ __global__ void __launch_bounds__(1024) k_split_plan(const int32_t *__restrict__
         }
         const bool lg = v >= 0 && clen > thresh;  // longer rows take the split kernels, the others k_detect
         if (lg && li >= 0 && al.len_next) al.len_next[li] = 0;
-        const int32_t nsub = clen > 0 ? (clen + split_len - 1) / split_len : 1;  // at least one chunk decides the row
-        int32_t tr, tc;
-        const int32_t er = block_exclusive_scan(lg ? 1 : 0, &tr, lds);
-        const int32_t ec = block_exclusive_scan(lg ? nsub : 0, &tc, lds);
-        if (lg) {
-            hub_v[nrow + er] = v;
-            hub_first[nrow + er] = nch + ec;
+        const uint32_t nsub = lg ? (clen > 0 ? (uint32_t)((clen + split_len - 1) / split_len) : 1u) : 0u;
+        const unsigned long long bm = __ballot(lg);
+        if (!bm) continue;
+        uint32_t inc = nsub;  // inclusive scan of the chunk counts over the wavefront
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
         }
-        nrow += tr;
-        nch += tc;
-    }
-    if (threadIdx.x == 0) {
-        plan[0] = (unsigned long long)nrow;
-        plan[1] = (unsigned long long)nch;
+        const uint32_t tot = __shfl(inc, 63);
+        unsigned long long old = 0;
+        if (lane == 0) old = atomicAdd(plan, ((unsigned long long)__popcll(bm) << 32) | tot);
+        old = __shfl(old, 0);
+        if (lg) {
+            const uint32_t slot = (uint32_t)(old >> 32) + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+            hub_v[slot] = v;
+            hub_first[slot] = (int32_t)((uint32_t)(old & 0xFFFFFFFFull) + inc - nsub);
+        }
     }
 }
 
@@ -411,7 +423,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_assign(const int32_t *__re
     const ActiveLists al{nullptr, nullptr, nullptr, nullptr, nullptr};  // whole rows (no masks on this path)
     const int lane = __lane_id();
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
-    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int32_t nrow = plan_rows(plan), nch = plan_chunks(plan);
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
@@ -475,7 +487,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
                                                              ActiveLists al) {
     const int lane = __lane_id();
-    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int32_t nrow = plan_rows(plan), nch = plan_chunks(plan);
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
@@ -520,7 +532,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_publish(const int32_t *__r
                                                               const int32_t *__restrict__ hub_first,
                                                               const unsigned long long *__restrict__ plan,
                                                               int32_t split_len, LongMasks lm, ActiveLists al) {
-    const int32_t nrow = (int32_t)plan[0], nch = (int32_t)plan[1];
+    const int32_t nrow = plan_rows(plan), nch = plan_chunks(plan);
     const int wpb = INIT_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int32_t c = blockIdx.x * wpb + wib; c < nch; c += gridDim.x * wpb) {
@@ -689,11 +701,17 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         int32_t *l0 = ctx->alen + acur * half_l, *l1 = ctx->alen + (acur ^ 1) * half_l;
         return ActiveLists{ctx->longidx, a0, l0, with_next ? a1 : nullptr, with_next ? l1 : nullptr};
     };
-    unsigned long long *plan = ctx->scal + S_PLAN;
-    auto split_plan = [&](const int32_t *list, const unsigned long long *count, const ActiveLists &al) {
-        k_split_plan<<<1, 1024, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v, ctx->hub_first, plan,
-                                        al);
+    // round r's plan total is scal[S_PLAN + (r & 1)]; its plan launch clears the other
+    unsigned long long *plan0 = ctx->scal + S_PLAN;
+    if (split) GC_HIP(hipMemsetAsync(plan0, 0, 2 * 8, s));
+    auto split_plan = [&](int32_t rr, const int32_t *list, const unsigned long long *count, int64_t items,
+                          const ActiveLists &al) {
+        const int64_t want = (items + 255) / 256;
+        const int grid = (int)(want < 1 ? 1 : (want > cap ? cap : want));
+        k_split_plan<<<grid, 256, 0, s>>>(g->row_ptr, g->nnz, list, count, thresh, split_len, ctx->hub_v,
+                                          ctx->hub_first, plan0 + (rr & 1), plan0 + ((rr + 1) & 1), al);
     };
+    unsigned long long *plan = plan0;  // the current round's plan total
     const Prio sp0 = prio_of(0);
     const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
     GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
@@ -705,7 +723,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     GC_LAUNCHED();
     if (split) {
         const ActiveLists al0 = lists_of(false);  // round 0 reads whole rows and writes no lists
-        GC_TIMED(GC_K_OTHER, s, split_plan(ctx->wl[3], cnt + 3, al0));
+        GC_TIMED(GC_K_OTHER, s, split_plan(0, ctx->wl[3], cnt + 3, (int64_t)cap * 256, al0));
         GC_LAUNCHED();
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
@@ -727,7 +745,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
         if (ss) return ss;
-        if (planned && lists && ctx->hscal[S_PLAN] == 0) split_live = false;
+        if (planned && lists && (ctx->hscal[S_PLAN + ((r - 1) & 1)] >> 32) == 0) split_live = false;
         const int64_t nlo = (int64_t)ctx->hscal[S_WL + 2 * cur], nhub = (int64_t)ctx->hscal[S_WL + 2 * cur + 1];
         if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4 + ((r - 1) & 1)]);
         const int64_t tot = nlo + nhub;
@@ -748,8 +766,9 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         const bool split_round = split_live && nhub > 0;
         planned = split_round;
         const ActiveLists al = lists_of(true);
+        plan = plan0 + (r & 1);
         if (split_round) {
-            GC_TIMED(GC_K_OTHER, s, split_plan(hub_in, c_hub_in, al));
+            GC_TIMED(GC_K_OTHER, s, split_plan(r, hub_in, c_hub_in, nhub, al));
             GC_LAUNCHED();
         }
         if (nlo) {

@@ -28,7 +28,7 @@ enum {
     S_TICKET = 10,   // work ticket of persistent kernels
     S_DONE = 11,
     S_MAXDEG = 12,   // longest row of the graph
-    S_PLAN = 13,     // split plan of the initial coloring: long rows (13), their chunks (14)
+    S_PLAN = 13,     // split plans of the initial coloring, two rounds (13, 14): rows << 32 | chunks
     S_WL = 16,       // initial coloring: 4 worklist counts + two degree-sum slots (16..21)
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
