@@ -53,7 +53,7 @@ static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
-                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen};
+                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -99,6 +99,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         {(void **)&ctx->coff, (3 * CC + 4) * 4},
         {(void **)&ctx->histw, CC * 4},      {(void **)&ctx->hist_s, CC * 4},
         {(void **)&ctx->hist_sc, CC * 4},    {(void **)&ctx->sbase, (CC + 2) * 4},
+        {(void **)&ctx->hcopy, (size_t)GC_HCOPY_INTS * 4},
         {(void **)&ctx->hsub, N * 4},        {(void **)&ctx->shadow, N * 2 + 256},
         {(void **)&ctx->cursor, (3 * CC + 4) * 4}, {(void **)&ctx->keys, CC * 8},
         {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
@@ -113,7 +114,8 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     }
     // buffers that must be zero between calls
     if (hipMemset(ctx->hist, 0, CC * 4) != hipSuccess || hipMemset(ctx->histw, 0, CC * 4) != hipSuccess ||
-        hipMemset(ctx->hist_s, 0, CC * 4) != hipSuccess || hipMemset(ctx->hist_sc, 0, CC * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
+        hipMemset(ctx->hist_s, 0, CC * 4) != hipSuccess || hipMemset(ctx->hist_sc, 0, CC * 4) != hipSuccess ||
+        hipMemset(ctx->hcopy, 0, (size_t)GC_HCOPY_INTS * 4) != hipSuccess || hipMemset(ctx->bitmap, 0, (size_t)ctx->bitmap_bits / 8) != hipSuccess ||
         hipMemset(ctx->scal, 0, S_COUNT * 8) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         free_all(ctx); free(ctx); return GC_ERR_DEVICE;
     }

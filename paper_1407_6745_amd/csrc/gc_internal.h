@@ -13,6 +13,17 @@
 // context
 // ---------------------------------------------------------------------------
 
+// Recoloring histogram: colors below GC_HIST_LDS are counted in workgroup
+// LDS and flushed into one of GC_HIST_COPIES copies (bin-0 counts, then bin-1
+// counts, GC_HIST_LDS entries per copy), chosen by the histogram tile, so that
+// concurrent flushes land on different cache lines.  A third array holds, per
+// copy and color, the copy's cursor inside the color's bin-0 segment (relative
+// to the segment start): the copies fill consecutive parts of the segment.
+// The counts are zero between calls; the cursors are rewritten every pass.
+#define GC_HIST_LDS 4096
+#define GC_HIST_COPIES 16
+#define GC_HCOPY_INTS (3 * GC_HIST_COPIES * GC_HIST_LDS)
+
 // Device scalar slots (int64 each) in ctx->scal.
 enum {
     S_WCOUNT0 = 0,   // worklist length, buffer 0
@@ -51,6 +62,7 @@ struct gc_ctx {
     int32_t *coff;           // recolor: work-chunk offsets per (rank, bin) segment (3 * ccap + 4)
     int32_t *hist_s;         // per color: vertices of the split bin; zero between calls
     int32_t *hist_sc;        // per color: work chunks of those vertices; zero between calls
+    int32_t *hcopy;          // recoloring's histogram copies and per-copy scatter cursors (GC_HCOPY_INTS)
     int32_t *sbase;          // per rank: first hub slot of the rank's split segment (ccap + 2)
     int32_t *hsub;           // per list slot of a split row: its first chunk inside the segment (max_n + 64)
     unsigned long long *hub_bits;  // per hub slot: HUB_WORDS color-mask words, zero between calls

@@ -38,32 +38,41 @@
 
 #include <vector>
 
-#define HIST_LDS 4096       // colors below this use the workgroup-private histogram
-#define HIST_BITS 12
+#define HIST_LDS GC_HIST_LDS  // colors below this use the workgroup-private histogram
 #define HIST_ITEMS 8        // vertices per thread of one histogram tile
 #define PERM_THREADS 1024
 #define ORDER_LDS 2048      // colors up to this run the class order on LDS copies
 #define SCATTER_BINS 1024   // segments below this reserve list ranges once per workgroup
 #define SCATTER_ITEMS 4
+#define SCATTER_BLOCK 256
 #define WALK_BLOCK 256
 #define SPIN_LIMIT (1u << 20)
 #define NSEG_PER_RANK 3
 #define CT_MAX_K1 127    // classes that fit the one-byte compact color copy
 #define CT_MAX_K2 32767  // classes that fit the two-byte compact color copy
 #define HUB_WORDS GC_HUB_WORDS  // hub slot stride; ranks above 64 * hub_words - 1 keep long rows in bin 1
+// the histogram copy of a vertex is (histogram tile) mod GC_HIST_COPIES; a
+// scatter tile (same block size) lies inside one histogram tile
+static_assert(HIST_ITEMS % SCATTER_ITEMS == 0, "scatter tiles must nest in histogram tiles");
+static_assert(ORDER_LDS < HIST_LDS, "the class order's LDS path takes all its counts from the copies");
 
 // bin of a row of length d (a split row of a rank above hub_max_rank goes to bin 1 later)
 __device__ inline int row_bin(int32_t d, int32_t deg_wave, int32_t deg_split) {
     return d <= deg_wave ? 0 : ((deg_split > 0 && d > deg_split) ? 2 : 1);
 }
 
+// Class sizes by degree bin.  Colors below HIST_LDS: bin-0 and bin-1 counts
+// in LDS, flushed into histogram copy blockIdx mod GC_HIST_COPIES (the grid
+// is the tile count or a multiple of the copy count, so every tile of a
+// workgroup has that copy); bin 2 always, and every bin of larger colors,
+// straight into the global arrays.
 __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t *__restrict__ rp, int64_t nnz,
                        int32_t deg_wave, int32_t deg_split, int32_t split_len, int32_t ccap,
                        int32_t *__restrict__ hist, int32_t *__restrict__ histw, int32_t *__restrict__ hist_s,
-                       int32_t *__restrict__ hist_sc, unsigned long long *scal) {
-    __shared__ int32_t h[HIST_LDS], hw[HIST_LDS];
+                       int32_t *__restrict__ hist_sc, int32_t *__restrict__ hcopy, unsigned long long *scal) {
+    __shared__ int32_t h[2 * HIST_LDS];  // bin 0 at [c], bin 1 at [HIST_LDS + c]
     __shared__ int32_t lds[32];
-    for (int i = threadIdx.x; i < HIST_LDS; i += blockDim.x) { h[i] = 0; hw[i] = 0; }
+    for (int i = threadIdx.x; i < 2 * HIST_LDS; i += blockDim.x) h[i] = 0;
     __syncthreads();
     int32_t mx = 0;
     bool bad = false;
@@ -100,8 +109,8 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
                 }
             }
             const bool in_lds = valid && c < HIST_LDS;
-            (void)wave_match_reserve_bits(h, c, in_lds, HIST_BITS);
-            (void)wave_match_reserve_bits(hw, c, in_lds && bin == 1, HIST_BITS);
+            // plain LDS adds: equal colors in a wavefront only serialize in the LDS
+            if (in_lds && bin < 2) atomicAdd(&h[bin * HIST_LDS + c], 1);
             if (valid && !in_lds) {
                 atomicAdd(&hist[c], 1);
                 if (bin == 1) atomicAdd(&histw[c], 1);
@@ -114,9 +123,11 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     }
     const int32_t bmax = block_max_i32(mx, lds);  // synchronizes the block
     const int32_t top = bmax < HIST_LDS - 1 ? bmax : HIST_LDS - 1;
+    int32_t *h0c = hcopy + (size_t)(blockIdx.x % GC_HIST_COPIES) * HIST_LDS;
+    int32_t *h1c = h0c + (size_t)GC_HIST_COPIES * HIST_LDS;
     for (int i = threadIdx.x + 1; i <= top; i += blockDim.x) {
-        if (h[i]) atomicAdd(&hist[i], h[i]);
-        if (hw[i]) atomicAdd(&histw[i], hw[i]);
+        if (h[i]) atomicAdd(&h0c[i], h[i]);
+        if (h[HIST_LDS + i]) atomicAdd(&h1c[i], h[HIST_LDS + i]);
     }
     unsigned long long anybad = __ballot(bad);
     if (__lane_id() == 0 && anybad) atomicOr(&scal[S_ERR], 1ull);
@@ -133,7 +144,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
                                                                int32_t hub_max_rank, int32_t *hist, int32_t *histw, int32_t *hist_s,
                                                                int32_t *hist_sc, int32_t *cls, int32_t *pi,
                                                                int32_t *rank, int32_t *off, int32_t *coff,
-                                                               int32_t *cursor, int32_t *sbase,
+                                                               int32_t *cursor, int32_t *sbase, int32_t *hcopy,
                                                                unsigned long long *scal) {
     __shared__ int32_t lds[32];
     // up to ORDER_LDS colors every step below runs on LDS copies of the class
@@ -144,14 +155,41 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
     if (maxc > ccap) maxc = ccap;
     int32_t *H = hist, *HW = histw, *HS = hist_s, *HSC = hist_sc, *CL = cls, *PI = pi;
     const bool local = maxc <= ORDER_LDS;
-    if (local) {
-        for (int32_t c = threadIdx.x; c <= maxc; c += blockDim.x) {
-            l_h[c] = hist[c];
-            l_hw[c] = histw[c];
-            l_hs[c] = hist_s[c];
-            l_hsc[c] = hist_sc[c];
+    // colors below HIST_LDS: class sizes from the histogram copies (which are
+    // cleared for the next call), and every copy's relative cursor in the
+    // color's bin-0 segment; with local, into the LDS copies directly
+    const int32_t lmax = maxc < HIST_LDS - 1 ? maxc : HIST_LDS - 1;
+    int32_t *h1c = hcopy + (size_t)GC_HIST_COPIES * HIST_LDS;
+    int32_t *rel = hcopy + (size_t)2 * GC_HIST_COPIES * HIST_LDS;
+    for (int32_t c = threadIdx.x; c <= lmax; c += blockDim.x) {
+        int32_t x[GC_HIST_COPIES], y[GC_HIST_COPIES];
+#pragma unroll
+        for (int p = 0; p < GC_HIST_COPIES; p++) {
+            x[p] = hcopy[(size_t)p * HIST_LDS + c];
+            y[p] = h1c[(size_t)p * HIST_LDS + c];
         }
-        __syncthreads();
+        const int32_t hs = hist_s[c];
+        int32_t a = 0, w = 0;
+#pragma unroll
+        for (int p = 0; p < GC_HIST_COPIES; p++) {
+            rel[(size_t)p * HIST_LDS + c] = a;
+            a += x[p];
+            w += y[p];
+            hcopy[(size_t)p * HIST_LDS + c] = 0;
+            h1c[(size_t)p * HIST_LDS + c] = 0;
+        }
+        if (local) {
+            l_h[c] = a + w + hs;
+            l_hw[c] = w;
+            l_hs[c] = hs;
+            l_hsc[c] = hist_sc[c];
+        } else {
+            hist[c] = a + w + hs;
+            histw[c] = w;
+        }
+    }
+    __syncthreads();
+    if (local) {  // maxc <= ORDER_LDS < HIST_LDS: every color was filled above
         H = l_h;
         HW = l_hw;
         HS = l_hs;
@@ -220,15 +258,19 @@ __global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int3
 
 // Counting-sort scatter into segments: one tile of SCATTER_ITEMS * blockDim
 // vertices per workgroup; segments below SCATTER_BINS reserve their list
-// range once per workgroup.  Writes Cout[v] = -(rank + 1) and the row range
-// next to each list entry.
-__global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S, const int32_t *__restrict__ rp, int64_t nnz,
+// range once per workgroup, and the tile's entries are staged in LDS in
+// segment order so that each segment's run is written out contiguously.
+// Writes Cout[v] = -(rank + 1) and the row range next to each list entry.
+__global__ void __launch_bounds__(SCATTER_BLOCK) k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S, const int32_t *__restrict__ rp, int64_t nnz,
                           int32_t deg_wave, int32_t deg_split, int32_t hub_max_rank, int32_t ccap,
                           const int32_t *__restrict__ rank,
                           int32_t *__restrict__ cursor, int32_t *__restrict__ list, int2 *__restrict__ rows,
-                          const unsigned long long *__restrict__ scal) {
-    __shared__ int32_t cnt[SCATTER_BINS];
+                          const int32_t *__restrict__ pi, const int32_t *__restrict__ off,
+                          int32_t *__restrict__ rel, const unsigned long long *__restrict__ scal) {
+    __shared__ int32_t cnt[SCATTER_BINS];  // per segment: count, then staging offset
     __shared__ int32_t basepos[SCATTER_BINS];
+    __shared__ int4 stage[SCATTER_ITEMS * SCATTER_BLOCK];  // (vertex, row begin, row end, list slot)
+    __shared__ int32_t lds[32];
     const int32_t k = (int32_t)scal[S_K];
     const int32_t nseg = NSEG_PER_RANK * k;
     const int32_t bins = nseg < SCATTER_BINS ? nseg : SCATTER_BINS;
@@ -291,18 +333,40 @@ __global__ void k_scatter(int32_t n, const int32_t *Cin, int32_t *Cout, void *S,
         if (in_lds) loc[it] = pos;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < bins; i += blockDim.x)
-        if (cnt[i]) basepos[i] = atomicAdd(&cursor[i], cnt[i]);
+    // bin-0 segments of colors with per-copy counts reserve from this tile's
+    // copy's part of the segment (the copy the histogram counted it in)
+    const int copy = (int)(((int64_t)blockIdx.x * SCATTER_ITEMS / HIST_ITEMS) % GC_HIST_COPIES);
+    int32_t staged = 0;
+    for (int base = 0; base < bins; base += blockDim.x) {
+        const int i = base + (int)threadIdx.x;
+        const int32_t ci = i < bins ? cnt[i] : 0;
+        if (ci) {
+            const int32_t c = i % NSEG_PER_RANK == 0 ? pi[i / NSEG_PER_RANK] : HIST_LDS;
+            if (c < HIST_LDS)
+                basepos[i] = off[i] + atomicAdd(&rel[(size_t)copy * HIST_LDS + c], ci);
+            else
+                basepos[i] = atomicAdd(&cursor[i], ci);
+        }
+        int32_t tot;
+        const int32_t ex = block_exclusive_scan(ci, &tot, lds);  // ends with a barrier
+        if (i < bins) cnt[i] = staged + ex;
+        staged += tot;
+    }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < SCATTER_ITEMS; it++) {
         const int64_t v = tile + (int64_t)it * blockDim.x + threadIdx.x;
         if (loc[it] >= 0) {
-            const int32_t p = basepos[sg[it]] + loc[it];
-            list[p] = (int32_t)v;
-            rows[p] = rw[it];
-            Cout[v] = -((sg[it] / NSEG_PER_RANK) + 1);
+            const int32_t g = sg[it];
+            stage[cnt[g] + loc[it]] = make_int4((int32_t)v, rw[it].x, rw[it].y, basepos[g] + loc[it]);
+            Cout[v] = -((g / NSEG_PER_RANK) + 1);
         }
+    }
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < staged; j += blockDim.x) {
+        const int4 e = stage[j];
+        list[e.w] = e.x;
+        rows[e.w] = make_int2(e.y, e.z);
     }
 }
 
@@ -786,6 +850,17 @@ static walk_fn walk_kernel(int G, bool full) { return full ? walk_kernel_t<true>
 // entries); the narrow one keeps only a 64-color register window (further
 // windows rescan the row) and lets the first sub-chunk of a split row scan the
 // whole row.
+// Histogram grid: one workgroup per tile up to two per CU (longer-lived
+// workgroups measured faster than one short one per tile), else a multiple of
+// the copy count with several tiles each (so that every tile of a workgroup
+// has its copy).
+static int hist_grid_for(const gc_ctx *ctx, int32_t n, int block) {
+    const int64_t tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
+    int64_t cap = (int64_t)(2 * ctx->num_cu) / GC_HIST_COPIES * GC_HIST_COPIES;
+    if (cap < GC_HIST_COPIES) cap = GC_HIST_COPIES;
+    return (int)(tiles <= cap ? tiles : cap);
+}
+
 static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
     const int G = gc_walk_group(ctx, full);
     walk_fn f = walk_kernel(G, full);
@@ -881,24 +956,25 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
         status = gc_ensure_hub_slots(ctx, g->nnz, deg_split, s);
         if (status) return status;
     }
-    const int64_t hist_tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
-    const int hist_grid = (int)(hist_tiles < 16 * ctx->num_cu ? hist_tiles : 16 * ctx->num_cu);
-    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8, s));
-    GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
+    const int hist_grid = hist_grid_for(ctx, n, block);
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8 * (S_ERR - S_MAXC + 1), s));  // max, min, error flags
     GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, deg_split,
                                                              split_len, ctx->ccap, ctx->hist, ctx->histw, ctx->hist_s,
-                                                             ctx->hist_sc, ctx->scal));
+                                                             ctx->hist_sc, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, hub_max_rank, ctx->hist,
                                 ctx->histw, ctx->hist_s, ctx->hist_sc, (int32_t *)ctx->keys, ctx->pi, ctx->rank,
-                                ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->scal));
+                                ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
-    const int64_t tiles = ((int64_t)n + block * SCATTER_ITEMS - 1) / (block * SCATTER_ITEMS);
-    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, block, 0, s>>>(n, colors_in, colors_out, ctx->shadow, g->row_ptr, g->nnz,
+    static_assert(SCATTER_BLOCK == 256, "scatter tiles share the histogram's block size");
+    const int64_t tiles = ((int64_t)n + SCATTER_BLOCK * SCATTER_ITEMS - 1) / (SCATTER_BLOCK * SCATTER_ITEMS);
+    GC_TIMED(GC_K_SCATTER, s, k_scatter<<<(unsigned)tiles, SCATTER_BLOCK, 0, s>>>(n, colors_in, colors_out, ctx->shadow, g->row_ptr, g->nnz,
                                                                          deg_wave, deg_split, hub_max_rank, ctx->ccap,
                                                                          ctx->rank,
-                                                                         ctx->cursor, ctx->list, ctx->rows, ctx->scal));
+                                                                         ctx->cursor, ctx->list, ctx->rows, ctx->pi, ctx->off,
+                                                                         ctx->hcopy + (size_t)2 * GC_HIST_COPIES * HIST_LDS,
+                                                                         ctx->scal));
     GC_LAUNCHED();
     if (deg_split > 0) {
         GC_TIMED(GC_K_SCATTER, s, k_split_prefix<<<4, 256, 0, s>>>(ctx->off, ctx->rows, split_len, ctx->hsub, ctx->scal));
@@ -988,19 +1064,17 @@ extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, 
     }
     const int block = 256;
     // class sizes and order (no split bins: only the ranks are used)
-    const int64_t hist_tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
-    const int hist_grid = (int)(hist_tiles < 16 * ctx->num_cu ? hist_tiles : 16 * ctx->num_cu);
-    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8, s));
-    GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
+    const int hist_grid = hist_grid_for(ctx, n, block);
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8 * (S_ERR - S_MAXC + 1), s));  // max, min, error flags
     GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, ctx->tune.deg_wave, 0,
                                                              ctx->tune.split_len, ctx->ccap, ctx->hist, ctx->histw,
-                                                             ctx->hist_s, ctx->hist_sc, ctx->scal));
+                                                             ctx->hist_s, ctx->hist_sc, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 1,
                                 64 * ctx->tune.hub_words - 1, ctx->hist, ctx->histw, ctx->hist_s, ctx->hist_sc,
                                 (int32_t *)ctx->keys, ctx->pi, ctx->rank, ctx->off, ctx->coff, ctx->cursor, ctx->sbase,
-                                ctx->scal));
+                                ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
     int32_t *prank = ctx->list;  // free outside the recoloring walk
     GC_TIMED(GC_K_OTHER, s, k_vertex_rank<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors_in, ctx->rank, ctx->ccap,
