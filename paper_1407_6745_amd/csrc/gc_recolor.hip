@@ -61,11 +61,23 @@ __device__ inline int row_bin(int32_t d, int32_t deg_wave, int32_t deg_split) {
     return d <= deg_wave ? 0 : ((deg_split > 0 && d > deg_split) ? 2 : 1);
 }
 
+// Histogram copy of the vertices of histogram tile t when the histogram runs
+// on `grid` workgroups: workgroup w takes the consecutive tiles
+// [w * tpw, (w + 1) * tpw), and the copies take consecutive blocks of
+// workgroups, so a copy's part of a segment lists its vertices in about
+// ascending order (neighboring rows stay close in the class walk).
+__device__ inline int hist_copy_of_tile(int64_t t, int64_t tpw, int grid) {
+    return (int)((t / tpw) * GC_HIST_COPIES / grid);
+}
+
+__device__ inline int64_t hist_tiles_per_wg(int32_t n, int block, int grid) {
+    const int64_t tiles = ((int64_t)n + (int64_t)HIST_ITEMS * block - 1) / ((int64_t)HIST_ITEMS * block);
+    return (tiles + grid - 1) / grid;
+}
+
 // Class sizes by degree bin.  Colors below HIST_LDS: bin-0 and bin-1 counts
-// in LDS, flushed into histogram copy blockIdx mod GC_HIST_COPIES (the grid
-// is the tile count or a multiple of the copy count, so every tile of a
-// workgroup has that copy); bin 2 always, and every bin of larger colors,
-// straight into the global arrays.
+// in LDS, flushed into the workgroup's histogram copy; bin 2 always, and
+// every bin of larger colors, straight into the global arrays.
 __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t *__restrict__ rp, int64_t nnz,
                        int32_t deg_wave, int32_t deg_split, int32_t split_len, int32_t ccap,
                        int32_t *__restrict__ hist, int32_t *__restrict__ histw, int32_t *__restrict__ hist_s,
@@ -78,7 +90,9 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     bool bad = false;
     // tiles of HIST_ITEMS * blockDim vertices; every load of a tile is issued before any is used
     const int64_t tile_sz = (int64_t)HIST_ITEMS * blockDim.x;
-    for (int64_t tile = (int64_t)blockIdx.x * tile_sz; tile < n; tile += (int64_t)gridDim.x * tile_sz) {
+    const int64_t tpw = hist_tiles_per_wg(n, blockDim.x, gridDim.x);
+    const int64_t tile_end = ((int64_t)blockIdx.x + 1) * tpw * tile_sz;
+    for (int64_t tile = (int64_t)blockIdx.x * tpw * tile_sz; tile < n && tile < tile_end; tile += tile_sz) {
         int32_t cs[HIST_ITEMS], a0[HIST_ITEMS], a1[HIST_ITEMS];
 #pragma unroll
         for (int it = 0; it < HIST_ITEMS; it++) {
@@ -123,7 +137,7 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
     }
     const int32_t bmax = block_max_i32(mx, lds);  // synchronizes the block
     const int32_t top = bmax < HIST_LDS - 1 ? bmax : HIST_LDS - 1;
-    int32_t *h0c = hcopy + (size_t)(blockIdx.x % GC_HIST_COPIES) * HIST_LDS;
+    int32_t *h0c = hcopy + (size_t)hist_copy_of_tile((int64_t)blockIdx.x * tpw, tpw, gridDim.x) * HIST_LDS;
     int32_t *h1c = h0c + (size_t)GC_HIST_COPIES * HIST_LDS;
     for (int i = threadIdx.x + 1; i <= top; i += blockDim.x) {
         if (h[i]) atomicAdd(&h0c[i], h[i]);
@@ -266,7 +280,7 @@ __global__ void __launch_bounds__(SCATTER_BLOCK) k_scatter(int32_t n, const int3
                           const int32_t *__restrict__ rank,
                           int32_t *__restrict__ cursor, int32_t *__restrict__ list, int2 *__restrict__ rows,
                           const int32_t *__restrict__ pi, const int32_t *__restrict__ off,
-                          int32_t *__restrict__ rel, const unsigned long long *__restrict__ scal) {
+                          int32_t *__restrict__ rel, int hist_grid, const unsigned long long *__restrict__ scal) {
     __shared__ int32_t cnt[SCATTER_BINS];  // per segment: count, then staging offset
     __shared__ int32_t basepos[SCATTER_BINS];
     __shared__ int4 stage[SCATTER_ITEMS * SCATTER_BLOCK];  // (vertex, row begin, row end, list slot)
@@ -335,7 +349,8 @@ __global__ void __launch_bounds__(SCATTER_BLOCK) k_scatter(int32_t n, const int3
     __syncthreads();
     // bin-0 segments of colors with per-copy counts reserve from this tile's
     // copy's part of the segment (the copy the histogram counted it in)
-    const int copy = (int)(((int64_t)blockIdx.x * SCATTER_ITEMS / HIST_ITEMS) % GC_HIST_COPIES);
+    const int copy = hist_copy_of_tile((int64_t)blockIdx.x * SCATTER_ITEMS / HIST_ITEMS,
+                                       hist_tiles_per_wg(n, blockDim.x, hist_grid), hist_grid);
     int32_t staged = 0;
     for (int base = 0; base < bins; base += blockDim.x) {
         const int i = base + (int)threadIdx.x;
@@ -851,13 +866,11 @@ static walk_fn walk_kernel(int G, bool full) { return full ? walk_kernel_t<true>
 // windows rescan the row) and lets the first sub-chunk of a split row scan the
 // whole row.
 // Histogram grid: one workgroup per tile up to two per CU (longer-lived
-// workgroups measured faster than one short one per tile), else a multiple of
-// the copy count with several tiles each (so that every tile of a workgroup
-// has its copy).
+// workgroups measured faster than one short one per tile), else consecutive
+// tiles per workgroup.
 static int hist_grid_for(const gc_ctx *ctx, int32_t n, int block) {
     const int64_t tiles = ((int64_t)n + block * HIST_ITEMS - 1) / (block * HIST_ITEMS);
-    int64_t cap = (int64_t)(2 * ctx->num_cu) / GC_HIST_COPIES * GC_HIST_COPIES;
-    if (cap < GC_HIST_COPIES) cap = GC_HIST_COPIES;
+    const int64_t cap = 2 * (int64_t)ctx->num_cu;
     return (int)(tiles <= cap ? tiles : cap);
 }
 
@@ -974,7 +987,7 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
                                                                          ctx->rank,
                                                                          ctx->cursor, ctx->list, ctx->rows, ctx->pi, ctx->off,
                                                                          ctx->hcopy + (size_t)2 * GC_HIST_COPIES * HIST_LDS,
-                                                                         ctx->scal));
+                                                                         hist_grid, ctx->scal));
     GC_LAUNCHED();
     if (deg_split > 0) {
         GC_TIMED(GC_K_SCATTER, s, k_split_prefix<<<4, 256, 0, s>>>(ctx->off, ctx->rows, split_len, ctx->hsub, ctx->scal));
