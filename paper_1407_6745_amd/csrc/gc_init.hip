@@ -25,6 +25,8 @@
 #include <vector>
 
 #define INIT_BLOCK 256
+#define GC_RUN_AHEAD 4  // rounds queued per host read-back when no launch needs one
+static_assert(S_REC + 2 * GC_RUN_AHEAD <= S_COUNT, "round records");
 // loads in flight per lane: whole-wavefront rows are long, so they keep more
 #define ROW_UNROLL(G) ((G) >= 32 ? 16 : GC_UNROLL)
 
@@ -197,14 +199,21 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
                                                        uint32_t X, int randx, unsigned long long *degsum,
                                                        int32_t skip_len, LongMasks lm, unsigned long long *zero2,
-                                                       unsigned long long *zero1) {
+                                                       unsigned long long *zero1, unsigned long long *rec,
+                                                       const unsigned long long *rec_in) {
     __shared__ unsigned long long sdeg;
     __shared__ unsigned long long lmask[INIT_BLOCK];
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
     if (threadIdx.x == 0) sdeg = 0;
     // counters the detect step appends to next, and the degree sum of the next
     // round (neither is touched by this launch)
+    // (a round queued without a host read first records its input size and
+    // the previous round's degree sum, which the last slot still holds)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (rec) {
+            rec[0] = rec_in[0] + rec_in[1];
+            rec[1] = *zero1;
+        }
         zero2[0] = 0;
         zero2[1] = 0;
         *zero1 = 0;
@@ -578,9 +587,10 @@ static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <int G>
 static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
                           const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
-                          int32_t skip_len, LongMasks lm, unsigned long long *zero2, unsigned long long *zero1) {
+                          int32_t skip_len, LongMasks lm, unsigned long long *zero2, unsigned long long *zero1,
+                          unsigned long long *rec, const unsigned long long *rec_in) {
     k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum,
-                                            skip_len, lm, zero2, zero1);
+                                            skip_len, lm, zero2, zero1, rec, rec_in);
 }
 
 template <int G>
@@ -742,9 +752,26 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     // the threshold; lists only shrink, so once a round plans no split row the
     // later rounds skip the split kernels.
     bool split_live = split, planned = split;
+    // Without split rows and active lists no launch of a round depends on a
+    // value the host must read: the kernels take the worklist counts from the
+    // device, each bin's list only shrinks (so the last counts read bound the
+    // grids), and a round whose list is empty does nothing.  The host then
+    // queues up to GC_RUN_AHEAD rounds per read-back; every queued round
+    // after the first records its input size and the previous round's degree
+    // sum in scal[S_REC + 2q ..], so the statistics stay exact.
+    const bool ahead = !split && !lists;
+    int32_t batch = 0;  // rounds queued since the last read-back
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
         if (ss) return ss;
+        bool ended = false;
+        for (int32_t q = 1; q < batch && !ended; q++) {
+            degsum.push_back((int64_t)ctx->hscal[S_REC + 2 * q + 1]);
+            const int64_t sz = (int64_t)ctx->hscal[S_REC + 2 * q];
+            if (sz == 0) ended = true;  // the queued rounds from this one on were empty
+            else sizes.push_back(sz);
+        }
+        if (ended) break;
         if (planned && lists && (ctx->hscal[S_PLAN + ((r - 1) & 1)] >> 32) == 0) split_live = false;
         const int64_t nlo = (int64_t)ctx->hscal[S_WL + 2 * cur], nhub = (int64_t)ctx->hscal[S_WL + 2 * cur + 1];
         if (r > 1) degsum.push_back((int64_t)ctx->hscal[S_WL + 4 + ((r - 1) & 1)]);
@@ -753,70 +780,79 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (max_rounds > 0 && r == max_rounds) { status = GC_ERR_NOT_CONVERGED; break; }
         if (r > n) return gc_fail(ctx, GC_ERR_DEVICE, "no progress after %d rounds", r);  // each round commits >= 1 vertex
         sizes.push_back(tot);
-        const int nxt = cur ^ 1;
-        int32_t *lo_in = ctx->wl[2 * cur], *hub_in = ctx->wl[2 * cur + 1];
-        int32_t *lo_out = ctx->wl[2 * nxt], *hub_out = ctx->wl[2 * nxt + 1];
-        unsigned long long *c_lo_in = cnt + 2 * cur, *c_hub_in = cnt + 2 * cur + 1;
-        unsigned long long *c_lo_out = cnt + 2 * nxt, *c_hub_out = cnt + 2 * nxt + 1;
-        // this round's degree sum goes to slot 4 + (r & 1); the assign launches
-        // clear c_*_out and the other slot (no memset launches per round)
-        unsigned long long *dsum = cnt + 4 + (r & 1), *dsum_next = cnt + 4 + ((r + 1) & 1);
-        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
-        const Prio sp = prio_of(r);
-        const bool split_round = split_live && nhub > 0;
-        planned = split_round;
-        const ActiveLists al = lists_of(true);
-        plan = plan0 + (r & 1);
-        if (split_round) {
-            GC_TIMED(GC_K_OTHER, s, split_plan(r, hub_in, c_hub_in, nhub, al));
-            GC_LAUNCHED();
+        batch = 1;
+        if (ahead) {
+            batch = GC_RUN_AHEAD;
+            if (max_rounds > 0 && max_rounds - r < batch) batch = max_rounds - r;
         }
-        if (nlo) {
-            GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
-                                                                        sc, (uint32_t)X, randx, dsum, skip, lm, c_lo_out,
-                                                                        dsum_next)));
-            GC_LAUNCHED();
-        }
-        if (nhub) {
-            // with the masks, long rows of every length take their color here
-            GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
-                                                       randx, dsum, masks ? INT32_MAX : skip, lm, c_lo_out, dsum_next));
-            GC_LAUNCHED();
-        }
-        if (split_round && !masks) {
-            GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
-                                         g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
-                                         split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
-                                         ctx->hub_cnt, dsum));
-            GC_LAUNCHED();
-        }
-        if (nlo) {
-            GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
-                                                                        c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                        sp, skip, lm, al)));
-            GC_LAUNCHED();
-        }
-        if (nhub) {
-            GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
-                                                       c_lo_out, hub_out, c_hub_out, sp, skip, lm, al));
-            GC_LAUNCHED();
-        }
-        if (split_round) {
-            GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
-                                         g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
-                                         split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
-                                         al));
-            GC_LAUNCHED();
-            if (masks) {
-                GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
-                                                                                  colors, ctx->hub_v, ctx->hub_first,
-                                                                                  plan, split_len, lm, al));
+        for (int32_t q = 0; q < batch; q++) {
+            unsigned long long *rec = q > 0 ? ctx->scal + S_REC + 2 * q : nullptr;
+            const int nxt = cur ^ 1;
+            int32_t *lo_in = ctx->wl[2 * cur], *hub_in = ctx->wl[2 * cur + 1];
+            int32_t *lo_out = ctx->wl[2 * nxt], *hub_out = ctx->wl[2 * nxt + 1];
+            unsigned long long *c_lo_in = cnt + 2 * cur, *c_hub_in = cnt + 2 * cur + 1;
+            unsigned long long *c_lo_out = cnt + 2 * nxt, *c_hub_out = cnt + 2 * nxt + 1;
+            // this round's degree sum goes to slot 4 + (r & 1); the assign launches
+            // clear c_*_out and the other slot (no memset launches per round)
+            unsigned long long *dsum = cnt + 4 + (r & 1), *dsum_next = cnt + 4 + ((r + 1) & 1);
+            const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)r);
+            const Prio sp = prio_of(r);
+            const bool split_round = split_live && nhub > 0;
+            planned = split_round;
+            const ActiveLists al = lists_of(true);
+            plan = plan0 + (r & 1);
+            if (split_round) {
+                GC_TIMED(GC_K_OTHER, s, split_plan(r, hub_in, c_hub_in, nhub, al));
                 GC_LAUNCHED();
             }
+            if (nlo) {
+                GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
+                                                                            sc, (uint32_t)X, randx, dsum, skip, lm, c_lo_out,
+                                                                            dsum_next, rec, c_lo_in)));
+                GC_LAUNCHED();
+            }
+            if (nhub) {
+                // with the masks, long rows of every length take their color here
+                GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
+                                                           randx, dsum, masks ? INT32_MAX : skip, lm, c_lo_out, dsum_next,
+                                                           nlo ? nullptr : rec, c_lo_in));
+                GC_LAUNCHED();
+            }
+            if (split_round && !masks) {
+                GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
+                                             g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
+                                             split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
+                                             ctx->hub_cnt, dsum));
+                GC_LAUNCHED();
+            }
+            if (nlo) {
+                GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
+                                                                            c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
+                                                                            sp, skip, lm, al)));
+                GC_LAUNCHED();
+            }
+            if (nhub) {
+                GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
+                                                           c_lo_out, hub_out, c_hub_out, sp, skip, lm, al));
+                GC_LAUNCHED();
+            }
+            if (split_round) {
+                GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
+                                             g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
+                                             split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
+                                             al));
+                GC_LAUNCHED();
+                if (masks) {
+                    GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
+                                                                                      colors, ctx->hub_v, ctx->hub_first,
+                                                                                      plan, split_len, lm, al));
+                    GC_LAUNCHED();
+                }
+            }
+            if (lists && nhub > 0) acur ^= 1;  // this round's surviving entries are the next round's lists
+            cur = nxt;
+            r++;
         }
-        if (lists && nhub > 0) acur ^= 1;  // this round's surviving entries are the next round's lists
-        cur = nxt;
-        r++;
     }
     if (st) {
         st->rounds = (int32_t)sizes.size();

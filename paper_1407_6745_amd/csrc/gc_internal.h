@@ -43,6 +43,7 @@ enum {
     S_WL = 16,       // initial coloring: 4 worklist counts + two degree-sum slots (16..21)
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
+    S_REC = 26,      // rounds queued ahead (26..33): input size, previous round's degree sum
     S_COUNT = 64
 };
 
