@@ -970,7 +970,10 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
         if (status) return status;
     }
     const int hist_grid = hist_grid_for(ctx, n, block);
-    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8 * (S_ERR - S_MAXC + 1), s));  // max, min, error flags
+    // max, min, error flags (and the conflict count, which its users clear
+    // anyway): 32 aligned bytes, one fill launch
+    static_assert(S_MAXC == 2 && S_ERR == 4 && S_CONFLICTS == 5, "scalar slots cleared per pass");
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 32, s));
     GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, deg_split,
                                                              split_len, ctx->ccap, ctx->hist, ctx->histw, ctx->hist_s,
                                                              ctx->hist_sc, ctx->hcopy, ctx->scal));
@@ -1078,7 +1081,10 @@ extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, 
     const int block = 256;
     // class sizes and order (no split bins: only the ranks are used)
     const int hist_grid = hist_grid_for(ctx, n, block);
-    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 8 * (S_ERR - S_MAXC + 1), s));  // max, min, error flags
+    // max, min, error flags (and the conflict count, which its users clear
+    // anyway): 32 aligned bytes, one fill launch
+    static_assert(S_MAXC == 2 && S_ERR == 4 && S_CONFLICTS == 5, "scalar slots cleared per pass");
+    GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 32, s));
     GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, ctx->tune.deg_wave, 0,
                                                              ctx->tune.split_len, ctx->ccap, ctx->hist, ctx->histw,
                                                              ctx->hist_s, ctx->hist_sc, ctx->hcopy, ctx->scal));
