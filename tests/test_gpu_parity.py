@@ -141,6 +141,41 @@ def test_not_converged(gc):
         gc.init_color(rp, col, gc.FIRST_FIT, 1, 4, max_rounds=7)
 
 
+@pytest.mark.parametrize("max_rounds", list(range(1, 12)))
+def test_round_cap_at_every_queue_position(gc, max_rounds):
+    """Where no launch needs a host read, the initial coloring queues several
+    rounds per read-back of the worklist counts; a round cap at any position
+    of such a queue stops after exactly that round, with the oracle's colors
+    and per-round statistics (K_30 with First Fit takes 30 rounds)."""
+    g = gen.complete(30)
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, gc.FIRST_FIT, 1, 4, max_rounds=max_rounds, allow_not_converged=True)
+    ref = oracle.init_color(g, oracle.FIRST_FIT, 1, 4, max_rounds=max_rounds)
+    assert st["status"] == gc.ERR_NOT_CONVERGED and ref.status == oracle.ERR_NOT_CONVERGED
+    assert st["rounds"] == max_rounds == ref.stats["rounds"]
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    got = c.cpu().numpy()
+    assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
+
+
+@pytest.mark.parametrize("extra", [0, 1, 2, 3, 4, 5])
+def test_queued_rounds_end_anywhere(gc, extra):
+    """The coloring ends at every offset inside a queue of rounds: caps from
+    the round count R to R + 5 all converge with the same colors and the
+    same per-round statistics as the oracle (empty queued rounds leave no
+    trace)."""
+    g = gen.er(3001, 15007, 3)
+    ref = oracle.init_color(g, oracle.RANDOM_X, 4, 9)
+    R = ref.stats["rounds"]
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, gc.RANDOM_X, 4, 9, max_rounds=R + extra)
+    assert st["rounds"] == R
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    assert np.array_equal(c.cpu().numpy(), ref.colors)
+
+
 def test_empty_graph_and_bad_args(gc):
     rp = torch.zeros(1, dtype=torch.int32, device="cuda")
     col = torch.zeros(0, dtype=torch.int32, device="cuda")
