@@ -1,7 +1,7 @@
 """Writes tests/golden/full_size.json: the oracle's results on the full-size
 workloads, as SHA-256 digests of the color arrays plus the round and color
 statistics, so that GPU tests can compare whole colorings at full size
-without running the oracle on the GPU machine.
+without running the oracle where the GPU tests run.
 
 Calls only gen/ (inputs) and oracle/ (expected values).  Run from the
 repository root:  python tests/golden/make_full_size.py
