@@ -155,7 +155,8 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
 // sbase[s]: first hub slot of segment 3s + 2.  A chunk is 64 / G vertices of
 // a bin-0 segment, one vertex of a bin-1 segment, split_len entries of a row
 // of a bin-2 segment.
-__global__ void __launch_bounds__(PERM_THREADS) k_class_order(int32_t ccap, int32_t perm, uint32_t s_perm, int32_t vpc,
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS) k_class_order(int32_t ccap, int32_t perm, uint32_t s_perm, int32_t vpc,
                                                                int32_t hub_max_rank, int32_t *hist, int32_t *histw, int32_t *hist_s,
                                                                int32_t *hist_sc, int32_t *cls, int32_t *pi,
                                                                int32_t *rank, int32_t *off, int32_t *coff,
@@ -986,8 +987,10 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
     int32_t maxdeg_o = 0;
     status = gc_graph_max_degree(ctx, g, s, &maxdeg_o);
     if (status) return status;
-    const int order_threads = (int64_t)maxdeg_o + GC_MAX_X + 1 <= ORDER_LDS ? PERM_THREADS_SMALL : PERM_THREADS;
-    GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, order_threads, 0, s>>>(
+    const bool order_small = (int64_t)maxdeg_o + GC_MAX_X + 1 <= ORDER_LDS;
+    const int order_threads = order_small ? PERM_THREADS_SMALL : PERM_THREADS;
+    auto order_kernel = order_small ? k_class_order<PERM_THREADS_SMALL> : k_class_order<PERM_THREADS>;
+    GC_TIMED(GC_K_ORDER, s, order_kernel<<<1, order_threads, 0, s>>>(
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, hub_max_rank, ctx->hist,
                                 ctx->histw, ctx->hist_s, ctx->hist_sc, (int32_t *)ctx->keys, ctx->pi, ctx->rank,
                                 ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->hcopy, ctx->scal));
@@ -1098,7 +1101,7 @@ extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, 
                                                              ctx->tune.split_len, ctx->ccap, ctx->hist, ctx->histw,
                                                              ctx->hist_s, ctx->hist_sc, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
-    GC_TIMED(GC_K_ORDER, s, k_class_order<<<1, PERM_THREADS, 0, s>>>(
+    GC_TIMED(GC_K_ORDER, s, k_class_order<PERM_THREADS><<<1, PERM_THREADS, 0, s>>>(
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 1,
                                 64 * ctx->tune.hub_words - 1, ctx->hist, ctx->histw, ctx->hist_s, ctx->hist_sc,
                                 (int32_t *)ctx->keys, ctx->pi, ctx->rank, ctx->off, ctx->coff, ctx->cursor, ctx->sbase,
