@@ -14,8 +14,39 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+# Builds of the same source: "plain" (gcc -O2) for the tests; "fast" (-O3,
+# AVX2-level x86-64-v3 rather than -march=native, because the library is
+# built on one host and may run on another) for the timed CPU baseline;
+# "san" (AddressSanitizer + UndefinedBehaviorSanitizer, any report fatal) for
+# a sanitizer run of the CPU suite, which needs the sanitizer runtimes
+# preloaded into the Python process (see tests/test_oracle_sanitized.py).
+VARIANTS = {
+    "plain": ("liboracle.so", ["-O2"]),
+    "fast": ("liboracle_o3.so", ["-O3", "-march=x86-64-v3"]),
+    "san": ("liboracle_san.so", ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                                 "-fno-sanitize-recover=undefined"]),
+}
+_variant = os.environ.get("ORACLE_VARIANT", "plain")
 _lib = None
+
+
+def use_variant(name: str) -> None:
+    """Select the build that _load() opens (before the first oracle call)."""
+    global _variant
+    if name not in VARIANTS:
+        raise ValueError(f"unknown oracle build {name!r}")
+    if _lib is not None and name != _variant:
+        raise RuntimeError(f"the {_variant!r} oracle build is already loaded")
+    _variant = name
+
+
+def variant() -> str:
+    return _variant
+
+
+def lib_path(name: str | None = None) -> str:
+    return os.path.join(_HERE, VARIANTS[name or _variant][0])
 
 OK, ERR_ARG, ERR_GRAPH, ERR_COLORING, ERR_OOM, ERR_NOT_CONVERGED = 0, 1, 2, 3, 4, 6
 FIRST_FIT, RANDOM_X = 0, 1
@@ -34,25 +65,31 @@ class Stats(ctypes.Structure):
                 "losers_total": self.losers_total}
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle (plain C, -O2, single-threaded) into liboracle.so."""
+def build(verbose: bool = False, variants=("plain", "fast")) -> str:
+    """Compile the oracle (plain C, single-threaded) into the requested builds;
+    returns the path of the first."""
     src = os.path.join(_HERE, "gc_oracle.c")
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", src, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    paths = []
+    for name in variants:
+        out = lib_path(name)
+        tmp = out + ".tmp"
+        cmd = ["gcc", *VARIANTS[name][1], "-fPIC", "-shared", "-std=c11", "-Wall", src, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+        paths.append(out)
+    return paths[0]
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    path = lib_path()
+    if not os.path.exists(path):
+        build(variants=(_variant,))
+    lib = ctypes.CDLL(path)
     i32p = ctypes.POINTER(ctypes.c_int32)
     i64p = ctypes.POINTER(ctypes.c_int64)
     u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
@@ -310,16 +347,12 @@ def recolor_d2(g, colors, perm=PERM_REVERSE, seed=1, pass_=0, sq=None) -> Recolo
 
 
 def validate_d2(g, colors, sq=None) -> tuple[int, int]:
-    """(vertices sharing their positive color with some vertex at distance 1 or
-    2, vertices with color <= 0): a coloring is a distance-2 coloring iff both
-    are 0."""
-    s = square(g) if sq is None else sq
-    c = np.ascontiguousarray(colors, dtype=np.int64)[:g.n]
-    src = np.repeat(np.arange(g.n), np.diff(s.row_ptr.astype(np.int64)))
-    same = (c[src] == c[s.col]) & (c[src] > 0)
-    bad = np.zeros(g.n, bool)
-    bad[src[same]] = True
-    return int(bad.sum()), int((c <= 0).sum())
+    """(pairs u < w within two edges of each other with equal positive colors,
+    vertices with color <= 0).  Section 1's distance-k condition is stated per
+    pair of vertices, so the check counts pairs, as the distance-1 check counts
+    edges: it is the distance-1 check on the square graph.  A coloring is a
+    distance-2 coloring iff both are 0."""
+    return validate(square(g) if sq is None else sq, colors)
 
 
 def run_pipeline(g, select, X, seed, perm_schedule, max_rounds=0):

@@ -541,7 +541,7 @@ static int bt_color(int32_t v, int32_t n, const int32_t *rp, const int32_t *col,
     for (int32_t x = 1; x <= lim; x++) {
         int ok = 1;
         for (int32_t e = rp[v]; e < rp[v + 1]; e++)
-            if (col[e] < v && c[col[e]] == x) { ok = 0; break; }
+            if (col[e] >= 0 && col[e] < v && c[col[e]] == x) { ok = 0; break; }
         if (!ok) continue;
         c[v] = x;
         if (bt_color(v + 1, n, rp, col, k, c)) return 1;

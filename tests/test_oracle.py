@@ -568,7 +568,7 @@ def test_validate_d2_bruteforce_and_injected():
         near = _dist2_pairs_scipy(g)
         c = rng.integers(1, 6, size=g.n).astype(np.int32)
         c[rng.random(g.n) < 0.1] = 0
-        want = sum(1 for u in range(g.n) if any(near[u, w] and c[u] == c[w] > 0 for w in range(g.n)))
+        want = sum(1 for u in range(g.n) for w in range(u + 1, g.n) if near[u, w] and c[u] == c[w] > 0)
         assert oracle.validate_d2(g, c) == (want, int((c <= 0).sum()))
     # a proper distance-2 coloring, then one injected conflict at distance exactly 2 (path 0-1-2)
     g = gen.path(9)
@@ -576,7 +576,7 @@ def test_validate_d2_bruteforce_and_injected():
     assert oracle.validate_d2(g, c) == (0, 0)
     assert oracle.validate(g, c) == (0, 0)
     c[0] = c[2]  # vertices 0 and 2 are two edges apart; vertex 1 keeps them distance-1 proper
-    assert oracle.validate_d2(g, c) == (2, 0) and oracle.validate(g, c) == (0, 0)
+    assert oracle.validate_d2(g, c) == (1, 0) and oracle.validate(g, c) == (0, 0)
 
 
 def _structurally_orthogonal(g, c):
@@ -688,3 +688,24 @@ def test_recolor_d2_closed_form_and_invariants():
     # a distance-1 coloring that is not a distance-2 coloring is rejected
     g = gen.path(5)
     assert oracle.recolor_d2(g, np.array([1, 2, 1, 2, 1], np.int32)).status == oracle.ERR_COLORING
+
+
+def test_checkpoint_resume_identity_oracle(tmp_path):
+    """Ten recoloring passes equal five passes, a checkpoint of the colors to a
+    text file, a restore from it and five more passes (pass indices 5..9): a
+    pass depends only on its input coloring, the seed and the pass index."""
+    g = gen.rmat(11, 16, seed=3)
+    c0 = oracle.init_color(g, oracle.RANDOM_X, 4, 3).colors
+    whole = c0
+    for p in range(10):
+        whole = oracle.recolor(g, whole, oracle.PERM_RANDOM, 3, p).colors
+    half = c0
+    for p in range(5):
+        half = oracle.recolor(g, half, oracle.PERM_RANDOM, 3, p).colors
+    f = tmp_path / "colors.txt"
+    np.savetxt(f, half, fmt="%d")
+    back = np.loadtxt(f, dtype=np.int32)
+    for p in range(5, 10):
+        back = oracle.recolor(g, back, oracle.PERM_RANDOM, 3, p).colors
+    assert np.array_equal(back, whole)
+    assert oracle.validate(g, whole) == (0, 0)
