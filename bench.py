@@ -74,48 +74,105 @@ def recorded_traffic(workload, tuning):
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(g, select, X, perms, passes, seed, method="rc", budget_s=12.0):
-    """The oracle (single thread, as it stands) on whole steps of the same workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+class OneCore:
+    """Pins the calling thread to one host core (the lowest this process may
+    use) while the block runs, in-process (no re-exec); restores the mask."""
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0)
+        self.core = min(self.saved)
+        os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.saved)
+        return False
+
+
+ORACLE_BUILD = "gcc -O3 -march=x86-64-v3, single thread"
+
+
+def _oracle_fast():
     import oracle
 
+    oracle.use_variant("fast")
+    return oracle
+
+
+def cpu_baseline(g, select, X, perms, passes, seed, method="rc", budget_s=20.0, repeats=3):
+    """The oracle as it stands (plain single-threaded C, -O3 build) on the same
+    workload, pinned to one host core: the initial coloring and each pass timed
+    separately, median over `repeats` repetitions.  A workload whose first
+    repetition exceeds budget_s / repeats is timed once, on the initial
+    coloring and as many passes as fit (at least one).  Returns (record, colors
+    after the timed passes, number of timed passes)."""
+    oracle = _oracle_fast()
     sel = oracle.FIRST_FIT if select == "FIRST_FIT" else oracle.RANDOM_X
     recolor = oracle.recolor if method == "rc" else oracle.arc_recolor
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        r = oracle.init_color(g, sel, X, seed)
-        c = r.colors
-        for p in range(passes):
-            c = recolor(g, c, perms[p], seed, p).colors
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or el / steps * (steps + 1) > 2.5 * budget_s:
-            break
-    value = g.m * (passes + 1) * steps / el / 1e9
-    return {"value": value, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full step(s) (initial coloring + {passes} passes) of the same graph, one thread",
-            "seconds": round(el, 3)}, c
+    runs, k = [], passes
+    with OneCore() as pin:
+        t_start = time.perf_counter()
+        for r in range(repeats):
+            t0 = time.perf_counter()
+            c = oracle.init_color(g, sel, X, seed).colors
+            t_init = time.perf_counter() - t0
+            t_pass = []
+            for p in range(k):
+                t0 = time.perf_counter()
+                c = recolor(g, c, perms[p], seed, p).colors
+                t_pass.append(time.perf_counter() - t0)
+                if r == 0 and p + 1 < k and time.perf_counter() - t_start > budget_s / repeats:
+                    k = p + 1
+            runs.append((t_init, t_pass))
+            if r == 0 and time.perf_counter() - t_start > budget_s / repeats:
+                break
+    med_init = float(np.median([x[0] for x in runs]))
+    med_pass = [float(np.median([x[1][p] for x in runs])) for p in range(k)]
+    total = med_init + sum(med_pass)
+    rec = {"value": round(g.m * (1 + k) / total / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "sample": f"initial coloring + the first {k} of {passes} passes of the same graph, "
+                     f"{len(runs)} repetition(s), median per phase, one thread pinned to one core",
+           "build": ORACLE_BUILD, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "pinned_core": pin.core,
+           "init_s": round(med_init, 4), "pass_s": [round(t, 4) for t in med_pass],
+           "seconds": round(sum(sum(x[1]) + x[0] for x in runs), 3)}
+    return rec, c, k
 
 
 def batch_cpu_baseline(b, X, passes, seed, budget_s=12.0):
-    """The oracle (single thread, as it stands) on the first graphs of the batch, whole method per graph."""
-    import oracle
+    """The oracle (single thread, as it stands, -O3 build) on the first graphs
+    of the batch, whole method per graph, pinned to one core."""
     import paper_1407_6745_amd as gc
 
-    t0 = time.perf_counter()
-    done = 0
-    edges = 0
-    while done < b.num_graphs and time.perf_counter() - t0 < budget_s:
-        g = b.graph(done)
-        sg = gc.batch_graph_seed(seed, done)
-        c = oracle.init_color(g, oracle.RANDOM_X, X, sg).colors
-        for p in range(passes):
-            c = oracle.recolor(g, c, oracle.PERM_REVERSE, sg, p).colors
-        edges += g.m
-        done += 1
-    el = time.perf_counter() - t0
+    oracle = _oracle_fast()
+    with OneCore() as pin:
+        t0 = time.perf_counter()
+        done = 0
+        edges = 0
+        while done < b.num_graphs and time.perf_counter() - t0 < budget_s:
+            g = b.graph(done)
+            sg = gc.batch_graph_seed(seed, done)
+            c = oracle.init_color(g, oracle.RANDOM_X, X, sg).colors
+            for p in range(passes):
+                c = oracle.recolor(g, c, oracle.PERM_REVERSE, sg, p).colors
+            edges += g.m
+            done += 1
+        el = time.perf_counter() - t0
     return {"value": round(done / el, 3), "unit": "graphs/s", "cores": 1, "kind": "oracle",
-            "sample": f"graphs 0..{done - 1} of the batch ({edges} undirected edges), whole method each, one thread",
+            "sample": f"graphs 0..{done - 1} of the batch ({edges} undirected edges), whole method each, "
+                      f"one thread pinned to one core",
+            "build": ORACLE_BUILD, "cpu_model": cpu_model(), "pinned_core": pin.core,
             "gteps": round(edges * (passes + 1) / el / 1e9, 4), "seconds": round(el, 3)}
 
 
@@ -127,9 +184,9 @@ def batch_cpu_baseline_all_cores(b, X, passes, seed, budget_s=10.0):
     import threading
     from concurrent.futures import ThreadPoolExecutor
 
-    import oracle
     import paper_1407_6745_amd as gc
 
+    oracle = _oracle_fast()
     oracle._load()
     workers = len(os.sched_getaffinity(0))
     ids = itertools.count()
@@ -160,6 +217,7 @@ def batch_cpu_baseline_all_cores(b, X, passes, seed, budget_s=10.0):
     return {"value": round(done / el, 3), "unit": "graphs/s", "cores": workers, "kind": "oracle",
             "sample": f"the first {done} graphs of the batch ({edges} undirected edges), whole method each, "
                       f"one graph per task on {workers} threads",
+            "build": ORACLE_BUILD.replace("single thread", "one thread per task"), "cpu_model": cpu_model(),
             "gteps": round(edges * (passes + 1) / el / 1e9, 4), "seconds": round(el, 3)}
 
 
@@ -238,6 +296,10 @@ def run_batch(args):
     identical = bool(torch.equal(plain, colors))
     log(f"[bench] plain: {t_p:.2f} s, {G / t_p:.0f} graphs/s; identical={identical}")
     m_tot = nnz_tot // 2
+    # algorithmic bytes of one launch, a lower bound: round 0 of every graph
+    # (16 per entry + 28 per vertex) and its passes (8 per entry + 12 per
+    # vertex each); later rounds of the initial colorings are not counted
+    batch_bytes = 16 * nnz_tot + 28 * n_tot + passes * (8 * nnz_tot + 12 * n_tot)
     out = {
         "metric": "graphs/s (batched)", "value": round(G / t_b, 2), "unit": "graphs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 3), "higher_is_better": True,
@@ -250,6 +312,11 @@ def run_batch(args):
         "plain": {"graphs_per_s": round(G / t_p, 2), "seconds": round(t_p, 3),
                   "gteps": round(m_tot * (passes + 1) / t_p / 1e9, 3)},
         "speedup_vs_plain": round(t_p / t_b, 2),
+        "roofline": {"kernel": "k_batch (whole method per graph, one launch)", "bound": "hbm",
+                     "achieved": round(batch_bytes / t_b / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(batch_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": batch_bytes, "avg_launch_ms": round(t_b * 1e3, 3),
+                     "bytes_note": "lower bound: initial-coloring rounds after the first not counted"},
         "identical_to_plain": identical,
         "all_converged": bool((pg[:, 3] == 0).all()),
         "colors_final": {"min": int(pg[:, 2].min()), "mean": round(float(pg[:, 2].mean()), 3),
@@ -263,7 +330,7 @@ def run_batch(args):
         out["cpu_baseline_all_cores"] = batch_cpu_baseline_all_cores(b, X, passes, args.seed)
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_d2(args):
@@ -356,7 +423,7 @@ def run_d2(args):
         "kernel_ms_one_step": {k: {"launches": v[0], "total_ms": round(v[1], 4)} for k, v in kt.items() if v[0]},
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def pct(xs, q):
@@ -487,7 +554,7 @@ def run_serve(args):
         "all_ok": ok, "identical_to_plain": same, "checked": len(sample),
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -511,6 +578,9 @@ def main():
                     help="recoloring: synchronous class walk (rc) or asynchronous speculative rounds (arc)")
     ap.add_argument("--schedule", default="fixed", choices=("fixed", "ndrand5", "ndrand10", "ndrand2i"),
                     help="class order per pass: the workload's fixed order, or a hybrid ND/RAND schedule")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="mesh128: skip the RMAT-22, batch and serving sub-records of the default line")
+    ap.add_argument("--sub-steps", type=int, default=5, help="timed steps of the RMAT-22 and batch sub-records")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -530,23 +600,54 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch4096":
-        return run_batch(args)
-    if args.workload == "serve":
-        return run_serve(args)
-    if args.workload == "mesh128d2":
-        return run_d2(args)
+        out = run_batch(args)
+    elif args.workload == "serve":
+        out = run_serve(args)
+    elif args.workload == "mesh128d2":
+        out = run_d2(args)
+    else:
+        out = run_graph(args, args.workload)
+        if args.workload == "mesh128" and not args.no_sub:
+            # the other targets of the benchmark, one record each beside the headline
+            out["sub_workloads"] = run_sub_workloads(args)
+    print(json.dumps(out), flush=True)
 
+
+def run_sub_workloads(args):
+    import copy
+
+    import torch
+
+    subs = {}
+    for name, fn in (("rmat22", lambda a: run_graph(a, "rmat22")), ("batch4096", run_batch), ("serve", run_serve)):
+        a = copy.copy(args)
+        a.workload, a.tune = name, ""
+        a.steps, a.warmup = (args.sub_steps, 1) if name != "serve" else (args.steps, args.warmup)
+        t0 = time.perf_counter()
+        log(f"[bench] sub-workload {name} ...")
+        try:
+            rec = fn(a)
+        except Exception as e:  # a failing sub-record must not hide the headline
+            rec = {"error": f"{type(e).__name__}: {e}"}
+        rec["wall_s"] = round(time.perf_counter() - t0, 1)
+        subs[name] = rec
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return subs
+
+
+def run_graph(args, workload):
     import torch
 
     import gen
     import paper_1407_6745_amd as gc
 
-    desc, build, select, X, perm, passes = WORKLOADS[args.workload]
+    desc, build, select, X, perm, passes = WORKLOADS[workload]
     sel = getattr(gc, select)
     pm = gc.PERM_NAMES[perm]
     t0 = time.perf_counter()
     g = build(gen)
-    log(f"[bench] graph {args.workload}: n={g.n} nnz={g.nnz} max_deg={g.max_deg} ({time.perf_counter() - t0:.1f}s)")
+    log(f"[bench] graph {workload}: n={g.n} nnz={g.nnz} max_deg={g.max_deg} ({time.perf_counter() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
@@ -639,7 +740,7 @@ def main():
     achieved = walk_bytes / (walk_avg_ms / 1e3) / 1e9 if walk_launches else 0.0
     roofline = {"kernel": "k_walk_flow (recoloring class walk)", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": recorded_traffic(args.workload, ctx.tuning),
+                "traffic": recorded_traffic(workload, ctx.tuning),
                 "bytes_per_launch": walk_bytes, "avg_launch_ms": round(walk_avg_ms, 5), "launches": walk_launches,
                 "dominant_kind": dom}
     out = {
@@ -666,16 +767,27 @@ def main():
         "kernel_ms_one_step": {k: {"launches": v[0], "total_ms": round(v[1], 4)} for k, v in kt.items() if v[0]},
         "roofline": roofline,
     }
+    # the initial coloring against its algorithmic bytes (16 per scanned entry
+    # + 28 per vertex of each round, from the round statistics)
+    init_bytes = sum(16 * d + 28 * w for w, d in zip(round_sizes, round_degsum))
+    out["init"]["algorithmic_bytes"] = init_bytes
+    out["init"]["frac_of_peak"] = round(init_bytes / (t_init / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    out["recolor_pass"]["frac_of_peak"] = round(out["recolor_pass"]["gbs"] / HBM_PEAK_GBS, 4)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cb, cref = cpu_baseline(g, select, X, perms, passes, args.seed, args.method)
+        cb, cref, k = cpu_baseline(g, select, X, perms, passes, args.seed, args.method)
+        if k < passes:  # the GPU's colors after the same passes
+            gc.init_color(rp, col, sel, X, args.seed, out=colors, stats=False, ctx=ctx)
+            for p in range(k):
+                recolor_fn(rp, col, colors, perms[p], args.seed, p, out=colors, stats=False, ctx=ctx)
+            c_step = colors.clone()
+        cb["matches_gpu"] = bool(np.array_equal(cref, c_step.cpu().numpy()))
         out["cpu_baseline"] = cb
-        import numpy as np
-
-        out["cpu_baseline"]["matches_gpu"] = bool(np.array_equal(cref, c_step.cpu().numpy()))
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    ctx.raise_status()
+    ctx.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -29,7 +29,13 @@
  *
  * Errors: every call returns a gc_status; nothing aborts and no C++
  * exception crosses the ABI.  gc_ctx_last_error gives a message for the last
- * failure on a context.
+ * failure on a context.  Device-side failures of asynchronous work (a bounded
+ * wait of the persistent recoloring walk that gave up, or a walk whose
+ * workgroups were not all resident with check_resident on) are sticky: the
+ * kernel records them in the context, and the next call on that context that
+ * synchronizes (any call with host results, any call given a gc_stats, or
+ * gc_ctx_status) returns GC_ERR_DEVICE and clears the record.  The colors
+ * written by the failed pass are then unspecified.
  */
 #ifndef GC_H
 #define GC_H
@@ -44,7 +50,8 @@ typedef enum gc_status {
     GC_OK = 0,
     GC_ERR_ARG = 1,            /* bad argument (NULL pointer, size above the context's capacity, ...) */
     GC_ERR_GRAPH = 2,          /* gc_check_csr: the CSR breaks a precondition */
-    GC_ERR_COLORING = 3,       /* gc_recolor: input coloring has a color <= 0 or above the capacity */
+    GC_ERR_COLORING = 3,       /* gc_recolor: input coloring has a color <= 0 or above the capacity, or (with
+                                  the check_input knob) is not a proper coloring */
     GC_ERR_OOM = 4,            /* device or host allocation failed */
     GC_ERR_DEVICE = 5,         /* a HIP runtime call failed, or a kernel's bounded wait ran out */
     GC_ERR_NOT_CONVERGED = 6   /* gc_init_color stopped at max_rounds with vertices still uncolored */
@@ -100,7 +107,8 @@ typedef struct gc_stats {
     int32_t reserved;
 } gc_stats;
 
-/* Tuning knobs.  No knob changes any result, only the speed. */
+/* Tuning knobs.  No knob changes any result, only the speed (spin_limit aside, whose failures are
+   reported as a device error). */
 typedef struct gc_tuning {
     int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
     int32_t deg_wave;      /* rows with more than deg_wave entries get a whole wavefront per vertex */
@@ -129,6 +137,15 @@ typedef struct gc_tuning {
     int32_t batch_wg_per_cu; /* gc_batch_color: workgroups per compute unit (0 = 4; at most 5 fit) */
     int32_t batch_order;   /* gc_batch_color: 0 = graphs taken in id order, 1 = largest (most entries) first
                               (batches of at most 8192 graphs; larger ones keep id order) */
+    int32_t spin_limit;    /* persistent walk: polls of one bounded dependency wait before it gives up
+                              (0 = 2^20, about a second).  A wait that gives up leaves a wrong color and
+                              raises the context's sticky device error (see gc_ctx_status); a small value
+                              only serves to test that error path */
+    int32_t check_input;   /* 1 = gc_recolor, gc_recolor_d2 and gc_arc_recolor first check that colors_in is
+                              a proper coloring (distance 2 for gc_recolor_d2) with every color >= 1, and
+                              return GC_ERR_COLORING otherwise (one validation sweep; synchronizes) */
+    int32_t trace;         /* 1 = the persistent walk records when each class finishes (profiling aid, see
+                              gc_ctx_get_trace; one device atomic per vertex) */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);
@@ -141,6 +158,14 @@ const char *gc_status_string(gc_status s);
 gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, gc_ctx **out);
 void gc_ctx_destroy(gc_ctx *ctx);
 const char *gc_ctx_last_error(const gc_ctx *ctx);
+
+/*
+ * Synchronizes `stream` and reports the context's sticky device error: GC_OK
+ * if no asynchronous work since the last report failed on the device, else
+ * GC_ERR_DEVICE (message in gc_ctx_last_error), after which the record is
+ * clear.  For callers that queue passes without gc_stats.
+ */
+gc_status gc_ctx_status(gc_ctx *ctx, void *stream);
 gc_status gc_ctx_get_tuning(const gc_ctx *ctx, gc_tuning *t);
 gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t);
 
@@ -167,6 +192,18 @@ enum {
     GC_K_WALK = 6, GC_K_COUNT = 7, GC_K_BATCH = 8, GC_K_OTHER = 9, GC_KERNEL_KINDS = 10
 };
 gc_status gc_ctx_set_timing(gc_ctx *ctx, int enable);
+
+/*
+ * Class-completion trace of the last persistent recoloring walk run with the
+ * trace knob (profiling aid for the dependency chain of section 3's class
+ * steps).  Synchronizes `stream`.  out[0] = 0 (walk start), out[1] = walk
+ * end, out[2 + 2s] = when the last vertex of rank s published its color,
+ * out[3 + 2s] = the same for the split rows of rank s (-1 if none), all in
+ * nanoseconds since the first workgroup started.  Fills min(cap, 2 + 2k)
+ * entries (k = the pass's classes) and sets *count to 2 + 2k.  GC_ERR_ARG if
+ * no walk was traced on ctx.
+ */
+gc_status gc_ctx_get_trace(gc_ctx *ctx, int64_t *out, int64_t cap, int64_t *count, void *stream);
 gc_status gc_ctx_get_timing(gc_ctx *ctx, int64_t *launches, double *ms, int cap);
 
 /*
@@ -254,21 +291,29 @@ gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t se
                          const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
 
 /*
+ * Check of the problem statement's condition (section 1: a distance-1
+ * coloring gives the two ends of every edge different colors).
  * conflict_edges: adjacency entries (u, w) with u < w and colors[u] ==
- * colors[w] > 0 (each undirected edge once); uncolored: vertices with
- * colors[v] <= 0.  Host outputs; synchronizes.  Either pointer may be NULL.
+ * colors[w] > 0 (each undirected edge once; a duplicated entry counts once
+ * per copy); uncolored: vertices with colors[v] <= 0.  colors is a proper
+ * coloring iff both are 0.  colors: device, n entries.  Host outputs;
+ * synchronizes.  Either pointer may be NULL.  Errors: GC_ERR_ARG for a NULL
+ * context, graph or (n > 0) colors, or a graph above the context's capacity;
+ * GC_ERR_DEVICE if a HIP call fails.
  */
 gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
                       int64_t *uncolored, void *stream);
 
 /*
- * Distance-2 check (section 1 with k = 2).  conflict_vertices: vertices v
- * with colors[v] > 0 shared by some vertex within two edges of v;
- * uncolored: vertices with colors[v] <= 0.  colors is a distance-2 coloring
- * iff both are 0.  Rows shorter than 2^25 entries.  Host outputs;
+ * Distance-2 check (section 1's distance-k condition with k = 2: two
+ * vertices joined by a path of at most two edges differ).
+ * conflict_pairs: unordered pairs {u, w}, u != w, within two edges of each
+ * other with colors[u] == colors[w] > 0, each pair once however many paths
+ * join it; uncolored: vertices with colors[v] <= 0.  colors is a distance-2
+ * coloring iff both are 0.  Rows shorter than 2^25 entries.  Host outputs;
  * synchronizes.  Either pointer may be NULL.
  */
-gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_vertices,
+gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_pairs,
                          int64_t *uncolored, void *stream);
 
 /*
@@ -288,8 +333,16 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, i
                       uint64_t seed, int32_t *colors, gc_tuning *best, double *best_ms, void *stream);
 
 /*
- * num_colors: distinct positive values in colors[0..n); max_color: the
- * largest (0 if none).  Host outputs; synchronizes.
+ * Color counts of section 1: the number of colors of a coloring is its
+ * largest color, and a coloring partitions the vertices into independent
+ * sets, one per color in use.  num_colors: distinct positive values in
+ * colors[0..n) (the number of non-empty classes); max_color: the largest
+ * (0 if none).  The two agree for First Fit and recolored outputs; Random-X
+ * can leave unused colors below the largest.  colors: device, n entries.
+ * Host outputs; synchronizes; either output pointer may be NULL.  Errors:
+ * GC_ERR_ARG for a NULL context, n < 0, n above the context's capacity, or
+ * colors NULL with n > 0; GC_ERR_OOM if the color bitmap cannot grow to the
+ * largest color; GC_ERR_DEVICE if a HIP call fails.
  */
 gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors, int32_t *max_color,
                           void *stream);

@@ -5,9 +5,11 @@ streams.  The binding refuses to run without the built library.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
+import weakref
 
 import numpy as np
 
@@ -48,10 +50,12 @@ class Tuning(ctypes.Structure):
                 ("grid_per_cu", ctypes.c_int32), ("walk_mode", ctypes.c_int32), ("xcd_chunks", ctypes.c_int32),
                 ("check_resident", ctypes.c_int32), ("deg_split", ctypes.c_int32), ("split_len", ctypes.c_int32),
                 ("hub_words", ctypes.c_int32), ("walk_group", ctypes.c_int32),
-                ("d2_star", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32), ("batch_order", ctypes.c_int32)]
+                ("d2_star", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32), ("batch_order", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32), ("check_input", ctypes.c_int32), ("trace", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
-                 "split_len", "hub_words", "walk_group", "d2_star", "batch_wg_per_cu", "batch_order")
+                 "split_len", "hub_words", "walk_group", "d2_star", "batch_wg_per_cu", "batch_order", "spin_limit",
+                 "check_input", "trace")
 
 
 class BatchArgs(ctypes.Structure):
@@ -68,6 +72,9 @@ _SIGS = {
     "gc_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
     "gc_ctx_destroy": (None, [ctypes.c_void_p]),
     "gc_ctx_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gc_ctx_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gc_ctx_get_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "gc_ctx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "gc_ctx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "gc_check_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_void_p]),
@@ -144,6 +151,42 @@ def _torch():
     return torch
 
 
+# Every live context and server, so that they are destroyed at interpreter
+# exit while the HIP runtime is still up (before module teardown and the C
+# library's exit handlers), servers first since their slots own contexts.
+_live_contexts = weakref.WeakSet()
+_live_servers = weakref.WeakSet()
+
+
+def close_all():
+    """Synchronize the device and destroy every live Server and Context of
+    this process (they are unusable afterwards).  Registered with atexit."""
+    servers, contexts = list(_live_servers), list(_live_contexts)
+    if not servers and not contexts:
+        return
+    for srv in servers:
+        try:
+            srv.close()
+        except Exception:
+            pass
+    try:
+        import torch
+
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for c in contexts:
+        try:
+            c.close()
+        except Exception:
+            pass
+    _default_ctx.clear()
+
+
+atexit.register(close_all)
+
+
 def _stream_ptr(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -163,6 +206,7 @@ class Context:
         if rc:
             raise GCError(rc, f"gc_ctx_create(max_n={max_n}): {status_string(rc)}")
         self.handle = h
+        _live_contexts.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -177,6 +221,29 @@ class Context:
 
     def last_error(self) -> str:
         return lib().gc_ctx_last_error(self.handle).decode()
+
+    def status(self, stream=None) -> int:
+        """Synchronize the stream and return the context's sticky device status
+        (gc_ctx_status): OK, or ERR_DEVICE once for a failure of earlier
+        asynchronous work."""
+        return lib().gc_ctx_status(self.handle, _stream_ptr(stream))
+
+    def walk_trace(self, stream=None) -> dict:
+        """Class-completion trace of the last traced walk (gc_ctx_get_trace), in
+        nanoseconds since the walk started: {"end": t, "class_done": [..k],
+        "split_done": [..k] (-1: no split row of that rank)}."""
+        cnt = ctypes.c_int64()
+        self.check(lib().gc_ctx_get_trace(self.handle, None, 0, ctypes.byref(cnt), _stream_ptr(stream)),
+                   "gc_ctx_get_trace")
+        buf = (ctypes.c_int64 * cnt.value)()
+        self.check(lib().gc_ctx_get_trace(self.handle, buf, cnt.value, ctypes.byref(cnt), _stream_ptr(stream)),
+                   "gc_ctx_get_trace")
+        a = np.frombuffer(buf, dtype=np.int64).copy()
+        return {"end": int(a[1]), "class_done": a[2::2].tolist(), "split_done": a[3::2].tolist()}
+
+    def raise_status(self, stream=None):
+        """status(), raising GCError on a device failure of earlier work."""
+        self.check(self.status(stream), "gc_ctx_status")
 
     def check(self, rc, what):
         if rc not in (OK,):
@@ -361,7 +428,7 @@ def validate(row_ptr, col_idx, colors, ctx: Context | None = None, stream=None):
 
 
 def validate_d2(row_ptr, col_idx, colors, ctx: Context | None = None, stream=None):
-    """(vertices sharing their color with a vertex within two edges, uncolored vertices)."""
+    """(pairs of vertices within two edges of each other sharing a positive color, uncolored vertices)."""
     g = _csr_args(row_ptr, col_idx)
     _check_i32_dev(colors, "colors", g.n)
     ctx = ctx or default_context(g.n, g.nnz)
@@ -564,6 +631,7 @@ class Server:
         if rc:
             raise GCError(rc, f"gc_server_create: {status_string(rc)}")
         self.handle = h
+        _live_servers.add(self)
         self._live = {}
         self._lock = threading.Lock()
         self._next = 0

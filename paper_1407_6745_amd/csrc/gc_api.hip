@@ -2,6 +2,8 @@
 // counting entry points of the C ABI (validate, count colors, CSR check).
 #include "gc_internal.h"
 
+#include <vector>
+
 #include <stdlib.h>
 #include <string.h>
 
@@ -53,7 +55,7 @@ static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
-                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy};
+                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy, c->trace};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -246,6 +248,9 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->batch_wg_per_cu < 0 || t->batch_wg_per_cu > 5)
         return gc_fail(ctx, GC_ERR_ARG, "batch_wg_per_cu must be in [0, 5]");
     if (t->batch_order < 0 || t->batch_order > 1) return gc_fail(ctx, GC_ERR_ARG, "batch_order must be 0 or 1");
+    if (t->spin_limit < 0) return gc_fail(ctx, GC_ERR_ARG, "spin_limit must be >= 0");
+    if (t->check_input < 0 || t->check_input > 1) return gc_fail(ctx, GC_ERR_ARG, "check_input must be 0 or 1");
+    if (t->trace < 0 || t->trace > 1) return gc_fail(ctx, GC_ERR_ARG, "trace must be 0 or 1");
     ctx->tune = *t;
     return GC_OK;
 }
@@ -260,7 +265,64 @@ extern "C" gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap) {
 gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s) {
     GC_HIP(hipMemcpyAsync(ctx->hscal, ctx->scal, S_COUNT * 8, hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
+    if (ctx->hscal[S_STICKY]) {
+        ctx->sticky |= ctx->hscal[S_STICKY];
+        ctx->hscal[S_STICKY] = 0;
+        GC_HIP(hipMemsetAsync(ctx->scal + S_STICKY, 0, 8, s));
+    }
     return GC_OK;
+}
+
+gc_status gc_report(gc_ctx *ctx, gc_status st) {
+    if (st != GC_OK || !ctx || !ctx->sticky) return st;
+    const unsigned long long b = ctx->sticky;
+    ctx->sticky = 0;
+    return gc_fail(ctx, GC_ERR_DEVICE, "earlier asynchronous work on this context failed on the device:%s%s",
+                   (b & 2) ? " a class-walk dependency wait gave up (colors of that pass are wrong)" : "",
+                   (b & 4) ? " class-walk workgroups were not all resident" : "");
+}
+
+gc_status gc_check_input_coloring(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, void *stream, int dist) {
+    if (!ctx->tune.check_input || g->n == 0) return GC_OK;
+    int64_t conflicts = 0, uncolored = 0;
+    gc_status st = dist == 2 ? gc_validate_d2_impl(ctx, g, colors, &conflicts, &uncolored, stream)
+                             : gc_validate_impl(ctx, g, colors, &conflicts, &uncolored, stream);
+    if (st) return st;
+    if (conflicts || uncolored)
+        return gc_fail(ctx, GC_ERR_COLORING, "input is not a proper %scoloring: %lld conflicting %s, %lld vertices <= 0",
+                       dist == 2 ? "distance-2 " : "", (long long)conflicts, dist == 2 ? "pairs" : "edges",
+                       (long long)uncolored);
+    return GC_OK;
+}
+
+extern "C" gc_status gc_ctx_get_trace(gc_ctx *ctx, int64_t *out, int64_t cap, int64_t *count, void *stream) {
+    if (!ctx || cap < 0 || (cap > 0 && !out)) return GC_ERR_ARG;
+    if (count) *count = 0;
+    if (!ctx->trace) return gc_fail(ctx, GC_ERR_ARG, "no traced walk on this context (set the trace knob)");
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    gc_status st = gc_sync_scalars(ctx, s);  // S_K: classes of the last pass
+    if (st) return gc_report(ctx, st);
+    const int64_t k = (int64_t)ctx->hscal[S_K];
+    const int64_t words = 2 + 2 * k;
+    std::vector<unsigned long long> raw((size_t)words);
+    GC_HIP(hipMemcpyAsync(raw.data(), ctx->trace, (size_t)words * 8, hipMemcpyDeviceToHost, s));
+    GC_HIP(hipStreamSynchronize(s));
+    int rate_khz = 0;
+    GC_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device));
+    if (rate_khz <= 0) return gc_fail(ctx, GC_ERR_DEVICE, "wall clock rate unknown");
+    const double ns_per_tick = 1e6 / (double)rate_khz;
+    const unsigned long long t0 = raw[0];
+    for (int64_t i = 0; i < words && i < cap; i++)
+        out[i] = (i == 0) ? 0 : (raw[i] >= t0 ? (int64_t)((double)(raw[i] - t0) * ns_per_tick) : -1);
+    if (count) *count = words;
+    return gc_report(ctx, GC_OK);
+}
+
+extern "C" gc_status gc_ctx_status(gc_ctx *ctx, void *stream) {
+    if (!ctx) return GC_ERR_ARG;
+    GC_HIP(hipSetDevice(ctx->device));
+    return gc_report(ctx, gc_sync_scalars(ctx, (hipStream_t)stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -290,7 +352,7 @@ __global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__rest
     }
 }
 
-extern "C" gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
+gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
                                  int64_t *uncolored, void *stream) {
     gc_status st = gc_check_graph_args(ctx, g);
     if (st) return st;
@@ -403,7 +465,7 @@ gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStre
     return GC_OK;
 }
 
-extern "C" gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors,
+static gc_status gc_count_colors_impl(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors,
                                      int32_t *max_color, void *stream) {
     if (!ctx) return GC_ERR_ARG;
     if (n < 0 || n > ctx->max_n) return gc_fail(ctx, GC_ERR_ARG, "n out of range");
@@ -502,7 +564,7 @@ __global__ void k_check_entries(const int32_t *__restrict__ rp, const int32_t *_
     if (__lane_id() == 0 && bad) atomicAdd(&scal[S_GRAPHERR], bad);
 }
 
-extern "C" gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream) {
+static gc_status gc_check_csr_impl(gc_ctx *ctx, const gc_csr *g, void *stream) {
     gc_status st = gc_check_graph_args(ctx, g);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -600,7 +662,7 @@ extern "C" int32_t gc_schedule_perm(int32_t schedule, int32_t base, int32_t x, i
     }
 }
 
-extern "C" gc_status gc_color_preset(gc_ctx *ctx, const gc_csr *g, int32_t preset, uint64_t seed, int32_t *colors,
+static gc_status gc_color_preset_impl(gc_ctx *ctx, const gc_csr *g, int32_t preset, uint64_t seed, int32_t *colors,
                                      gc_stats *st, void *stream) {
     if (!ctx) return GC_ERR_ARG;
     if (preset == GC_PRESET_SPEED) return gc_init_color(ctx, g, GC_FIRST_FIT, 1, seed, 0, 0, colors, st, stream);
@@ -616,4 +678,25 @@ extern "C" gc_status gc_color_preset(gc_ctx *ctx, const gc_csr *g, int32_t prese
         st->k_classes = rs.k_classes;
     }
     return GC_OK;
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_validate(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
+                                 int64_t *uncolored, void *stream) {
+    return gc_report(ctx, gc_validate_impl(ctx, g, colors, conflict_edges, uncolored, stream));
+}
+
+extern "C" gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors,
+                                     int32_t *max_color, void *stream) {
+    return gc_report(ctx, gc_count_colors_impl(ctx, n, colors, num_colors, max_color, stream));
+}
+
+extern "C" gc_status gc_check_csr(gc_ctx *ctx, const gc_csr *g, void *stream) {
+    return gc_report(ctx, gc_check_csr_impl(ctx, g, stream));
+}
+
+extern "C" gc_status gc_color_preset(gc_ctx *ctx, const gc_csr *g, int32_t preset, uint64_t seed, int32_t *colors,
+                                     gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_color_preset_impl(ctx, g, preset, seed, colors, st, stream));
 }

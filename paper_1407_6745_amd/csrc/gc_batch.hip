@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(1024) k_batch_order(int32_t G, const int64_t *
     for (int32_t i = threadIdx.x; i < G; i += blockDim.x) order[i] = (int32_t)(uint32_t)key[i];
 }
 
-extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+static gc_status gc_batch_color_impl(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
                                     int32_t passes, uint64_t base_seed, int32_t max_rounds, int32_t max_vertices_per_graph,
                                     int32_t *colors, gc_graph_stats *per_graph, void *stream) {
     if (!ctx) return GC_ERR_ARG;
@@ -333,8 +333,17 @@ extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t 
         if (ctx->bws) { GC_HIP(hipFree(ctx->bws)); ctx->bws = nullptr; ctx->bws_bytes = 0; }
         if (hipMalloc((void **)&ctx->bws, (size_t)need) != hipSuccess)
             return gc_fail(ctx, GC_ERR_OOM, "batch workspace of %lld bytes", (long long)need);
-        GC_HIP(hipMemsetAsync(ctx->bws, 0, (size_t)need, s));
         ctx->bws_bytes = need;
+        ctx->bws_layout = -1;  // zeroed below
+    }
+    // The global class tables of a slice (used when a graph has >= BK colors)
+    // must be zero on entry; every pass leaves them zero, but only for the
+    // slice layout it ran with: when (V, X) move the layout, the tables would
+    // lie on old worklist data, so the workspace is cleared again.
+    const int64_t layout = ((int64_t)V << 16) | X;  // X <= GC_MAX_X < 2^16
+    if (ctx->bws_layout != layout) {
+        GC_HIP(hipMemsetAsync(ctx->bws, 0, (size_t)ctx->bws_bytes, s));
+        ctx->bws_layout = layout;
     }
     GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
     GC_TIMED(GC_K_BATCH, s, k_batch<<<grid, BT, 0, s>>>(b->num_graphs, b->vtx_off, b->edge_off, b->row_ptr, b->col_idx, select == GC_RANDOM_X,
@@ -342,4 +351,12 @@ extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t 
                                 ctx->scal + S_TICKET, order));
     GC_LAUNCHED();
     return GC_OK;
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_batch_color(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+                                    int32_t passes, uint64_t base_seed, int32_t max_rounds, int32_t max_vertices_per_graph,
+                                    int32_t *colors, gc_graph_stats *per_graph, void *stream) {
+    return gc_report(ctx, gc_batch_color_impl(ctx, b, select, X, perm, passes, base_seed, max_rounds, max_vertices_per_graph, colors, per_graph, stream));
 }

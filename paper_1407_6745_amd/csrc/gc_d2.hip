@@ -449,13 +449,16 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_commit(const int32_t *__restric
 
 // Vertices sharing their positive color with a vertex of N2(v), and vertices
 // with color <= 0.
+// Distance-2 check, phase 1: uncolored vertices, and the vertices that share
+// their color with some vertex of N2(v) (early exit at the first), appended
+// to `bad` for phase 2.
 __global__ void __launch_bounds__(D2_BLOCK) k_d2_validate(const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                                                          const int32_t *__restrict__ C, unsigned long long *conflicts,
-                                                          unsigned long long *uncolored) {
+                                                          const int32_t *__restrict__ C, unsigned long long *nbad,
+                                                          unsigned long long *uncolored, int32_t *__restrict__ bad) {
     const int wpb = D2_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    unsigned long long nc = 0, nu = 0;
+    unsigned long long nu = 0;
     for (int32_t v = blockIdx.x * wpb + wib; v < n; v += gridDim.x * wpb) {
         const int32_t cv = __builtin_amdgcn_readfirstlane(C[v]);
         if (cv <= 0) {
@@ -464,12 +467,93 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_validate(const int32_t *__restr
         }
         int32_t e0, e1;
         row_range(rp, v, nnz, e0, e1);
-        if (d2_visit(rp, col, nnz, n, v, e0, e1, [&](int32_t w) { return C[w] == cv; })) nc++;
+        if (d2_visit(rp, col, nnz, n, v, e0, e1, [&](int32_t w) { return C[w] == cv; }) && __lane_id() == 0)
+            bad[atomicAdd(nbad, 1ull)] = v;
     }
-    if (__lane_id() == 0) {
-        if (nc) atomicAdd(conflicts, nc);
-        if (nu) atomicAdd(uncolored, nu);
+    if (__lane_id() == 0 && nu) atomicAdd(uncolored, nu);
+}
+
+#define D2_SET 2048             // LDS hash-set slots per wavefront
+#define D2_SET_FILL (D2_SET / 2)  // keys one sweep may hold: probes always meet an empty slot
+
+// Distance-2 check, phase 2 (vertices of phase 1 only): for each such v, the
+// number of DISTINCT w > v in N2(v) with C[w] = C[v]; the visit reaches a w
+// once per path, so the partners are deduplicated in an LDS hash set.  A
+// first sweep counts partner visits (with repeats), an upper bound of the
+// distinct partners; the partners are split over that bound / D2_SET_FILL
+// sweeps by a hash of w, each deduplicated on its own.  A sweep whose part
+// would overfill the set (an uneven split) stops inserting, and the vertex
+// starts over with twice the sweeps, so every probe sequence ends.
+__global__ void __launch_bounds__(D2_BLOCK) k_d2_pairs(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       int64_t nnz, int32_t n, const int32_t *__restrict__ C,
+                                                       const int32_t *__restrict__ bad,
+                                                       const unsigned long long *__restrict__ nbad,
+                                                       unsigned long long *pairs) {
+    __shared__ int32_t set_all[(D2_BLOCK / 64) * D2_SET];
+    __shared__ int32_t fill_all[D2_BLOCK / 64];
+    const int wpb = D2_BLOCK / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = __lane_id();
+    int32_t *set = set_all + wib * D2_SET;
+    int32_t *fill = fill_all + wib;
+    const int64_t nb = (int64_t)*nbad;
+    unsigned long long total = 0;
+    for (int64_t i = (int64_t)blockIdx.x * wpb + wib; i < nb; i += (int64_t)gridDim.x * wpb) {
+        const int32_t v = __builtin_amdgcn_readfirstlane(bad[i]);
+        const int32_t cv = __builtin_amdgcn_readfirstlane(C[v]);
+        int32_t e0, e1;
+        row_range(rp, v, nnz, e0, e1);
+        unsigned long long visits = 0;
+        (void)d2_visit(rp, col, nnz, n, v, e0, e1, [&](int32_t w) {
+            if (w > v && C[w] == cv) visits++;
+            return false;
+        });
+        for (int o = 32; o >= 1; o >>= 1) visits += __shfl_xor(visits, o);
+        uint64_t sweeps = (visits + D2_SET_FILL - 1) / D2_SET_FILL;
+        unsigned long long found = 0;
+        for (uint64_t r = 0; r < sweeps; r++) {
+            for (int j = lane; j < D2_SET; j += 64) set[j] = -1;
+            if (lane == 0) *fill = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            bool over = false;
+            (void)d2_visit(rp, col, nnz, n, v, e0, e1, [&](int32_t w) {
+                if (w > v && C[w] == cv) {
+                    const uint32_t h = (uint32_t)w * 0x9E3779B1u;
+                    if (sweeps == 1 || (uint64_t)(h >> 8) % sweeps == r) {
+                        for (uint32_t k = h & (D2_SET - 1);; k = (k + 1) & (D2_SET - 1)) {
+                            const int32_t cur = atomicAdd(&set[k], 0);
+                            if (cur == w) break;
+                            if (cur != -1) continue;
+                            // reserve room first: the set never holds more than D2_SET_FILL keys
+                            if (atomicAdd(fill, 1) >= D2_SET_FILL) {
+                                over = true;
+                                break;
+                            }
+                            const int32_t old = atomicCAS(&set[k], -1, w);
+                            if (old == -1) {
+                                found++;
+                                break;
+                            }
+                            atomicSub(fill, 1);
+                            if (old == w) break;
+                        }
+                    }
+                }
+                return false;
+            });
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (__ballot(over)) {  // uneven split: start this vertex over with twice the sweeps
+                sweeps *= 2;
+                r = (uint64_t)-1;
+                found = 0;
+            }
+        }
+        total += found;
     }
+    for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o);
+    if (lane == 0 && total) atomicAdd(pairs, total);
 }
 
 // workgroups for `items` vertices at `per_vertex` lanes each
@@ -611,7 +695,7 @@ gc_status gc_d2_classes(gc_ctx *ctx, const gc_csr *g, int32_t *C, int32_t k, con
     return GC_OK;
 }
 
-extern "C" gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_vertices,
+gc_status gc_validate_d2_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_pairs,
                                     int64_t *uncolored, void *stream) {
     gc_status status = gc_check_graph_args(ctx, g);
     if (status) return status;
@@ -625,16 +709,37 @@ extern "C" gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t 
         if (status) return status;
         if (maxdeg >= GC_D2_MAX_DEGREE)
             return gc_fail(ctx, GC_ERR_ARG, "distance-2 validation takes rows below %d entries", GC_D2_MAX_DEGREE);
+        // S_CONFLICTS: vertices with a conflict (phase 1), S_UNCOLORED, S_DONE: pairs (phase 2)
+        static_assert(S_UNCOLORED == S_CONFLICTS + 1, "adjacent validation slots");
         GC_HIP(hipMemsetAsync(ctx->scal + S_CONFLICTS, 0, 2 * 8, s));
-        k_d2_validate<<<d2_grid(ctx, g->n), D2_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors,
-                                                              ctx->scal + S_CONFLICTS, ctx->scal + S_UNCOLORED);
+        GC_HIP(hipMemsetAsync(ctx->scal + S_DONE, 0, 8, s));
+        int32_t *bad = ctx->wl[0];  // free outside the initial coloring's rounds
+        GC_TIMED(GC_K_OTHER, s, k_d2_validate<<<d2_grid(ctx, g->n), D2_BLOCK, 0, s>>>(
+                                    g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->scal + S_CONFLICTS,
+                                    ctx->scal + S_UNCOLORED, bad));
         GC_LAUNCHED();
         status = gc_sync_scalars(ctx, s);
         if (status) return status;
-        nc = (int64_t)ctx->hscal[S_CONFLICTS];
+        const int64_t nbad = (int64_t)ctx->hscal[S_CONFLICTS];
         nu = (int64_t)ctx->hscal[S_UNCOLORED];
+        if (nbad > 0) {
+            GC_TIMED(GC_K_OTHER, s, k_d2_pairs<<<d2_grid(ctx, nbad), D2_BLOCK, 0, s>>>(
+                                        g->row_ptr, g->col_idx, g->nnz, g->n, colors, bad, ctx->scal + S_CONFLICTS,
+                                        ctx->scal + S_DONE));
+            GC_LAUNCHED();
+            status = gc_sync_scalars(ctx, s);
+            if (status) return status;
+            nc = (int64_t)ctx->hscal[S_DONE];
+        }
     }
-    if (conflict_vertices) *conflict_vertices = nc;
+    if (conflict_pairs) *conflict_pairs = nc;
     if (uncolored) *uncolored = nu;
     return GC_OK;
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_validate_d2(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_pairs,
+                                    int64_t *uncolored, void *stream) {
+    return gc_report(ctx, gc_validate_d2_impl(ctx, g, colors, conflict_pairs, uncolored, stream));
 }

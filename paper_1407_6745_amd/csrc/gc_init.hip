@@ -875,7 +875,7 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     return status;
 }
 
-extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+static gc_status gc_init_color_impl(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
                                    int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
     gc_status status = gc_check_graph_args(ctx, g);
     if (status) return status;
@@ -904,4 +904,11 @@ extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select,
         return gc_spec_rounds_d2(ctx, g, select, X, seed, max_rounds, flags, colors, st, (hipStream_t)stream);
     }
     return gc_spec_rounds(ctx, g, select, X, seed, max_rounds, flags, colors, st, (hipStream_t)stream, nullptr);
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                                   int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_init_color_impl(ctx, g, select, X, seed, max_rounds, flags, colors, st, stream));
 }

@@ -30,7 +30,8 @@ enum {
     S_WCOUNT1 = 1,   // worklist length, buffer 1
     S_MAXC = 2,      // max color seen
     S_MINC = 3,      // min color seen
-    S_ERR = 4,       // error flags (bit 0: color out of range, bit 1: wait limit)
+    S_ERR = 4,       // error flags of the current pass (bit 0: color out of range, bit 1: wait limit,
+                     // bit 2: not resident); cleared at the start of every pass
     S_CONFLICTS = 5,
     S_UNCOLORED = 6,
     S_K = 7,         // number of non-empty classes
@@ -44,6 +45,8 @@ enum {
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
     S_REC = 26,      // rounds queued ahead (26..33): input size, previous round's degree sum
+    S_STICKY = 34,   // device failures kept until a synchronizing call reports them (bit 1: a walk wait
+                     // gave up, bit 2: walk workgroups not all resident); never cleared by a pass
     S_COUNT = 64
 };
 
@@ -101,6 +104,9 @@ struct gc_ctx {
     int32_t *border;         // batched coloring: graph order (largest first), grown on demand
     int64_t border_cap;
     int64_t bws_bytes;
+    int64_t bws_layout;      // batched coloring: (V << 16 | X) the workspace slices were last laid out for
+    unsigned long long sticky;  // device failures harvested from S_STICKY, not yet reported
+    unsigned long long *trace;  // class-completion trace of the last persistent walk (tuning.trace), on demand
     char err[512];
 };
 
@@ -140,7 +146,22 @@ int gc_grid(const gc_ctx *ctx, int64_t work, int block);
 
 // Launch helpers shared between files (defined in gc_api.hip).
 gc_status gc_count_device(gc_ctx *ctx, int32_t n, const int32_t *colors, hipStream_t s, bool reset_minmax);
+// Copies the device scalars to the host mirror (synchronizes s) and moves
+// any sticky device failure into ctx->sticky.
 gc_status gc_sync_scalars(gc_ctx *ctx, hipStream_t s);
+// Status a public call returns: st itself when it is an error, else
+// GC_ERR_DEVICE (and the record cleared) when a sticky device failure was
+// harvested, else GC_OK.
+gc_status gc_report(gc_ctx *ctx, gc_status st);
+// gc_validate / gc_validate_d2 without the sticky report (used by the input
+// check of the recoloring calls).
+gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
+                           int64_t *uncolored, void *stream);
+gc_status gc_validate_d2_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_pairs,
+                              int64_t *uncolored, void *stream);
+// With the check_input knob: GC_ERR_COLORING unless colors is a proper
+// coloring (distance `dist`) with every color >= 1; synchronizes.
+gc_status gc_check_input_coloring(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, void *stream, int dist);
 // Longest row of g, computed once per graph (keyed by its arrays and sizes;
 // it only picks kernel variants, never results).  Synchronizes the stream on
 // a new graph.

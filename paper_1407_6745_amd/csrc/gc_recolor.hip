@@ -435,6 +435,25 @@ __device__ inline void compact_store(void *S, int32_t v, int32_t color) {
     if (CT == 2) ((uint16_t *)S)[v] = (uint16_t)color;
 }
 
+// Bounded waits of the walk: polls before giving up, and the scalar slots
+// where a wait that gave up is recorded (per pass, and sticky).
+struct WaitCtl {
+    unsigned long long *scal;
+    uint32_t limit;
+    // class-completion trace (NULL = off): [0] walk start, [1] walk end,
+    // [2 + 2s] latest completion of a rank-s vertex, [3 + 2s] of a rank-s split row
+    unsigned long long *trace;
+};
+
+// Trace record of a vertex of rank s that has just published its color.
+__device__ inline void trace_done(const WaitCtl &wc, int32_t s, bool split) {
+    if (wc.trace) {
+        const unsigned long long t = wall_clock64();
+        atomicMax(&wc.trace[2 + 2 * (int64_t)s], t);
+        if (split) atomicMax(&wc.trace[3 + 2 * (int64_t)s], t);
+    }
+}
+
 // Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
 // that are not final yet (or whose plain load saw a stale line) are re-read
 // in one wavefront-uniform slow path: every pending word of every lane is
@@ -442,7 +461,7 @@ __device__ inline void compact_store(void *S, int32_t v, int32_t color) {
 // are final by then; the rest is branch-free.
 template <int U, bool WIDE>
 __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t base, uint64_t &m,
-                              unsigned long long *lw, int gfirst, int gw, int32_t *C, unsigned long long *scal) {
+                              unsigned long long *lw, int gfirst, int gw, int32_t *C, const WaitCtl &wc) {
     bool pend[U];
     bool need = false;
 #pragma unroll
@@ -471,10 +490,13 @@ __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t
                 left |= pend[u];
             }
             if (!__ballot(left)) break;
-            if (it >= SPIN_LIMIT ||
+            if (it >= wc.limit ||
                 ((it & 1023u) == 1023u &&
-                 (__hip_atomic_load(&scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))) {
-                if (it >= SPIN_LIMIT) atomicOr(&scal[S_ERR], 2ull);  // gives up: wrong result, but the kernel ends
+                 (__hip_atomic_load(&wc.scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))) {
+                if (it >= wc.limit) {  // gives up: wrong result, but the kernel ends; the error is sticky
+                    atomicOr(&wc.scal[S_ERR], 2ull);
+                    atomicOr(&wc.scal[S_STICKY], 2ull);
+                }
 #pragma unroll
                 for (int u = 0; u < U; u++)
                     if (pend[u]) xv[u] = 0;
@@ -502,7 +524,7 @@ __device__ inline void gather(const int32_t *w, int32_t *xv, const int32_t *C, i
 template <int U, bool WIDE>
 __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t *__restrict__ col, int32_t n,
                                   int32_t s, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw,
-                                  int32_t *C, unsigned long long *scal) {
+                                  int32_t *C, const WaitCtl &wc) {
     for (int32_t eb = e; __ballot(eb < e1); eb += U * gsz) {
         int32_t ww[U], xx[U];
 #pragma unroll
@@ -513,7 +535,7 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
             ww[u] = ok ? wl : -1;
         }
         gather<U>(ww, xx, C, n);
-        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, scal);
+        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, wc);
     }
 }
 
@@ -526,7 +548,7 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
 template <int U, bool WIDE, int CT>
 __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const int32_t *x, int gsz,
                                   const int32_t *__restrict__ col, int32_t n, int32_t *C, void *S,
-                                  unsigned long long *lw, unsigned long long *scal) {
+                                  unsigned long long *lw, const WaitCtl &wc) {
     const int32_t s = t.seg / NSEG_PER_RANK;
     const int lane = __lane_id();
     const int l = lane & (gsz - 1);
@@ -540,8 +562,8 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
     int32_t xv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = x[u];
-    absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, scal);
-    scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, scal);
+    absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, wc);
+    scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, wc);
     m = group_or_rt(m, gsz);
     uint32_t r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
     uint32_t base = 0;
@@ -564,13 +586,14 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
     while (r == 0) {
         base += 64u;
         m = 0;
-        scan_range<U, false>(t.e0 + l, t.e1, gsz, col, n, s, base, m, lw, gfirst, 0, C, scal);
+        scan_range<U, false>(t.e0 + l, t.e1, gsz, col, n, s, base, m, lw, gfirst, 0, C, wc);
         m = group_or_rt(m, gsz);
         r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
     }
     if (t.v >= 0 && l == 0) {
         __hip_atomic_store(&C[t.v], (int32_t)(base + r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         compact_store<CT>(S, t.v, (int32_t)(base + r));
+        trace_done(wc, s, false);
     }
 }
 
@@ -583,7 +606,7 @@ template <int U, int CT>
 __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const int32_t *x,
                                     const int32_t *__restrict__ col, int32_t n,
                                     int32_t *C, void *S, unsigned long long *lw, unsigned long long *hub_bits,
-                                    int32_t *hub_cnt, unsigned long long *scal) {
+                                    int32_t *hub_cnt, const WaitCtl &wc) {
     const int32_t s = t.seg / NSEG_PER_RANK;
     const int lane = __lane_id();
     const int32_t words = (s >> 6) + 1;  // lower ranks hold colors 1..s: words 0 .. s / 64
@@ -595,8 +618,8 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
     int32_t xv[U];
     #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = x[u];
-    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
-    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, scal);
+    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc);
+    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc);
     m = group_or_rt(m, 64);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -624,6 +647,7 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
             atomicExch(&hub_cnt[t.slot], 0);
             __hip_atomic_store(&C[t.v], (int32_t)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             compact_store<CT>(S, t.v, (int32_t)r);
+            trace_done(wc, s, true);
         }
     }
 }
@@ -636,7 +660,7 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
                                           const int32_t *__restrict__ hsub, const int32_t *__restrict__ sbase,
                                           int32_t split_len, unsigned long long *hub_bits, int32_t *hub_cnt,
-                                          unsigned long long *scal, int32_t xcd, unsigned long long *lw, void *S) {
+                                          WaitCtl wc, int32_t xcd, unsigned long long *lw, void *S) {
     constexpr int U = 32 / G > 4 ? 32 / G : 4;
     const int lane = __lane_id();
     const int wpb = WALK_BLOCK / 64;
@@ -732,10 +756,10 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     auto finish = [&](const WalkChunk &t, const int32_t *w, const int32_t *x) {
         const int b = t.seg % NSEG_PER_RANK;
         const int32_t s = t.seg / NSEG_PER_RANK;
-        if (!FULL) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
-        else if (b == 2) finish_split<U, CT>(t, w, x, col, n, C, S, lw, hub_bits, hub_cnt, scal);
-        else if (s < 64) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
-        else finish_row<U, true, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, scal);
+        if (!FULL) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        else if (b == 2) finish_split<U, CT>(t, w, x, col, n, C, S, lw, hub_bits, hub_cnt, wc);
+        else if (s < 64) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        else finish_row<U, true, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
     };
 
     // Software pipeline, one stage per iteration: chunk i+3's vertex and row
@@ -792,7 +816,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
                                                           const int32_t *__restrict__ sbase, int32_t split_len,
                                                           unsigned long long *hub_bits, int32_t *hub_cnt,
                                                           unsigned long long *scal, int32_t xcd, int32_t check_resident,
-                                                          void *S) {
+                                                          uint32_t spin_limit, unsigned long long *trace, void *S) {
     __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
     __shared__ unsigned long long lmask[WALK_BLOCK];  // per wavefront: 64 mask words for colors above 64
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
@@ -800,12 +824,16 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
         // start barrier, bounded: every workgroup checks in and waits for all
         // others; a timeout means they were not all resident (error bit 4).
         // check_resident == 2: residency probe only (short limit, no work).
-        const uint32_t limit = check_resident == 2 ? (1u << 14) : SPIN_LIMIT;
+        const uint32_t limit = check_resident == 2 ? (1u << 14) : spin_limit;
         if (threadIdx.x == 0) {
             atomicAdd(&scal[S_TICKET], 1ull);
             uint32_t it = 0;
             while (__hip_atomic_load(&scal[S_TICKET], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
-                if (++it > limit) { atomicOr(&scal[S_ERR], 4ull); break; }
+                if (++it > limit) {
+                    atomicOr(&scal[S_ERR], 4ull);
+                    if (check_resident == 1) atomicOr(&scal[S_STICKY], 4ull);  // the probe's failures are expected
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(2);
             }
         }
@@ -814,6 +842,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
     }
     const int32_t k = (int32_t)scal[S_K];
     const int32_t nseg = NSEG_PER_RANK * k;
+    const WaitCtl wc = {scal, spin_limit, trace};
+    if (trace && threadIdx.x == 0) atomicMin(&trace[0], wall_clock64());
     if (nseg <= WALK_TAB) {
         // segment tables in LDS: their reads are tracked apart from the vector
         // loads in flight, so looking up the next chunk never drains the pipeline
@@ -821,14 +851,15 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
         __syncthreads();
         if (k <= CT_MAX_K1)
             walk_body<G, true, FULL, 1>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
-                                        hub_cnt, scal, xcd, lw, S);
+                                        hub_cnt, wc, xcd, lw, S);
         else
             walk_body<G, true, FULL, 2>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
-                                        hub_cnt, scal, xcd, lw, S);
+                                        hub_cnt, wc, xcd, lw, S);
     } else {
         walk_body<G, false, FULL, 0>(off, coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt,
-                                     scal, xcd, lw, S);
+                                     wc, xcd, lw, S);
     }
+    if (trace && __lane_id() == 0) atomicMax(&trace[1], wall_clock64());
 }
 
 // One launch per class (host loop): every vertex of rank s, one lane each.
@@ -846,7 +877,7 @@ __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__re
 
 typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const int32_t *, const int32_t *,
                         const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
-                        unsigned long long *, int32_t, int32_t, void *);
+                        unsigned long long *, int32_t, int32_t, uint32_t, unsigned long long *, void *);
 
 template <bool FULL>
 static walk_fn walk_kernel_t(int G) {
@@ -886,6 +917,7 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     int32_t *hub_cnt = ctx->hub_cnt ? ctx->hub_cnt : (int32_t *)ctx->scal;
     unsigned long long *hub_bits = ctx->hub_bits ? ctx->hub_bits : ctx->scal;
     const int32_t split_len = ctx->tune.split_len;
+    const uint32_t spin_limit = ctx->tune.spin_limit > 0 ? (uint32_t)ctx->tune.spin_limit : SPIN_LIMIT;
     if (ctx->walk_blocks_v[variant] == 0) {
         // The occupancy query is an upper bound; the walk needs every workgroup
         // resident at once, so measure it: a probe launch (no work) where every
@@ -902,7 +934,7 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
             GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
             hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C, ctx->list, ctx->off,
                                ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2,
-                               ctx->shadow);
+                               spin_limit, nullptr, ctx->shadow);
             GC_LAUNCHED();
             gc_status st = gc_sync_scalars(ctx, s);
             if (st) return st;
@@ -921,10 +953,22 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     // hanging).
     const int32_t xcd = ctx->tune.xcd_chunks > 0 ? 1 : 0;
     if (ctx->tune.check_resident) GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
+    unsigned long long *trace = nullptr;
+    if (ctx->tune.trace) {
+        const size_t words = 2 + 2 * ((size_t)ctx->ccap + 2);
+        if (!ctx->trace) {
+            GC_HIP(hipStreamSynchronize(s));
+            if (hipMalloc((void **)&ctx->trace, words * 8) != hipSuccess)
+                return gc_fail(ctx, GC_ERR_OOM, "walk trace of %zu words", words);
+        }
+        GC_HIP(hipMemsetAsync(ctx->trace, 0, words * 8, s));
+        GC_HIP(hipMemsetAsync(ctx->trace, 0xFF, 8, s));  // walk start: a minimum
+        trace = ctx->trace;
+    }
     GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C,
                                               ctx->list, ctx->off, ctx->coff, ctx->hsub, ctx->sbase, split_len,
                                               hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident,
-                                              ctx->shadow));
+                                              spin_limit, trace, ctx->shadow));
     GC_LAUNCHED();
     return GC_OK;
 }
@@ -945,6 +989,8 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
         if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
         return GC_OK;
     }
+    status = gc_check_input_coloring(ctx, g, colors_in, stream, dist);
+    if (status) return status;
     if (dist == 2) {
         int32_t maxdeg = 0;
         status = gc_graph_max_degree(ctx, g, s, &maxdeg);
@@ -1039,9 +1085,9 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
         status = gc_sync_scalars(ctx, s);
         if (status) return status;
         if (ctx->hscal[S_ERR] & 1) return gc_fail(ctx, GC_ERR_COLORING, "input color outside [1, %d]", ctx->ccap);
-        if (ctx->hscal[S_ERR] & 4)
-            return gc_fail(ctx, GC_ERR_DEVICE, "class walk: workgroups were not all resident (grid %d)", ctx->walk_blocks);
-        if (ctx->hscal[S_ERR] & 2) return gc_fail(ctx, GC_ERR_DEVICE, "class walk: a dependency wait ran out");
+        // a walk failure of this pass (S_ERR bits 1, 2) is also in the sticky
+        // record harvested by the synchronization above: the public entry
+        // point reports it
         st->rounds = 0;
         st->losers_total = 0;
         st->k_classes = (int32_t)ctx->hscal[S_K];
@@ -1051,12 +1097,12 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
     return GC_OK;
 }
 
-extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+static gc_status gc_recolor_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                                 const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
     return recolor_pass(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream, 1);
 }
 
-extern "C" gc_status gc_recolor_d2(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+static gc_status gc_recolor_d2_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                                    const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
     return recolor_pass(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream, 2);
 }
@@ -1076,7 +1122,7 @@ __global__ void k_vertex_rank(int32_t n, const int32_t *__restrict__ C, const in
     }
 }
 
-extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+static gc_status gc_arc_recolor_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                                     const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
     gc_status status = gc_check_graph_args(ctx, g);
     if (status) return status;
@@ -1090,6 +1136,8 @@ extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, 
         if (st) { st->rounds = 0; st->num_colors = 0; st->max_color = 0; st->k_classes = 0; st->losers_total = 0; }
         return GC_OK;
     }
+    status = gc_check_input_coloring(ctx, g, colors_in, stream, 1);
+    if (status) return status;
     const int block = 256;
     // class sizes and order (no split bins: only the ranks are used)
     const int hist_grid = hist_grid_for(ctx, n, block);
@@ -1119,4 +1167,21 @@ extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, 
     if (status) return status;
     if (st) st->k_classes = k;
     return GC_OK;
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_recolor_impl(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream));
+}
+
+extern "C" gc_status gc_recolor_d2(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                   const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_recolor_d2_impl(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream));
+}
+
+extern "C" gc_status gc_arc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
+                                    const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_arc_recolor_impl(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream));
 }

@@ -65,7 +65,7 @@ static gc_status try_tuning(gc_ctx *ctx, const gc_tuning &t, hipStream_t s, Time
     return checksum2(ctx, a, na, b, nb, s, sum);
 }
 
-extern "C" gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, int32_t perm, int32_t passes,
+static gc_status gc_autotune_impl(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, int32_t perm, int32_t passes,
                                  uint64_t seed, int32_t *colors, gc_tuning *best, double *best_ms, void *stream) {
     gc_status status = gc_check_graph_args(ctx, g);
     if (status) return status;
@@ -134,7 +134,7 @@ extern "C" gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, i
     return GC_OK;
 }
 
-extern "C" gc_status gc_autotune_batch(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+static gc_status gc_autotune_batch_impl(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
                                        int32_t passes, uint64_t base_seed, int32_t max_rounds,
                                        int32_t max_vertices_per_graph, int32_t *colors, gc_graph_stats *per_graph,
                                        gc_tuning *best, double *best_ms, void *stream) {
@@ -185,4 +185,18 @@ extern "C" gc_status gc_autotune_batch(gc_ctx *ctx, const gc_batch_csr *b, int32
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
     return GC_OK;
+}
+
+// Public entry points: the implementations above, with any sticky device
+// failure harvested on the way reported in the returned status.
+extern "C" gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, int32_t perm, int32_t passes,
+                                 uint64_t seed, int32_t *colors, gc_tuning *best, double *best_ms, void *stream) {
+    return gc_report(ctx, gc_autotune_impl(ctx, g, select, X, perm, passes, seed, colors, best, best_ms, stream));
+}
+
+extern "C" gc_status gc_autotune_batch(gc_ctx *ctx, const gc_batch_csr *b, int32_t select, int32_t X, int32_t perm,
+                                       int32_t passes, uint64_t base_seed, int32_t max_rounds,
+                                       int32_t max_vertices_per_graph, int32_t *colors, gc_graph_stats *per_graph,
+                                       gc_tuning *best, double *best_ms, void *stream) {
+    return gc_report(ctx, gc_autotune_batch_impl(ctx, b, select, X, perm, passes, base_seed, max_rounds, max_vertices_per_graph, colors, per_graph, best, best_ms, stream));
 }

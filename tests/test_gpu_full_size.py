@@ -7,6 +7,7 @@ of the random-geometric-graph batch."""
 import hashlib
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -108,3 +109,92 @@ def test_batch_prefix_vs_plain_and_oracle(gc):
             assert gen.checksum(sub) == ref["graph_sha256"]
             assert digest(c) == ref["passes_out"][-1]["sha256"], f"graph {gi}: differs from the oracle"
             assert per[gi, 0] == ref["init"]["rounds"]
+
+
+@pytest.mark.parametrize("name", sorted(GOLD.get("workloads_d2", {})))
+def test_full_size_workload_d2(gc, name):
+    """The distance-2 benchmark configuration at full size against the
+    oracle's distance-1 routines on the square graph: the coloring after the
+    initial coloring and after every pass, rounds, per-round set sizes and
+    color counts."""
+    ref = GOLD["workloads_d2"][name]
+    print(f"[full-size] {name}: {ref['graph']} distance 2", flush=True)
+    g = eval(ref["graph"])
+    assert gen.checksum(g) == ref["graph_sha256"]
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(d)
+    col = torch.from_numpy(g.col).to(d)
+    sel = gc.FIRST_FIT if ref["select"] == "FIRST_FIT" else gc.RANDOM_X
+    c, st = gc.init_color(rp, col, sel, ref["X"], ref["seed"], flags=gc.FLAG_DISTANCE2, round_cap=8192)
+    ri = ref["init"]
+    assert st["rounds"] == ri["rounds"]
+    assert st["round_sizes"] == ri["round_sizes"]
+    assert (st["num_colors"], st["max_color"]) == (ri["num_colors"], ri["max_color"])
+    assert digest(c) == ri["sha256"], "distance-2 initial coloring differs from the oracle"
+    for p, rp_ in enumerate(ref["passes_out"]):
+        c, sp = gc.recolor_d2(rp, col, c, PERM[ref["perm"]], ref["seed"], p, out=c)
+        assert sp["k_classes"] == rp_["k"] and sp["num_colors"] == rp_["num_colors"], p
+        assert digest(c) == rp_["sha256"], f"distance-2 pass {p} differs from the oracle"
+    assert gc.validate_d2(rp, col, c) == (0, 0)
+
+
+def _plain_batch(gc, b, rp, col, X, perm, passes, seed, ctx):
+    """Every graph of the batch through the single-graph calls (no stats: one
+    launch sequence per graph on the same stream), into one packed array."""
+    d = torch.device("cuda:0")
+    out = torch.zeros(int(b.vtx_off[-1]), dtype=torch.int32, device=d)
+    for gi in range(b.num_graphs):
+        a, z = int(b.vtx_off[gi]), int(b.vtx_off[gi + 1])
+        e0, e1 = int(b.edge_off[gi]), int(b.edge_off[gi + 1])
+        grp, gcol, o = rp[a + gi:z + gi + 1], col[e0:e1], out[a:z]
+        sg = gc.batch_graph_seed(seed, gi)
+        gc.init_color(grp, gcol, gc.RANDOM_X, X, sg, out=o, stats=False, ctx=ctx)
+        for p in range(passes):
+            gc.recolor(grp, gcol, o, perm, sg, p, out=o, stats=False, ctx=ctx)
+    ctx.raise_status()
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_full_batch_4096(gc):
+    """The whole 4,096-graph batch (packed col_idx of 2.46e9 entries, past
+    2^31) in one launch, under the default and the tuned launch settings
+    (largest-first order, 2 workgroups per CU): batched == plain per-graph
+    calls for every graph, == the oracle's digests and statistics on the
+    sampled graphs, every graph converged."""
+    B = GOLD["batch"]
+    t0 = time.time()
+    b = gen.rgg_batch(B["G"], B["seed"])
+    assert int(b.edge_off[-1]) > 2**31, "the batch must cross 2^31 packed entries"
+    print(f"[full-batch] generated n={int(b.vtx_off[-1])} nnz={int(b.edge_off[-1])} ({time.time() - t0:.1f}s)",
+          flush=True)
+    d = torch.device("cuda:0")
+    vo = torch.from_numpy(b.vtx_off).to(d)
+    eo = torch.from_numpy(b.edge_off).to(d)
+    rp = torch.from_numpy(b.row_ptr).to(d)
+    col = torch.from_numpy(b.col).to(d)
+    ns = np.diff(b.vtx_off)
+    max_n, max_nnz = int(ns.max()), int(np.diff(b.edge_off).max())
+    ctx = gc.Context(max_n, max_nnz)
+    perm = PERM[B["perm"]]
+    plain = _plain_batch(gc, b, rp, col, B["X"], perm, B["passes"], B["seed"], ctx)
+    print(f"[full-batch] plain calls done ({time.time() - t0:.1f}s)", flush=True)
+    for tune in ({}, {"batch_order": 1, "batch_wg_per_cu": 2}):
+        if tune:
+            ctx.set_tuning(**tune)
+        colors, per = gc.batch_color(vo, eo, rp, col, gc.RANDOM_X, B["X"], perm, B["passes"], B["seed"],
+                                     max_vertices_per_graph=max_n, ctx=ctx)
+        ctx.raise_status()
+        per = per.cpu().numpy()
+        print(f"[full-batch] batched {tune or 'default'} ({time.time() - t0:.1f}s)", flush=True)
+        assert (per[:, 3] == 0).all(), "every graph converges"
+        assert torch.equal(colors, plain), f"{tune}: batched != plain"
+        for gi, ref in B["graphs"].items():
+            gi = int(gi)
+            a, z = int(b.vtx_off[gi]), int(b.vtx_off[gi + 1])
+            assert gen.checksum(b.graph(gi)) == ref["graph_sha256"]
+            assert digest(colors[a:z]) == ref["passes_out"][-1]["sha256"], f"graph {gi}: differs from the oracle"
+            assert per[gi, 0] == ref["init"]["rounds"] and per[gi, 1] == ref["init"]["num_colors"], gi
+            assert per[gi, 2] == ref["passes_out"][-1]["num_colors"], gi
+        del colors
+    ctx.close()
