@@ -347,6 +347,24 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, i
 gc_status gc_count_colors(gc_ctx *ctx, int32_t n, const int32_t *colors, int32_t *num_colors, int32_t *max_color,
                           void *stream);
 
+/*
+ * gc_count_colors for callers that cannot allocate device memory (harnesses
+ * that forbid hipMalloc, tight serving loops): same results, no context, and
+ * no allocation of any kind.  The kernels work in one static device array of
+ * the library (about 128 KiB per GPU, held until the process ends) that
+ * every call on that GPU shares: calls that overlap on one GPU (from several
+ * host threads or streams at once) race and give wrong counts.  Runs on the
+ * calling thread's current HIP device; `stream` must belong to it.  Colors
+ * are counted up to GC_STATIC_MAX_COLOR: a larger color gives GC_ERR_ARG.
+ * Host outputs (either may be NULL); synchronizes the stream, so it cannot
+ * be captured into a HIP graph.  Errors: GC_ERR_ARG for n < 0, colors NULL
+ * with n > 0, or a color above GC_STATIC_MAX_COLOR; GC_ERR_DEVICE if a HIP
+ * call fails.
+ */
+#define GC_STATIC_MAX_COLOR (1 << 20)
+gc_status gc_count_colors_static(int32_t n, const int32_t *colors, int32_t *num_colors, int32_t *max_color,
+                                 void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched coloring: many independent graphs in one persistent launch.
  *

@@ -93,6 +93,8 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "gc_count_colors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "gc_count_colors_static": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "gc_batch_color": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchArgs), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -448,6 +450,22 @@ def count_colors(colors, ctx: Context | None = None, stream=None):
     rc = lib().gc_count_colors(ctx.handle, n, colors.data_ptr() if n else None, ctypes.byref(num), ctypes.byref(mx),
                                _stream_ptr(stream))
     ctx.check(rc, "gc_count_colors")
+    return num.value, mx.value
+
+
+STATIC_MAX_COLOR = 1 << 20
+
+
+def count_colors_static(colors, stream=None):
+    """(distinct positive colors, max color) through the allocation-free
+    gc_count_colors_static (no context; colors up to STATIC_MAX_COLOR)."""
+    _check_i32_dev(colors, "colors")
+    n = colors.numel()
+    num, mx = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().gc_count_colors_static(n, colors.data_ptr() if n else None, ctypes.byref(num), ctypes.byref(mx),
+                                      _stream_ptr(stream))
+    if rc:
+        raise GCError(rc, f"gc_count_colors_static: {status_string(rc)}")
     return num.value, mx.value
 
 

@@ -2,6 +2,7 @@
 // counting entry points of the C ABI (validate, count colors, CSR check).
 #include "gc_internal.h"
 
+#include <mutex>
 #include <vector>
 
 #include <stdlib.h>
@@ -495,6 +496,72 @@ static gc_status gc_count_colors_impl(gc_ctx *ctx, int32_t n, const int32_t *col
     }
     if (num_colors) *num_colors = (int32_t)ctx->hscal[S_NUMC];
     if (max_color) *max_color = (int32_t)ctx->hscal[S_MAXC];
+    return GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// gc_count_colors_static: gc_count_colors without a context and without any
+// allocation.  Its kernels (the ones above) work in one file-scope device
+// array: 64 scalar slots, then the distinct-color bitmap for colors
+// 1 .. GC_STATIC_MAX_COLOR.  Each device holds its own copy at its own
+// address, looked up once per device with hipGetSymbolAddress; host code
+// uses only that address.
+// ---------------------------------------------------------------------------
+
+#define STATIC_SLOTS 64
+static __device__ __align__(256) unsigned long long scratch[STATIC_SLOTS + GC_STATIC_MAX_COLOR / 64];
+
+#define STATIC_MAX_DEVICES 64
+static unsigned long long *g_scratch[STATIC_MAX_DEVICES];  // device address of `scratch`, per device
+static std::mutex g_scratch_mu;
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t words, unsigned long long value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = value;
+}
+
+extern "C" gc_status gc_count_colors_static(int32_t n, const int32_t *colors, int32_t *num_colors, int32_t *max_color,
+                                            void *stream) {
+    if (n < 0) return GC_ERR_ARG;
+    if (n > 0 && !colors) return GC_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return GC_ERR_DEVICE;
+    unsigned long long *ptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[dev]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GC_ERR_DEVICE;
+            g_scratch[dev] = (unsigned long long *)p;
+        }
+        ptr = g_scratch[dev];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *bitmap = (uint32_t *)(ptr + STATIC_SLOTS);
+    const int64_t bits = GC_STATIC_MAX_COLOR;
+    // start from a clear array whatever an earlier call left (fill kernels, no memset nodes)
+    k_fill_u64<<<64, 256, 0, s>>>(ptr, STATIC_SLOTS + GC_STATIC_MAX_COLOR / 64, 0ull);
+    k_init_minmax<<<1, 64, 0, s>>>(ptr);
+    if (n > 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
+        const int block = 256;
+        const int64_t want = ((int64_t)n + block - 1) / block;
+        const int grid = (int)(want < 2 * ncu ? want : 2 * ncu);
+        k_minmax<<<grid, block, 0, s>>>(n, colors, ptr);
+        k_bitmap<<<grid, block, 0, s>>>(n, colors, bitmap, bits);
+        k_popcount_clear<<<(int)((bits / 32 + block - 1) / block), block, 0, s>>>(bitmap, bits, ptr);
+    }
+    if (hipGetLastError() != hipSuccess) return GC_ERR_DEVICE;
+    static_assert(S_MAXC < 16 && S_NUMC < 16, "the slots read back");
+    unsigned long long hs[16];  // host stack copy of the first scalar slots
+    if (hipMemcpyAsync(hs, ptr, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GC_ERR_DEVICE;
+    const int32_t maxc = (int32_t)hs[S_MAXC];
+    if (maxc > GC_STATIC_MAX_COLOR) return GC_ERR_ARG;  // above the static bitmap
+    if (num_colors) *num_colors = (int32_t)hs[S_NUMC];
+    if (max_color) *max_color = maxc;
     return GC_OK;
 }
 
