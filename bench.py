@@ -728,6 +728,36 @@ def run_graph(args, workload):
     kt_cold = ctx.timing()
     ctx.set_timing(False)
     del scrub
+    # the validation kernel (section 1's condition) on the step's colors, timed alone
+    ev_v = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    vt = []
+    for _ in range(3):
+        ev_v[0].record(stream)
+        gc.validate(rp, col, c_step, ctx=ctx)
+        ev_v[1].record(stream)
+        torch.cuda.synchronize()
+        vt.append(ev_v[0].elapsed_time(ev_v[1]))
+    validate_ms = min(vt)
+    validate_bytes = 8 * g.nnz + 8 * g.n + 4  # col_idx + neighbor colors + row_ptr + own color
+    # one traced pass (outside the timed region): when each class finished
+    ctx.set_tuning(trace=1)
+    colors = c_step.clone()
+    recolor_fn(rp, col, colors, perms[0], args.seed, 0, out=colors, stats=False, ctx=ctx)
+    walk_trace = None
+    if args.method == "rc":
+        tr = ctx.walk_trace()
+        done = np.asarray(tr["class_done"], np.float64) / 1e3
+        split = np.asarray(tr["split_done"], np.float64) / 1e3
+        gaps = np.diff(np.concatenate([[0.0], np.maximum.accumulate(done)]))
+        walk_trace = {"classes": int(done.size), "walk_us": round(tr["end"] / 1e3, 2),
+                      "last_class_done_us": round(float(done.max()), 2) if done.size else 0.0,
+                      "class_gap_us": {"median": round(float(np.median(gaps)), 3) if done.size else 0.0,
+                                       "p90": round(float(np.percentile(gaps, 90)), 3) if done.size else 0.0,
+                                       "max": round(float(gaps.max()), 3) if done.size else 0.0},
+                      "classes_with_split_rows": int((split > 0).sum()),
+                      "split_row_finishes_class": int(((split > 0) & (split >= done)).sum()),
+                      "class_done_us": [round(float(x), 2) for x in done[:512]]}
+    ctx.set_tuning(trace=0)
     ms_step = el / args.steps * 1e3
     m = g.nnz // 2
     value = m * (passes + 1) / (ms_step / 1e3) / 1e9
@@ -765,6 +795,10 @@ def run_graph(args, workload):
             "walk_gbs": round(walk_bytes / (kt_cold["walk"][1] / max(kt_cold["walk"][0], 1) / 1e3) / 1e9, 1)
             if kt_cold["walk"][0] else None},
         "kernel_ms_one_step": {k: {"launches": v[0], "total_ms": round(v[1], 4)} for k, v in kt.items() if v[0]},
+        "walk_trace_one_pass": walk_trace,
+        "validate": {"ms": round(validate_ms, 4), "algorithmic_bytes": validate_bytes,
+                     "frac_of_peak": round(validate_bytes / (validate_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "note": "gc_validate call incl. its two scalar resets and read-back, events on the stream"},
         "roofline": roofline,
     }
     # the initial coloring against its algorithmic bytes (16 per scanned entry

@@ -117,7 +117,9 @@ typedef struct gc_tuning {
     int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
     int32_t walk_mode;     /* recoloring class walk: 0 = one persistent launch, waits per dependency;
                               1 = one launch per class (host reads the class count) */
-    int32_t xcd_chunks;    /* persistent walk: consecutive work chunks kept on one XCD (0 = round robin) */
+    int32_t xcd_chunks;    /* persistent walk: 1 (default) = every class's chunks cut into 8 consecutive parts,
+                              part x taken by the workgroups the hardware places on XCD x, so a region of the
+                              vertex order stays in one XCD's L2 across classes; 0 = round robin */
     int32_t check_resident;/* persistent walk: verify at start that every workgroup is resident (diagnostic;
                               a failed check makes the call return GC_ERR_DEVICE when it synchronizes) */
     int32_t deg_split;     /* rows longer than both deg_wave and deg_split (0 = never) are scanned by
@@ -145,7 +147,19 @@ typedef struct gc_tuning {
                               a proper coloring (distance 2 for gc_recolor_d2) with every color >= 1, and
                               return GC_ERR_COLORING otherwise (one validation sweep; synchronizes) */
     int32_t trace;         /* 1 = the persistent walk records when each class finishes (profiling aid, see
-                              gc_ctx_get_trace; one device atomic per vertex) */
+                              gc_ctx_get_trace; device atomics per wavefront and class) */
+    int32_t tail_max;      /* initial coloring: once a round has at most tail_max vertices (0 = 16384) and no
+                              row needs the split kernels, the remaining rounds run in one persistent launch
+                              with grid barriers (no host read-back per round); -1 = never */
+    int32_t walk_flags;    /* persistent walk, bit mask: 1 = inside a class, split rows are taken first, then
+                              wavefront rows, then group rows; 2 = a split-row sub-chunk still waiting when all
+                              the row's other sub-chunks are done takes their mask words and publishes the color
+                              itself */
+    int32_t cu_count;      /* compute units the context's streams may use (0 = all of the device): sizes the
+                              grids, and the persistent launches measure their co-resident grid on it; for
+                              streams created with a compute-unit mask (as the request server does) */
+    int32_t compact_init;  /* initial coloring: 1 (default) = neighbor colors are read from a one-byte copy when
+                              no color can exceed 127 (longest row + X <= 127); 0 = always from colors */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);

@@ -19,11 +19,21 @@
  *
  * A request's result does not depend on what else runs: every slot runs the
  * same kernels as the single-graph calls of gc.h with the request's seed.
- * Initial colorings of different slots overlap on the device; a recoloring
- * pass (the persistent class walk, which needs all of its workgroups resident
- * at once) has the device to itself: it waits until the initial colorings in
- * flight have finished, and new ones wait for it.  Each slot's walk is sized
- * on the idle device at creation.
+ *
+ * Device sharing (cu_partition):
+ *   1: every slot's stream is confined to its own disjoint set of compute
+ *      units (a compute-unit mask taking an equal share of every XCD), so the
+ *      initial colorings and the recoloring passes of different requests run
+ *      on the device at the same time without interfering: each slot's
+ *      persistent class walk is sized, at creation, to what its own compute
+ *      units hold, and no other kernel can take them.  Needs at least 8
+ *      compute units per slot; otherwise, or if the runtime refuses the mask,
+ *      the server falls back to 0.
+ *   0: the slots share all compute units.  Initial colorings of different
+ *      slots overlap; a recoloring pass (the persistent walk needs all of its
+ *      workgroups resident at once) has the device to itself: it waits until
+ *      the initial colorings in flight have finished, and new ones wait for
+ *      it.
  *
  * Threads: gc_server_submit, gc_server_poll and gc_server_stats may be
  * called from any host thread.  gc_server_destroy waits for every submitted
@@ -48,6 +58,8 @@ typedef struct gc_server_config {
     int64_t hbm_budget;   /* bytes of the device arena for request graphs and colors */
     int64_t max_n;        /* largest request accepted (vertices, CSR entries); sizes each slot's workspace */
     int64_t max_nnz;
+    int32_t cu_partition; /* 1 = each slot on its own compute units (passes overlap), 0 = shared device */
+    int32_t reserved;
 } gc_server_config;
 
 /* One coloring request.  row_ptr, col_idx (host, the CSR of gc.h) and
@@ -70,7 +82,10 @@ typedef struct gc_request {
 
 /* Completion record.  Times are seconds on the server's steady clock
  * (gc_server_now); device_ms is the request's stream time from the first
- * copy to the colors on the host. */
+ * copy to the colors on the host; pass_start_ms / pass_end_ms bound its
+ * recoloring passes on the device, in ms since a reference event the server
+ * records at creation (comparable across slots: they show which requests'
+ * passes overlapped on the device). */
 typedef struct gc_request_done {
     uint64_t tag;
     int32_t status;       /* gc_status of the request */
@@ -82,12 +97,15 @@ typedef struct gc_request_done {
     int64_t footprint;    /* arena bytes it held */
     double t_submit, t_admit, t_done;
     double device_ms;
+    double pass_start_ms, pass_end_ms;
 } gc_request_done;
 
 typedef struct gc_server_stats {
     int64_t submitted, completed, waiting, running;
     int64_t peak_running;
     int64_t arena_size, arena_used, arena_peak;
+    int64_t cu_partition;  /* the sharing mode in effect (cu_partition of the config, or 0 after a fallback) */
+    int64_t slot_cus;      /* compute units per slot */
 } gc_server_stats;
 
 /* Creates the server: the arena, and per slot a stream, a gc_ctx sized for

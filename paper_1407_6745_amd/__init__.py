@@ -51,11 +51,13 @@ class Tuning(ctypes.Structure):
                 ("check_resident", ctypes.c_int32), ("deg_split", ctypes.c_int32), ("split_len", ctypes.c_int32),
                 ("hub_words", ctypes.c_int32), ("walk_group", ctypes.c_int32),
                 ("d2_star", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32), ("batch_order", ctypes.c_int32),
-                ("spin_limit", ctypes.c_int32), ("check_input", ctypes.c_int32), ("trace", ctypes.c_int32)]
+                ("spin_limit", ctypes.c_int32), ("check_input", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("tail_max", ctypes.c_int32), ("walk_flags", ctypes.c_int32), ("cu_count", ctypes.c_int32),
+                ("compact_init", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
                  "split_len", "hub_words", "walk_group", "d2_star", "batch_wg_per_cu", "batch_order", "spin_limit",
-                 "check_input", "trace")
+                 "check_input", "trace", "tail_max", "walk_flags", "cu_count", "compact_init")
 
 
 class BatchArgs(ctypes.Structure):
@@ -610,7 +612,8 @@ def color(row_ptr, col_idx, select=RANDOM_X, X=4, seed=1, perms=(PERM_REVERSE,),
 
 class ServerConfigArgs(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
-                ("max_n", ctypes.c_int64), ("max_nnz", ctypes.c_int64)]
+                ("max_n", ctypes.c_int64), ("max_nnz", ctypes.c_int64), ("cu_partition", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RequestArgs(ctypes.Structure):
@@ -624,12 +627,13 @@ class RequestDoneArgs(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("rounds", ctypes.c_int32), ("colors_init", ctypes.c_int32), ("colors_final", ctypes.c_int32),
                 ("running_at_admit", ctypes.c_int32), ("footprint", ctypes.c_int64), ("t_submit", ctypes.c_double),
-                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double)]
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("pass_start_ms", ctypes.c_double), ("pass_end_ms", ctypes.c_double)]
 
 
 class ServerStatsArgs(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "waiting", "running", "peak_running",
-                                              "arena_size", "arena_used", "arena_peak")]
+                                              "arena_size", "arena_used", "arena_peak", "cu_partition", "slot_cus")]
 
 
 def request_footprint(n: int, nnz: int) -> int:
@@ -642,8 +646,8 @@ class Server:
     """Continuous-batching request server of libgc (gc_serve.h).  Requests are
     host CSR graphs (numpy int32); results come back as host color arrays."""
 
-    def __init__(self, slots=4, hbm_budget=16 << 30, max_n=1 << 22, max_nnz=1 << 26, device=0):
-        cfg = ServerConfigArgs(device, slots, hbm_budget, max_n, max_nnz)
+    def __init__(self, slots=4, hbm_budget=16 << 30, max_n=1 << 22, max_nnz=1 << 26, device=0, cu_partition=1):
+        cfg = ServerConfigArgs(device, slots, hbm_budget, max_n, max_nnz, cu_partition, 0)
         h = ctypes.c_void_p()
         rc = lib().gc_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc:

@@ -2,6 +2,7 @@
 // counting entry points of the C ABI (validate, count colors, CSR check).
 #include "gc_internal.h"
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -56,7 +57,7 @@ static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
                     c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
-                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy, c->trace};
+                    c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy, c->trace, c->sync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -77,18 +78,21 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.group = 4;
     ctx->tune.grid_per_cu = 8;
     ctx->tune.walk_mode = 0;
-    ctx->tune.xcd_chunks = 0;
+    ctx->tune.xcd_chunks = 1;
     ctx->tune.deg_split = 4096;
     ctx->tune.split_len = 1024;
     ctx->tune.hub_words = GC_HUB_WORDS;
     ctx->tune.walk_group = 0;
     ctx->tune.d2_star = 0;
+    ctx->tune.walk_flags = 0;
+    ctx->tune.compact_init = 1;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     ctx->num_cu = prop.multiProcessorCount;
+    ctx->dev_cu = prop.multiProcessorCount;
     size_t N = (size_t)max_n + 64;
     size_t CC = (size_t)ctx->ccap + 64;
     ctx->bitmap_bits = (int64_t)((CC + 63) / 64 * 64);
@@ -108,6 +112,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         {(void **)&ctx->bitmap, (size_t)ctx->bitmap_bits / 8},
         {(void **)&ctx->round_stats, 2 * N * 8},
         {(void **)&ctx->scal, S_COUNT * 8},
+        {(void **)&ctx->sync, GC_SYNC_BYTES},
     };
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) { free_all(ctx); free(ctx); return GC_ERR_OOM; }
@@ -252,6 +257,16 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->spin_limit < 0) return gc_fail(ctx, GC_ERR_ARG, "spin_limit must be >= 0");
     if (t->check_input < 0 || t->check_input > 1) return gc_fail(ctx, GC_ERR_ARG, "check_input must be 0 or 1");
     if (t->trace < 0 || t->trace > 1) return gc_fail(ctx, GC_ERR_ARG, "trace must be 0 or 1");
+    if (t->tail_max < -1) return gc_fail(ctx, GC_ERR_ARG, "tail_max must be >= -1");
+    if (t->walk_flags < 0 || t->walk_flags > 3) return gc_fail(ctx, GC_ERR_ARG, "walk_flags must be in [0, 3]");
+    if (t->cu_count < 0) return gc_fail(ctx, GC_ERR_ARG, "cu_count must be >= 0");
+    if (t->compact_init < 0 || t->compact_init > 1) return gc_fail(ctx, GC_ERR_ARG, "compact_init must be 0 or 1");
+    const int cus = t->cu_count > 0 && t->cu_count < ctx->dev_cu ? t->cu_count : ctx->dev_cu;
+    if (cus != ctx->num_cu) {
+        // launch sizes follow the compute units; the persistent walk's grid is measured again
+        ctx->num_cu = cus;
+        for (int &b : ctx->walk_blocks_v) b = 0;
+    }
     ctx->tune = *t;
     return GC_OK;
 }
@@ -330,18 +345,84 @@ extern "C" gc_status gc_ctx_status(gc_ctx *ctx, void *stream) {
 // validate: conflicting edges and uncolored vertices
 // ---------------------------------------------------------------------------
 
-__global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n,
-                           const int32_t *__restrict__ C, unsigned long long *scal) {
+// Validation by degree: each wavefront takes 64 consecutive vertices and
+// spreads the entries of their rows over its 64 lanes (a lane finds the row
+// of its entry by a binary search over the rows' prefix sums, read across
+// lanes), so short and mid rows keep every lane busy whatever the degree
+// mix.  Rows longer than VAL_LONG entries go, as (row, chunk) pairs of
+// VAL_LONG entries, to a list that k_validate_long scans one wavefront per
+// chunk.  Counts entries (u, w) with u < w and equal positive colors, and
+// vertices with a color <= 0.
+#define VAL_LONG 4096
+#define VAL_U 4
+
+__global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                  int64_t nnz, int32_t n, const int32_t *__restrict__ C,
+                                                  int32_t *__restrict__ long_row, int32_t *__restrict__ long_chunk,
+                                                  int64_t long_cap, unsigned long long *scal) {
+    const int wpb = blockDim.x / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = __lane_id();
     unsigned long long conf = 0, unc = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-        int32_t cu = C[u];
-        if (cu <= 0) { unc++; continue; }
-        int32_t e0, e1;
-        row_range(rp, (int32_t)u, nnz, e0, e1);
-        for (int32_t e = e0; e < e1; e++) {
-            int32_t w = col[e];
-            if ((uint32_t)w < (uint32_t)n && w > u && C[w] == cu) conf++;
+    for (int64_t base = ((int64_t)blockIdx.x * wpb + wib) * 64; base < n; base += (int64_t)gridDim.x * wpb * 64) {
+        const int64_t v = base + lane;
+        const bool valid = v < n;
+        int32_t e0 = 0, e1 = 0, cv = 0;
+        if (valid) {
+            row_range(rp, (int32_t)v, nnz, e0, e1);
+            cv = C[v];
+            if (cv <= 0) unc++;
+        }
+        int32_t len = cv > 0 ? e1 - e0 : 0;  // an uncolored vertex has no conflicting edge
+        if (len > VAL_LONG) {
+            const int32_t nch = (len + VAL_LONG - 1) / VAL_LONG;
+            const int64_t p = (int64_t)atomicAdd(&scal[S_VLONG], (unsigned long long)nch);
+            if (p + nch <= long_cap) {
+                for (int32_t j = 0; j < nch; j++) {
+                    long_row[p + j] = (int32_t)v;
+                    long_chunk[p + j] = j;
+                }
+                len = 0;
+            } else {
+                // list full: the row stays here, scanned by the whole wavefront; the
+                // reserved slots that do exist are marked empty
+                for (int64_t j = p; j < p + nch && j < long_cap; j++) long_row[j] = -1;
+            }
+        }
+        int32_t incl = len;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int32_t excl = incl - len;
+        const int32_t total = __shfl(incl, 63);
+        for (int32_t t0 = 0; t0 < total; t0 += 64 * VAL_U) {
+            int32_t w[VAL_U], c[VAL_U], uu[VAL_U];
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++) {
+                const int32_t t = t0 + 64 * k + lane;
+                int32_t lo = 0, hi = 63;  // last lane whose rows start at or before t
+#pragma unroll
+                for (int step = 0; step < 6; step++) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (__shfl(excl, mid) <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int32_t a = __shfl(e0, lo), x = __shfl(excl, lo);
+                c[k] = __shfl(cv, lo);
+                uu[k] = (int32_t)base + lo;
+                w[k] = t < total ? col[a + (t - x)] : -1;
+            }
+            // each edge is checked from its smaller end only: half the color gathers
+            int32_t cw[VAL_U];
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++) {
+                const bool need = (uint32_t)w[k] < (uint32_t)n && w[k] > uu[k];
+                cw[k] = need ? C[w[k]] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++)
+                if (cw[k] == c[k] && (uint32_t)w[k] < (uint32_t)n && w[k] > uu[k]) conf++;
         }
     }
     __shared__ unsigned long long lds[16];
@@ -353,6 +434,43 @@ __global__ void k_validate(const int32_t *__restrict__ rp, const int32_t *__rest
     }
 }
 
+// The long rows' chunks listed by k_validate: one wavefront per chunk.
+__global__ void __launch_bounds__(256) k_validate_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       int64_t nnz, int32_t n, const int32_t *__restrict__ C,
+                                                       const int32_t *__restrict__ long_row,
+                                                       const int32_t *__restrict__ long_chunk, int64_t long_cap,
+                                                       unsigned long long *scal) {
+    const int wpb = blockDim.x / 64;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = __lane_id();
+    int64_t cnt = (int64_t)scal[S_VLONG];
+    if (cnt > long_cap) cnt = long_cap;  // reservations past the list were scanned by k_validate
+    unsigned long long conf = 0;
+    for (int64_t i = (int64_t)blockIdx.x * wpb + wib; i < cnt; i += (int64_t)gridDim.x * wpb) {
+        const int32_t v = long_row[i];
+        if (v < 0) continue;
+        int32_t e0, e1;
+        row_range(rp, v, nnz, e0, e1);
+        const int32_t a = e0 + long_chunk[i] * VAL_LONG;
+        const int32_t b = min(e1, a + VAL_LONG);
+        const int32_t cv = C[v];
+        for (int32_t e = a + lane; e < b; e += 64 * VAL_U) {
+            int32_t w[VAL_U];
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++) w[k] = e + 64 * k < b ? col[e + 64 * k] : -1;
+            int32_t cw[VAL_U];
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++) cw[k] = ((uint32_t)w[k] < (uint32_t)n && w[k] > v) ? C[w[k]] : 0;
+#pragma unroll
+            for (int k = 0; k < VAL_U; k++)
+                if (cw[k] == cv && (uint32_t)w[k] < (uint32_t)n && w[k] > v) conf++;
+        }
+    }
+    __shared__ unsigned long long lds[16];
+    conf = block_sum_u64(conf, lds);
+    if (threadIdx.x == 0 && conf) atomicAdd(&scal[S_CONFLICTS], conf);
+}
+
 gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, int64_t *conflict_edges,
                                  int64_t *uncolored, void *stream) {
     gc_status st = gc_check_graph_args(ctx, g);
@@ -361,9 +479,19 @@ gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, 
     hipStream_t s = (hipStream_t)stream;
     GC_HIP(hipSetDevice(ctx->device));
     GC_HIP(hipMemsetAsync(ctx->scal + S_CONFLICTS, 0, 2 * 8, s));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_VLONG, 0, 8, s));
     if (g->n > 0) {
-        int block = 256;
-        GC_TIMED(GC_K_OTHER, s, k_validate<<<gc_grid(ctx, g->n, block), block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->scal));
+        const int block = 256;
+        const int64_t waves = ((int64_t)g->n + 63) / 64;
+        const int64_t cap = (int64_t)ctx->num_cu * 16;
+        const int grid = (int)std::min<int64_t>((waves + 3) / 4, cap);
+        // the long-row chunk list lives in two initial-coloring worklists (free here)
+        GC_TIMED(GC_K_OTHER, s, k_validate<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors,
+                                                                   ctx->wl[1], ctx->wl[2], ctx->max_n, ctx->scal));
+        GC_LAUNCHED();
+        GC_TIMED(GC_K_OTHER, s, k_validate_long<<<ctx->num_cu * 4, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
+                                                                                   g->n, colors, ctx->wl[1],
+                                                                                   ctx->wl[2], ctx->max_n, ctx->scal));
         GC_LAUNCHED();
     }
     st = gc_sync_scalars(ctx, s);

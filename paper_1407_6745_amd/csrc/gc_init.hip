@@ -38,9 +38,9 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
-template <int G, bool ROUND0, int UNR = GC_UNROLL>
+template <int G, bool ROUND0, int UNR = GC_UNROLL, typename T = int32_t>
 __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
-                                   const int32_t *C, int32_t n, const Prio &pr, uint32_t s_color, uint32_t X,
+                                   const T *C, int32_t n, const Prio &pr, uint32_t s_color, uint32_t X,
                                    bool randx) {
     const int l = __lane_id() & (G - 1);
     bool lose = false;
@@ -58,7 +58,7 @@ __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t 
             if (ROUND0) {
                 t[u] = ok ? round0_color(s_color, w[u], X, randx) : 0;
             } else {
-                const int32_t cl = C[ok ? w[u] : 0];
+                const int32_t cl = (int32_t)C[ok ? w[u] : 0];
                 t[u] = ok ? abs(cl) : 0;
             }
         }
@@ -67,6 +67,65 @@ __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t 
             if (t[u] == tv && round_prio(pr, w[u]) > pv) lose = true;
     }
     return group_any<G>(lose);
+}
+
+// One wavefront over src[e0, e1): does v (tentative color tv, priority pv)
+// lose to a neighbor, and (out != NULL) which entries are still uncolored.
+// Every batch of UNR x 64 entries issues all its id loads, then all its color
+// loads, and appends its kept entries in order at out[*] with one
+// reservation per batch: *cursor (wavefront-private, len == NULL) or an
+// atomic add on *len (several wavefronts append to one list).  EARLY stops
+// at the first batch that finds a conflict (no kept entries then).
+template <int UNR, bool EARLY, typename T = int32_t>
+__device__ inline bool wave_loses_keep(int32_t tv, uint64_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ src,
+                                       const T *C, int32_t n, const Prio &pr, int32_t *out, int32_t *cursor,
+                                       int32_t *len) {
+    const int lane = __lane_id();
+    bool lose = false;
+    for (int32_t eb = e0; eb < e1; eb += 64 * UNR) {
+        int32_t w[UNR], c[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const int32_t e = eb + u * 64 + lane;
+            const int32_t wl = src[e < e1 ? e : eb];
+            w[u] = e < e1 ? wl : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const bool ok = (uint32_t)w[u] < (uint32_t)n;
+            const int32_t cl = (int32_t)C[ok ? w[u] : 0];
+            c[u] = ok ? cl : INT32_MAX;  // an invalid id: neither a conflict nor kept
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++)
+            if (c[u] != INT32_MAX && abs(c[u]) == tv && round_prio(pr, w[u]) > pv) lose = true;
+        if (out) {
+            unsigned long long bm[UNR];
+            int32_t tot = 0;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                bm[u] = __ballot(c[u] <= 0);
+                tot += (int32_t)__popcll(bm[u]);
+            }
+            if (tot) {
+                int32_t base = 0;
+                if (len) {
+                    if (lane == 0) base = atomicAdd(len, tot);
+                    base = __shfl(base, 0);
+                } else {
+                    base = *cursor;
+                    *cursor += tot;
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; u++) {
+                    if (c[u] <= 0) out[base + __popcll(bm[u] & ((1ull << lane) - 1ull))] = w[u];
+                    base += (int32_t)__popcll(bm[u]);
+                }
+            }
+        }
+        if (EARLY && __ballot(lose)) return true;
+    }
+    return __ballot(lose) != 0ull;
 }
 
 // Committed-color masks of the long rows (more than deg_wave entries): for a
@@ -153,9 +212,17 @@ __device__ inline void queues_flush(InitQueues &q, int32_t *wl_lo, unsigned long
 // second queue (they get their own launch, one wavefront each); over a list,
 // rows longer than skip_len are left to the split kernels.  Writes
 // C[v] = +T (kept) or -T (lost) and appends losers by bin.
-template <int G>
+// Compact copy of the colors for the neighbor reads of the rounds (T = int8_t,
+// when every color the coloring can take fits: the longest row plus X is at
+// most 127), written beside C at every change; T = int32_t: C itself.
+template <typename CT>
+__device__ inline void compact_put(CT *S, int32_t v, int32_t x) {
+    if (sizeof(CT) < sizeof(int32_t)) S[v] = (CT)x;
+}
+
+template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C, int32_t deg_wave,
+                                                       int64_t nnz, int32_t n, int32_t *C, CT *S, int32_t deg_wave,
                                                        int32_t skip_len, const int32_t *__restrict__ in_list,
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
@@ -182,7 +249,10 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
         const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, pr, s_color, X, randx != 0);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
-        if (leader && !forward) C[v] = lose ? -tv : tv;
+        if (leader && !forward) {
+            C[v] = lose ? -tv : tv;
+            compact_put<CT>(S, v, lose ? -tv : tv);
+        }
         if (v >= 0 && !forward && !lose) publish_long<G>(lm, col, e0, e1, n, tv);
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && (forward || (lose && hub)), v);
@@ -192,9 +262,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
 }
 
 // Assign step of round r >= 1: C[v] = -T for every v of the list.
-template <int G>
+template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C,
+                                                       int64_t nnz, int32_t n, int32_t *C, CT *S,
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
                                                        uint32_t X, int randx, unsigned long long *degsum,
@@ -235,9 +305,11 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
         int32_t t;
         const int32_t li = (G == 64 && lm.idx && v >= 0) ? lm.idx[v] : -1;  // one row per wavefront: uniform
         if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
-        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, C, n, j, lw);
+        else t = group_select_wide<G, ROW_UNROLL(G), CT>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n,
+                                                           j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
+            compact_put<CT>(S, v, -t);
             degs += (unsigned long long)(e1 - e0);
         }
     }
@@ -250,9 +322,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
 // Detect step of round r >= 1: v loses when a neighbor has the same tentative
 // color and a larger priority; winners commit (flip the sign), losers go to
 // the next worklist of their bin.
-template <int G>
+template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C, int32_t deg_wave,
+                                                       int64_t nnz, int32_t n, int32_t *C, CT *S, int32_t deg_wave,
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
@@ -283,23 +355,24 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         }
         const int32_t *src = act ? al.cur : col;
         const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
-        const bool lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src, C, n, pr, 0u, 1u, false);
-        const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
-        if (leader && !lose) C[v] = t;
-        if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
+        bool lose;
         if (G == 64 && al.next && v >= 0 && li >= 0) {
-            // the entries still uncolored: the row's list for the next round (one wavefront, in order)
+            // one scan decides the conflict and keeps the entries still uncolored:
+            // the row's list for the next round (one wavefront, in order)
             int32_t kept = 0;
-            for (int32_t eb = e0; eb < e1; eb += 64) {
-                const int32_t e = eb + __lane_id();
-                const int32_t w = e < e1 ? src[e] : -1;
-                const bool keep = (uint32_t)w < (uint32_t)n && C[w] <= 0;
-                const unsigned long long bm = __ballot(keep);
-                if (keep) al.next[e0 + kept + __popcll(bm & ((1ull << __lane_id()) - 1ull))] = w;
-                kept += (int32_t)__popcll(bm);
-            }
+            lose = wave_loses_keep<ROW_UNROLL(G), false>(t, pv, e0, e1, src, C, n, pr, al.next + e0, &kept, nullptr);
             if (__lane_id() == 0) al.len_next[li] = kept;
+        } else {
+            lose = group_loses<G, false, ROW_UNROLL(G), CT>(t, pv, e0, e1, src,
+                                                           sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, pr, 0u, 1u,
+                                                           false);
         }
+        const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
+        if (leader && !lose) {
+            C[v] = t;
+            compact_put<CT>(S, v, t);
+        }
+        if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
         const bool hub = full > deg_wave;  // worklist bins by the full row length
         bq_push(q.buf[0], &q.cnt[0], leader && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && lose && hub, v);
@@ -505,21 +578,12 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
         const int32_t t = ROUND0 ? round0_color(s_color, k.v, X, randx != 0) : -C[k.v];
         const uint64_t pv = round_prio(pr, k.v);
         const int32_t *src = k.act ? al.cur : col;
-        const bool lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, src, C, n, pr, s_color, X, randx != 0);
-        if (!ROUND0 && al.next && k.li >= 0) {
-            // the chunk's entries still uncolored go to the row's list for the next round
-            for (int32_t eb = k.a; eb < k.b; eb += 64) {
-                const int32_t e = eb + lane;
-                const int32_t w = e < k.b ? src[e] : -1;
-                const bool keep = (uint32_t)w < (uint32_t)n && C[w] <= 0;
-                const unsigned long long bm = __ballot(keep);
-                if (!bm) continue;
-                int32_t base = 0;
-                if (lane == 0) base = atomicAdd(&al.len_next[k.li], (int32_t)__popcll(bm));
-                base = __shfl(base, 0);
-                if (keep) al.next[k.e0 + base + __popcll(bm & ((1ull << lane) - 1ull))] = w;
-            }
-        }
+        bool lose;
+        if (!ROUND0 && al.next && k.li >= 0)  // the chunk's entries still uncolored go to the row's next list
+            lose = wave_loses_keep<ROW_UNROLL(64), false>(t, pv, k.a, k.b, src, C, n, pr, al.next + k.e0, nullptr,
+                                                          &al.len_next[k.li]);
+        else
+            lose = group_loses<64, ROUND0, ROW_UNROLL(64)>(t, pv, k.a, k.b, src, C, n, pr, s_color, X, randx != 0);
         if (lose && lane == 0) atomicOr(flag, 1ull);
         if (split_last(hub_cnt, k.slot, k.nsub)) {
             if (lane == 0) {
@@ -571,53 +635,249 @@ __global__ void k_long_index(const int32_t *__restrict__ rp, int32_t n, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Tail of the initial coloring: the remaining (small) rounds in one
+// persistent launch, rounds and their assign / detect steps separated by grid
+// barriers, so that no round pays for kernel launches and a host read-back.
+// One wavefront per vertex, with the per-vertex steps of k_assign<64> /
+// k_detect<64> (long-row masks and active lists included); losers go to a
+// single worklist.  Every workgroup must be resident for the barriers: the
+// workgroups first check in, and unless all of them do within a bounded
+// wait the launch decides to do nothing (the host then goes on round by
+// round from the same state).  Slots T = scal + S_TAIL: [0] check-in,
+// [1] decision (0 open, 1 run, 2 give up), [2] barrier arrivals, [3] barrier
+// generation, [4 + (q & 1)] losers of tail round q, [6 + (q & 1)] its degree
+// sum, [8] rounds run, [9] status.  Round q's record goes to round_stats.
+// ---------------------------------------------------------------------------
+
+#define TAIL_CHECKIN_LIMIT (1u << 14)
+
+// Grid barrier over every (resident) workgroup; false when a bounded wait ran
+// out (recorded as a sticky device error; the launch then stops).  Two
+// levels, so that no counter sees more than a few dozen arrivals: workgroup b
+// arrives at group counter b % TAIL_GROUPS (each on its own 128-byte line of
+// `bar`), the last of each group at the top counter, and the last of those
+// bumps the generation T[3] that everyone waits for.
+#define TAIL_GROUPS 16
+#define TAIL_LINE 16  // 64-bit words per 128-byte line
+__device__ inline bool tail_barrier(unsigned long long *T, unsigned long long *bar, uint32_t &gen, uint32_t limit,
+                                    unsigned long long *scal, int32_t *lds_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        const uint32_t groups = gridDim.x < TAIL_GROUPS ? gridDim.x : TAIL_GROUPS;
+        const uint32_t grp = blockIdx.x % groups;
+        const uint32_t gsize = (gridDim.x - grp + groups - 1) / groups;  // workgroups b with b % groups == grp
+        __threadfence();  // this workgroup's writes before the arrival
+        if (atomicAdd(&bar[grp * TAIL_LINE], 1ull) == gsize - 1) {
+            atomicExch(&bar[grp * TAIL_LINE], 0ull);
+            if (atomicAdd(&bar[TAIL_GROUPS * TAIL_LINE], 1ull) == groups - 1) {
+                atomicExch(&bar[TAIL_GROUPS * TAIL_LINE], 0ull);
+                __threadfence();
+                atomicExch(&T[3], (unsigned long long)(gen + 1));
+            }
+        }
+        uint32_t it = 0;
+        while ((uint32_t)__hip_atomic_load(&T[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            if (++it > limit) {
+                ok = false;
+                atomicOr(&scal[S_ERR], 2ull);
+                atomicOr(&scal[S_STICKY], 2ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();  // the other workgroups' writes after it
+        *lds_flag = ok ? 1 : 0;
+    }
+    gen++;
+    __syncthreads();
+    return *lds_flag != 0;
+}
+
+template <int UNR, typename CT>
+__global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n, int32_t *C, CT *S,
+    const int32_t *__restrict__ lo_in, const int32_t *__restrict__ hub_in, const unsigned long long *c_lo_in,
+    const unsigned long long *c_hub_in, int32_t *buf0, int32_t *buf1, int32_t r0, int32_t max_rounds, uint64_t seed,
+    int fixed_prio, Prio pbase, int randx, uint32_t X, LongMasks lm, ActiveLists al, long long *round_stats,
+    unsigned long long *T, unsigned long long *bar, unsigned long long *scal, uint32_t limit) {
+    __shared__ unsigned long long lmask[INIT_BLOCK];
+    __shared__ int32_t sh[4];
+    unsigned long long *lw = lmask + (threadIdx.x & ~63u);
+    const int lane = __lane_id();
+    // check in; run only if every workgroup is resident
+    if (threadIdx.x == 0) {
+        int32_t d = (int32_t)__hip_atomic_load(&T[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (d == 0) {
+            atomicAdd(&T[0], 1ull);
+            for (uint32_t it = 0;; it++) {
+                d = (int32_t)__hip_atomic_load(&T[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (d != 0) break;
+                if (__hip_atomic_load(&T[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gridDim.x)
+                    atomicCAS(&T[1], 0ull, 1ull);
+                else if (it > TAIL_CHECKIN_LIMIT)
+                    atomicCAS(&T[1], 0ull, 2ull);
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+        sh[0] = d;
+    }
+    __syncthreads();
+    if (sh[0] != 1) return;
+    const int wpb = INIT_BLOCK / 64;
+    const int64_t wave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int64_t waves = (int64_t)gridDim.x * wpb;
+    uint32_t gen = 0;
+    int32_t status = GC_OK;
+    int32_t q = 0;
+    for (;; q++) {
+        const int32_t R = r0 + q;
+        int64_t cnt_a, cnt_b = 0;
+        const int32_t *A, *B = hub_in;
+        if (q == 0) {
+            A = lo_in;
+            cnt_a = (int64_t)__hip_atomic_load(c_lo_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cnt_b = (int64_t)__hip_atomic_load(c_hub_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            A = (q - 1) & 1 ? buf1 : buf0;
+            cnt_a = (int64_t)__hip_atomic_load(&T[4 + ((q - 1) & 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int64_t cnt = cnt_a + cnt_b;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (q > 0) {  // the previous round's record
+                round_stats[2 * (int64_t)(R - 1)] = (long long)
+                    (q == 1 ? (int64_t)__hip_atomic_load(c_lo_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                                  (int64_t)__hip_atomic_load(c_hub_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : (int64_t)__hip_atomic_load(&T[4 + ((q - 2) & 1)], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+                round_stats[2 * (int64_t)(R - 1) + 1] =
+                    (long long)__hip_atomic_load(&T[6 + ((q - 1) & 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the degree-sum slot of round q - 1 is round q + 1's: clear it now
+                // (round q accumulates in the other one, cleared at the top of round q - 1)
+                atomicExch(&T[6 + ((q - 1) & 1)], 0ull);
+            }
+            // this round's loser count starts at 0 (the slot of round q - 2, recorded above)
+            if (q >= 2) atomicExch(&T[4 + (q & 1)], 0ull);
+        }
+        if (cnt == 0) break;
+        if (max_rounds > 0 && R >= max_rounds) {
+            status = GC_ERR_NOT_CONVERGED;
+            break;
+        }
+        // assign: the (j+1)-th color free among the neighbors' committed colors
+        const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)R);
+        unsigned long long degs = 0;
+        for (int64_t i = wave; i < cnt; i += waves) {
+            const int32_t v = i < cnt_a ? A[i] : B[i - cnt_a];
+            int32_t e0, e1;
+            row_range(rp, v, nnz, e0, e1);
+            const uint32_t j = randx ? gc_pick(sc, v, X) : 0u;
+            const int32_t li = lm.idx ? lm.idx[v] : -1;
+            int32_t t;
+            if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
+            else t = group_select_wide<64, UNR, CT>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, j, lw);
+            if (lane == 0) {
+                C[v] = -t;
+                compact_put<CT>(S, v, -t);
+                degs += (unsigned long long)(e1 - e0);
+            }
+        }
+        if (lane == 0 && degs) atomicAdd(&T[6 + (q & 1)], degs);
+        if (!tail_barrier(T, bar, gen, limit, scal, &sh[1])) return;
+        // detect: v loses to a neighbor of the same tentative color and larger
+        // priority.  The scan stops at the first batch with a conflict, and the
+        // active lists are read as they are (no compaction): an entry committed
+        // since is never a conflict (its color was excluded by the assign step).
+        Prio pr = pbase;
+        pr.s_prio = gc_stream_value(seed, GC_TAG_PRIO, fixed_prio ? 0u : (uint32_t)R);
+        int32_t *out = q & 1 ? buf1 : buf0;
+        for (int64_t i = wave; i < cnt; i += waves) {
+            const int32_t v = i < cnt_a ? A[i] : B[i - cnt_a];
+            int32_t e0, e1;
+            row_range(rp, v, nnz, e0, e1);
+            const int32_t full = e1 - e0;
+            int32_t li = -1;
+            bool act = false;
+            if (al.idx) {
+                li = al.idx[v];
+                if (li >= 0 && al.len[li] >= 0) {
+                    act = true;
+                    e1 = e0 + min(al.len[li], full);
+                }
+            }
+            const int32_t t = -C[v];
+            const int32_t *src = act ? al.cur : col;
+            const bool lose = wave_loses_keep<UNR, true, CT>(t, round_prio(pr, v), e0, e1, src,
+                                                            sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, pr,
+                                                            nullptr, nullptr, nullptr);
+            if (!lose) {
+                if (lane == 0) {
+                    C[v] = t;
+                    compact_put<CT>(S, v, t);
+                }
+                publish_long<64>(lm, src, e0, e1, n, t);
+            }
+            if (lose && lane == 0) out[atomicAdd(&T[4 + (q & 1)], 1ull)] = v;
+        }
+        if (!tail_barrier(T, bar, gen, limit, scal, &sh[1])) return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        T[8] = (unsigned long long)q;
+        T[9] = (unsigned long long)status;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
-template <int G>
-static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, int32_t skip_len,
+template <int G, typename CT>
+static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, int32_t deg_wave, int32_t skip_len,
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
                           int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx,
                           LongMasks lm) {
-    k_round0<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, skip_len, in_list, in_count, wl_lo,
+    k_round0<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, skip_len, in_list, in_count, wl_lo,
                                             c_lo, wl_hub, c_hub, pr, sc, X, randx, lm);
 }
 
-template <int G>
-static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, const int32_t *wl,
+template <int G, typename CT>
+static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, const int32_t *wl,
                           const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
                           int32_t skip_len, LongMasks lm, unsigned long long *zero2, unsigned long long *zero1,
                           unsigned long long *rec, const unsigned long long *rec_in) {
-    k_assign<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, wl, wc, sc, X, randx, degsum,
+    k_assign<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, wl, wc, sc, X, randx, degsum,
                                             skip_len, lm, zero2, zero1, rec, rec_in);
 }
 
-template <int G>
-static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, int32_t deg_wave, const int32_t *wl,
+template <int G, typename CT>
+static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                           unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
                           ActiveLists al) {
-    k_detect<G><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
+    k_detect<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
                                             c_hub, pr, skip_len, lm, al);
 }
 
-#define GC_DISPATCH_G(G, CALL)                           \
-    switch (G) {                                         \
-        case 1: { constexpr int GG = 1; CALL; } break;   \
-        case 2: { constexpr int GG = 2; CALL; } break;   \
-        case 4: { constexpr int GG = 4; CALL; } break;   \
-        case 8: { constexpr int GG = 8; CALL; } break;   \
-        case 16: { constexpr int GG = 16; CALL; } break; \
-        case 32: { constexpr int GG = 32; CALL; } break; \
-        default: { constexpr int GG = 64; CALL; } break; \
+#define GC_DISPATCH_G(G, ...)                                   \
+    switch (G) {                                                \
+        case 1: { constexpr int GG = 1; __VA_ARGS__; } break;   \
+        case 2: { constexpr int GG = 2; __VA_ARGS__; } break;   \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; } break; \
+        case 32: { constexpr int GG = 32; __VA_ARGS__; } break; \
+        default: { constexpr int GG = 64; __VA_ARGS__; } break; \
     }
 
 // Speculative rounds over every vertex (arguments already checked, n > 0).
 // prank == NULL: the initial coloring with hash priorities; otherwise a
 // per-vertex class rank that decides conflicts (asynchronous recoloring).
-gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
-                         uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank) {
+template <typename CT>
+static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                               int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s,
+                               const int32_t *prank, CT *S) {
     gc_status status = GC_OK;
     if (select == GC_FIRST_FIT) X = 1;
     const int randx = select == GC_RANDOM_X ? 1 : 0;
@@ -724,11 +984,11 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     unsigned long long *plan = plan0;  // the current round's plan total
     const Prio sp0 = prio_of(0);
     const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
-    GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG>(grid_for(n, GG), s, g, colors, deg_wave, skip, nullptr,
+    GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG, CT>(grid_for(n, GG), s, g, colors, S, deg_wave, skip, nullptr,
                                                                 nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
                                                                 sc0, (uint32_t)X, randx, lm)));
     GC_LAUNCHED();
-    GC_TIMED(GC_K_ROUND0, s, launch_round0<64>(cap, s, g, colors, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
+    GC_TIMED(GC_K_ROUND0, s, launch_round0<64, CT>(cap, s, g, colors, S, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
                                                ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, lm));
     GC_LAUNCHED();
     if (split) {
@@ -761,6 +1021,15 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
     // sum in scal[S_REC + 2q ..], so the statistics stay exact.
     const bool ahead = !split && !lists;
     int32_t batch = 0;  // rounds queued since the last read-back
+    // Rounds of at most tail_max vertices run in one persistent launch
+    // (k_tail_rounds) once no row needs the split kernels.
+    bool tail_on = ctx->tune.tail_max >= 0;
+    const int64_t tail_max = ctx->tune.tail_max > 0 ? ctx->tune.tail_max : 16384;
+    int tail_per_cu = 0;  // one workgroup per compute unit, when the kernel fits at all
+    GC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &tail_per_cu, reinterpret_cast<const void *>(k_tail_rounds<ROW_UNROLL(64), CT>), INIT_BLOCK, 0));
+    if (tail_per_cu < 1) tail_on = false;
+    const int tail_grid = ctx->num_cu;
     for (;;) {
         gc_status ss = gc_sync_scalars(ctx, s);
         if (ss) return ss;
@@ -779,6 +1048,43 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (tot == 0) break;
         if (max_rounds > 0 && r == max_rounds) { status = GC_ERR_NOT_CONVERGED; break; }
         if (r > n) return gc_fail(ctx, GC_ERR_DEVICE, "no progress after %d rounds", r);  // each round commits >= 1 vertex
+        if (tail_on && !split_live && tot <= tail_max) {
+            // the remaining rounds in one persistent launch
+            unsigned long long *T = ctx->scal + S_TAIL;
+            GC_HIP(hipMemsetAsync(T, 0, 10 * 8, s));
+            GC_HIP(hipMemsetAsync(ctx->sync, 0, GC_SYNC_BYTES, s));
+            const int nxt = cur ^ 1;
+            const ActiveLists al = lists_of(false);  // read as they are
+            const bool fixed = (flags & (GC_FLAG_FIXED_PRIORITY | GC_FLAG_PRIO_LF)) != 0;
+            const uint32_t limit = ctx->tune.spin_limit > 0 ? (uint32_t)ctx->tune.spin_limit : (1u << 20);
+            GC_TIMED(GC_K_DETECT, s, k_tail_rounds<ROW_UNROLL(64), CT><<<tail_grid, INIT_BLOCK, 0, s>>>(
+                                         g->row_ptr, g->col_idx, g->nnz, n, colors, S, ctx->wl[2 * cur],
+                                         ctx->wl[2 * cur + 1],
+                                         cnt + 2 * cur, cnt + 2 * cur + 1, ctx->wl[2 * nxt], ctx->wl[2 * cur], r,
+                                         max_rounds, seed, fixed ? 1 : 0, prio_of(0), randx, (uint32_t)X, lm, al,
+                                         (long long *)ctx->round_stats, T, ctx->sync, ctx->scal, limit));
+            GC_LAUNCHED();
+            ss = gc_sync_scalars(ctx, s);
+            if (ss) return ss;
+            if (ctx->hscal[S_TAIL + 1] == 1) {
+                const int32_t q = (int32_t)ctx->hscal[S_TAIL + 8];
+                if (q > 0) {
+                    std::vector<long long> rec((size_t)2 * q);
+                    GC_HIP(hipMemcpyAsync(rec.data(), ctx->round_stats + 2 * (int64_t)r, rec.size() * 8,
+                                          hipMemcpyDeviceToHost, s));
+                    GC_HIP(hipStreamSynchronize(s));
+                    for (int32_t i = 0; i < q; i++) {
+                        sizes.push_back(rec[2 * i]);
+                        degsum.push_back(rec[2 * i + 1]);
+                    }
+                }
+                r += q;
+                // (a barrier that ran out is a sticky device error, reported by the entry point)
+                if (ctx->hscal[S_TAIL + 9] == GC_ERR_NOT_CONVERGED) status = GC_ERR_NOT_CONVERGED;
+                break;
+            }
+            tail_on = false;  // not every workgroup was resident: go on round by round
+        }
         sizes.push_back(tot);
         batch = 1;
         if (ahead) {
@@ -806,14 +1112,14 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                 GC_LAUNCHED();
             }
             if (nlo) {
-                GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG>(grid_for(nlo, GG), s, g, colors, lo_in, c_lo_in,
+                GC_TIMED(GC_K_ASSIGN, s, GC_DISPATCH_G(G, launch_assign<GG, CT>(grid_for(nlo, GG), s, g, colors, S, lo_in, c_lo_in,
                                                                             sc, (uint32_t)X, randx, dsum, skip, lm, c_lo_out,
                                                                             dsum_next, rec, c_lo_in)));
                 GC_LAUNCHED();
             }
             if (nhub) {
                 // with the masks, long rows of every length take their color here
-                GC_TIMED(GC_K_ASSIGN, s, launch_assign<64>(grid_for(nhub, 64), s, g, colors, hub_in, c_hub_in, sc, (uint32_t)X,
+                GC_TIMED(GC_K_ASSIGN, s, launch_assign<64, CT>(grid_for(nhub, 64), s, g, colors, S, hub_in, c_hub_in, sc, (uint32_t)X,
                                                            randx, dsum, masks ? INT32_MAX : skip, lm, c_lo_out, dsum_next,
                                                            nlo ? nullptr : rec, c_lo_in));
                 GC_LAUNCHED();
@@ -826,13 +1132,13 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
                 GC_LAUNCHED();
             }
             if (nlo) {
-                GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG>(grid_for(nlo, GG), s, g, colors, deg_wave, lo_in,
+                GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG, CT>(grid_for(nlo, GG), s, g, colors, S, deg_wave, lo_in,
                                                                             c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
                                                                             sp, skip, lm, al)));
                 GC_LAUNCHED();
             }
             if (nhub) {
-                GC_TIMED(GC_K_DETECT, s, launch_detect<64>(grid_for(nhub, 64), s, g, colors, deg_wave, hub_in, c_hub_in, lo_out,
+                GC_TIMED(GC_K_DETECT, s, launch_detect<64, CT>(grid_for(nhub, 64), s, g, colors, S, deg_wave, hub_in, c_hub_in, lo_out,
                                                            c_lo_out, hub_out, c_hub_out, sp, skip, lm, al));
                 GC_LAUNCHED();
             }
@@ -873,6 +1179,20 @@ gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X
         if (status == GC_ERR_NOT_CONVERGED) gc_fail(ctx, status, "not converged after %d rounds", max_rounds);
     }
     return status;
+}
+
+gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
+                         uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank) {
+    // neighbor reads through a one-byte copy of the colors when no color can
+    // exceed 127: a color is at most the row length plus X
+    int32_t maxdeg = 0;
+    gc_status status = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (status) return status;
+    const int32_t xw = select == GC_FIRST_FIT ? 1 : X;
+    if (ctx->tune.compact_init != 0 && (int64_t)maxdeg + xw <= 127)
+        return spec_rounds_t<int8_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank,
+                                     (int8_t *)ctx->shadow);
+    return spec_rounds_t<int32_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank, colors);
 }
 
 static gc_status gc_init_color_impl(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,

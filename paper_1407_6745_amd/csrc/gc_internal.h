@@ -23,6 +23,7 @@
 #define GC_HIST_LDS 4096
 #define GC_HIST_COPIES 16
 #define GC_HCOPY_INTS (3 * GC_HIST_COPIES * GC_HIST_LDS)
+#define GC_SYNC_BYTES 4096  // grid-barrier counters, one 128-byte line each
 
 // Device scalar slots (int64 each) in ctx->scal.
 enum {
@@ -45,6 +46,9 @@ enum {
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
     S_REC = 26,      // rounds queued ahead (26..33): input size, previous round's degree sum
+    S_VLONG = 35,    // validation: (row, chunk) pairs of long rows listed
+    S_TAIL = 36,     // initial coloring's persistent tail launch (36..45): check-in, decision, barrier count and
+                     // generation, two list counts, two degree sums, rounds run, status
     S_STICKY = 34,   // device failures kept until a synchronizing call reports them (bit 1: a walk wait
                      // gave up, bit 2: walk workgroups not all resident); never cleared by a pass
     S_COUNT = 64
@@ -52,7 +56,8 @@ enum {
 
 struct gc_ctx {
     int device;
-    int num_cu;
+    int num_cu;              // compute units this context's launches are sized for (the cu_count knob, else all)
+    int dev_cu;              // compute units of the device
     int64_t max_n;
     int64_t max_nnz;
     int32_t ccap;            // largest color any buffer indexed by color can hold
@@ -107,6 +112,7 @@ struct gc_ctx {
     int64_t bws_layout;      // batched coloring: (V << 16 | X) the workspace slices were last laid out for
     unsigned long long sticky;  // device failures harvested from S_STICKY, not yet reported
     unsigned long long *trace;  // class-completion trace of the last persistent walk (tuning.trace), on demand
+    unsigned long long *sync;   // grid-barrier counters of the initial coloring's tail launch (GC_SYNC_BYTES)
     char err[512];
 };
 
@@ -227,7 +233,7 @@ __host__ __device__ inline uint32_t gc_fmix32(uint32_t h) {
 // Per-round (or per-pass) stream value: the top 32 bits of
 // mix64(seed + golden * (tag << 32 | counter)).  Uniform over a launch, so the
 // host computes it once and passes it to the kernels.
-inline uint32_t gc_stream_value(uint64_t seed, uint32_t tag, uint32_t counter) {
+__host__ __device__ inline uint32_t gc_stream_value(uint64_t seed, uint32_t tag, uint32_t counter) {
     return (uint32_t)(gc_mix64(seed + GC_GOLDEN * (((uint64_t)tag << 32) | counter)) >> 32);
 }
 
@@ -567,8 +573,8 @@ __device__ inline void bq_flush(int32_t *lbuf, int32_t *lcnt, int32_t *lbase, in
 
 // (j+1)-th smallest positive color absent from {C[w] > 0 : w in row}, by a
 // group of G lanes (group-uniform result).  Colors <= 0 are "no color".
-template <int G>
-__device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+template <int G, typename T = int32_t>
+__device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const T *C,
                                        int32_t n, uint32_t j, uint32_t base = 0) {
     const int l = __lane_id() & (G - 1);
     for (;;) {
@@ -652,8 +658,8 @@ __device__ inline uint32_t wave_nth_free(uint64_t word, uint32_t j) {
 // 65 .. 64 * G in the group's LDS words (lw: the wavefront's 64 words, lane L
 // owns lw[L]); colors beyond rescan the row in 64-color windows.  Result
 // uniform over the group.
-template <int G, int UNR = GC_UNROLL>
-__device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+template <int G, int UNR = GC_UNROLL, typename T = int32_t>
+__device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const T *C,
                                             int32_t n, uint32_t j, unsigned long long *lw) {
     const int lane = __lane_id();
     const int o = lane & (G - 1);
@@ -701,5 +707,5 @@ __device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int
         return (int32_t)__shfl(r, fl);
     }
     const uint32_t total = __shfl(inc, gfirst + G - 1);
-    return group_select<G>(col, e0, e1, C, n, j - total, 64u * G);
+    return group_select<G, T>(col, e0, e1, C, n, j - total, 64u * G);
 }

@@ -437,15 +437,21 @@ __device__ inline void compact_store(void *S, int32_t v, int32_t color) {
 
 // Bounded waits of the walk: polls before giving up, and the scalar slots
 // where a wait that gave up is recorded (per pass, and sticky).
+// walk_flags knob bits
+#define WALK_LONG_FIRST 1u   // inside a rank: split rows, then wavefront rows, then group rows
+#define WALK_EARLY_MERGE 2u  // a waiting split-row sub-chunk takes the others' words once they are all in
+
 struct WaitCtl {
     unsigned long long *scal;
     uint32_t limit;
+    uint32_t flags;  // walk_flags
     // class-completion trace (NULL = off): [0] walk start, [1] walk end,
     // [2 + 2s] latest completion of a rank-s vertex, [3 + 2s] of a rank-s split row
     unsigned long long *trace;
 };
 
-// Trace record of a vertex of rank s that has just published its color.
+// Trace record of a split row of rank s that has just published its color
+// (the other vertices are recorded per wavefront and rank, see walk_body).
 __device__ inline void trace_done(const WaitCtl &wc, int32_t s, bool split) {
     if (wc.trace) {
         const unsigned long long t = wall_clock64();
@@ -454,6 +460,18 @@ __device__ inline void trace_done(const WaitCtl &wc, int32_t s, bool split) {
     }
 }
 
+// A sub-chunk of a split row while it waits: the row's hub slot (finished
+// sub-chunks and their merged mask words).  When every other sub-chunk of the
+// row has finished (count nsub - 1), the waiting one takes their words into
+// its own mask at once (merged): it is the last, and publishes the row's color
+// as soon as its own waits end, with no further round trip through the slot.
+struct HubWait {
+    int32_t *cnt;
+    const unsigned long long *bits;
+    int32_t nsub, words;
+    bool merged;
+};
+
 // Neighbor words -> marks for colors of lower ranks.  Words of lower ranks
 // that are not final yet (or whose plain load saw a stale line) are re-read
 // in one wavefront-uniform slow path: every pending word of every lane is
@@ -461,7 +479,8 @@ __device__ inline void trace_done(const WaitCtl &wc, int32_t s, bool split) {
 // are final by then; the rest is branch-free.
 template <int U, bool WIDE>
 __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t base, uint64_t &m,
-                              unsigned long long *lw, int gfirst, int gw, int32_t *C, const WaitCtl &wc) {
+                              unsigned long long *lw, int gfirst, int gw, int32_t *C, const WaitCtl &wc,
+                              HubWait *hw = nullptr) {
     bool pend[U];
     bool need = false;
 #pragma unroll
@@ -490,6 +509,22 @@ __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t
                 left |= pend[u];
             }
             if (!__ballot(left)) break;
+            if (hw && !hw->merged) {
+                int32_t done = 0;
+                if (__lane_id() == 0) done = __hip_atomic_load(hw->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                done = __shfl(done, 0);
+                if (done == hw->nsub - 1) {
+                    // each other sub-chunk ORed its words and fenced before counting itself
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    const int lane = __lane_id();
+                    const uint64_t b =
+                        lane < hw->words ? __hip_atomic_load(&hw->bits[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                         : 0ull;
+                    if (lane == 0) m |= b;  // word 0 lives in the register words (ORed over the wavefront later)
+                    else if (b) atomicOr(&lw[lane - 1], b);
+                    hw->merged = true;
+                }
+            }
             if (it >= wc.limit ||
                 ((it & 1023u) == 1023u &&
                  (__hip_atomic_load(&wc.scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))) {
@@ -524,7 +559,7 @@ __device__ inline void gather(const int32_t *w, int32_t *xv, const int32_t *C, i
 template <int U, bool WIDE>
 __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t *__restrict__ col, int32_t n,
                                   int32_t s, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw,
-                                  int32_t *C, const WaitCtl &wc) {
+                                  int32_t *C, const WaitCtl &wc, HubWait *hw = nullptr) {
     for (int32_t eb = e; __ballot(eb < e1); eb += U * gsz) {
         int32_t ww[U], xx[U];
 #pragma unroll
@@ -535,7 +570,7 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
             ww[u] = ok ? wl : -1;
         }
         gather<U>(ww, xx, C, n);
-        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, wc);
+        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, wc, hw);
     }
 }
 
@@ -593,7 +628,6 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
     if (t.v >= 0 && l == 0) {
         __hip_atomic_store(&C[t.v], (int32_t)(base + r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         compact_store<CT>(S, t.v, (int32_t)(base + r));
-        trace_done(wc, s, false);
     }
 }
 
@@ -618,14 +652,36 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
     int32_t xv[U];
     #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = x[u];
-    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc);
-    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc);
+    HubWait hw{hub_cnt + t.slot, bits, t.nsub, words, false};
+    HubWait *hwp = (wc.flags & WALK_EARLY_MERGE) ? &hw : nullptr;
+    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp);
+    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp);
     m = group_or_rt(m, 64);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // word i of the row: register word for i = 0, LDS word i - 1 above
     const uint64_t lword = lane >= 1 ? lw[lane - 1] : 0ull;
     const uint64_t mine = lane == 0 ? m : lword;
+    if (hw.merged) {
+        // the other sub-chunks' words are already in this mask: publish now,
+        // then clear the slot for the next pass
+        const uint64_t word = lane < words ? mine : ~0ull;
+        const uint64_t fr = __ballot(~word != 0ull);
+        uint32_t r = 64u * (uint32_t)words + 1u;  // unreachable: at most s colors are taken
+        if (fr) {
+            const int first = __ffsll((long long)fr) - 1;
+            const uint64_t wf = __shfl(word, first);
+            r = 64u * (uint32_t)first + (uint32_t)__ffsll((long long)~wf);
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&C[t.v], (int32_t)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            compact_store<CT>(S, t.v, (int32_t)r);
+            trace_done(wc, s, true);
+        }
+        if (lane < words) atomicExch(&bits[lane], 0ull);
+        if (lane == 0) atomicExch(&hub_cnt[t.slot], 0);
+        return;
+    }
     if (lane < words && mine) atomicOr(&bits[lane], mine);
     __threadfence();
     int32_t done = 0;
@@ -669,15 +725,24 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     const uint32_t x = xl ? (blockIdx.x & 7) : 0;
     const uint32_t Wx = (gridDim.x >> xl) * wpb;  // wavefronts sharing one part
     const uint32_t me = (blockIdx.x >> xl) * wpb + wib;
-    // cursor over this wavefront's chunks: segment seg, chunk c in [.., hi)
-    int32_t seg = -1;
+    // cursor over this wavefront's chunks: segment seg, chunk c in [.., hi).
+    // Segments are visited rank by rank; inside a rank (whose vertices never
+    // wait for each other) the split rows come first, then the wavefront rows,
+    // then the group rows: the longest scans of a class start earliest, and a
+    // split row's sub-chunks are already waiting when the previous class ends.
+    int32_t idx = -1, seg = -1;
     uint32_t c = 0, hi = 0;
     bool first = true;
     auto advance = [&]() {
         if (!first) c += Wx;
         first = false;
         while (c >= hi) {
-            if (++seg >= nseg) return;
+            if (++idx >= nseg) {
+                seg = nseg;
+                return;
+            }
+            seg = (wc.flags & WALK_LONG_FIRST) ? idx - idx % NSEG_PER_RANK + (NSEG_PER_RANK - 1 - idx % NSEG_PER_RANK)
+                                               : idx;
             const uint32_t s0 = (uint32_t)CO[seg], len = (uint32_t)CO[seg + 1] - s0;
             const uint32_t lo = s0 + (uint32_t)(((uint64_t)len * x) >> xl);
             hi = s0 + (uint32_t)(((uint64_t)len * (x + 1)) >> xl);
@@ -767,6 +832,13 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     // (C, plain loads; stale or unfinished words are re-read in stage D), and
     // chunk i's waits, First Fit and store (D).  Every stage's inputs were
     // requested one iteration earlier.
+    // trace: this wavefront's latest finish time in its current rank, one
+    // atomic per (wavefront, rank) instead of one per vertex
+    int32_t tr_rank = -1;
+    unsigned long long tr_time = 0;
+    auto trace_flush = [&]() {
+        if (wc.trace && tr_rank >= 0 && lane == 0) atomicMax(&wc.trace[2 + 2 * (int64_t)tr_rank], tr_time);
+    };
     advance();
     WalkChunk c0, c1, c2, c3;
     int32_t w0[U], w1[U], w2[U], x0[U], x1[U];
@@ -781,6 +853,14 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
         if (c2.seg < nseg) load_ids(c2, w2);             // B: chunk i+2
         if (c1.seg < nseg) gather_c(w1, x1);             // C: chunk i+1
         finish(c0, w0, x0);                              // D: chunk i
+        if (wc.trace) {
+            const int32_t rk = c0.seg / NSEG_PER_RANK;
+            if (rk != tr_rank) {
+                trace_flush();
+                tr_rank = rk;
+            }
+            tr_time = wall_clock64();
+        }
         c0 = c1;
         c1 = c2;
         c2 = c3;
@@ -791,6 +871,7 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             w1[u] = w2[u];
         }
     }
+    trace_flush();
 }
 
 // Persistent dataflow class walk (one launch per pass).
@@ -816,7 +897,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
                                                           const int32_t *__restrict__ sbase, int32_t split_len,
                                                           unsigned long long *hub_bits, int32_t *hub_cnt,
                                                           unsigned long long *scal, int32_t xcd, int32_t check_resident,
-                                                          uint32_t spin_limit, unsigned long long *trace, void *S) {
+                                                          uint32_t spin_limit, uint32_t walk_flags,
+                                                          unsigned long long *trace, void *S) {
     __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
     __shared__ unsigned long long lmask[WALK_BLOCK];  // per wavefront: 64 mask words for colors above 64
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
@@ -842,7 +924,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
     }
     const int32_t k = (int32_t)scal[S_K];
     const int32_t nseg = NSEG_PER_RANK * k;
-    const WaitCtl wc = {scal, spin_limit, trace};
+    const WaitCtl wc = {scal, spin_limit, walk_flags, trace};
     if (trace && threadIdx.x == 0) atomicMin(&trace[0], wall_clock64());
     if (nseg <= WALK_TAB) {
         // segment tables in LDS: their reads are tracked apart from the vector
@@ -877,7 +959,7 @@ __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__re
 
 typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const int32_t *, const int32_t *,
                         const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
-                        unsigned long long *, int32_t, int32_t, uint32_t, unsigned long long *, void *);
+                        unsigned long long *, int32_t, int32_t, uint32_t, uint32_t, unsigned long long *, void *);
 
 template <bool FULL>
 static walk_fn walk_kernel_t(int G) {
@@ -934,7 +1016,7 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
             GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
             hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C, ctx->list, ctx->off,
                                ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2,
-                               spin_limit, nullptr, ctx->shadow);
+                               spin_limit, 0u, nullptr, ctx->shadow);
             GC_LAUNCHED();
             gc_status st = gc_sync_scalars(ctx, s);
             if (st) return st;
@@ -968,7 +1050,7 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C,
                                               ctx->list, ctx->off, ctx->coff, ctx->hsub, ctx->sbase, split_len,
                                               hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident,
-                                              spin_limit, trace, ctx->shadow));
+                                              spin_limit, (uint32_t)ctx->tune.walk_flags, trace, ctx->shadow));
     GC_LAUNCHED();
     return GC_OK;
 }

@@ -89,8 +89,24 @@ struct Waiting {
 struct Slot {
     gc_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
 };
+
+// Compute-unit mask of slot s out of `slots` on a device of `cus` compute
+// units in 8 XCDs: unit i goes to slot (i / (cus / 8) + i) % slots, so every
+// slot holds units of every XCD whether the mask's bits count units XCD by
+// XCD (i / (cus / 8)) or round robin over the XCDs (i % 8).
+std::vector<uint32_t> slot_cu_mask(int cus, int slots, int s, int *count) {
+    std::vector<uint32_t> m((size_t)(cus + 31) / 32, 0u);
+    const int block = cus / 8 > 0 ? cus / 8 : 1;
+    *count = 0;
+    for (int i = 0; i < cus; i++)
+        if ((i / block + i) % slots == s) {
+            m[(size_t)i / 32] |= 1u << (i % 32);
+            ++*count;
+        }
+    return m;
+}
 
 int64_t footprint_of(const gc_request &r) {
     return align_up(4 * ((int64_t)r.n + 1)) + align_up(4 * r.nnz) + align_up(4 * (int64_t)r.n);
@@ -112,6 +128,9 @@ struct gc_server {
     std::condition_variable gate_cv;
     int gate_shared = 0, gate_waiting = 0;
     bool gate_excl = false;
+    bool partitioned = false;  // slots on disjoint compute units: no gate
+    int slot_cus = 0;
+    hipEvent_t ref = nullptr;  // device time reference of the pass timestamps
     std::condition_variable cv_work, cv_done;
     std::deque<Waiting> queue;
     std::deque<gc_request_done> done;
@@ -125,15 +144,18 @@ struct gc_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     void enter_shared() {
+        if (partitioned) return;
         std::unique_lock<std::mutex> lk(gate_mu);
         gate_cv.wait(lk, [&] { return !gate_excl && gate_waiting == 0; });
         gate_shared++;
     }
     void leave_shared() {
+        if (partitioned) return;
         std::lock_guard<std::mutex> lk(gate_mu);
         if (--gate_shared == 0) gate_cv.notify_all();
     }
     void enter_excl() {
+        if (partitioned) return;
         std::unique_lock<std::mutex> lk(gate_mu);
         gate_waiting++;
         gate_cv.wait(lk, [&] { return !gate_excl && gate_shared == 0; });
@@ -141,6 +163,7 @@ struct gc_server {
         gate_excl = true;
     }
     void leave_excl() {
+        if (partitioned) return;
         std::lock_guard<std::mutex> lk(gate_mu);
         gate_excl = false;
         gate_cv.notify_all();
@@ -180,19 +203,33 @@ gc_request_done gc_server::run(int idx, const Waiting &w, int64_t off) {
     d.rounds = s0.rounds;
     d.colors_init = s0.num_colors;
     d.colors_final = s0.num_colors;
-    for (int32_t p = 0; p < r.passes && st == GC_OK; p++) {
-        enter_excl();
-        st = gc_recolor(sl.ctx, &g, r.perm, r.seed, p, colors, colors, p == r.passes - 1 ? &s1 : nullptr, sl.stream);
-        if (st == GC_OK && p == r.passes - 1) d.colors_final = s1.num_colors;
-        hip_ok(hipStreamSynchronize(sl.stream));
-        leave_excl();
+    hip_ok(hipEventRecord(sl.evp0, sl.stream));
+    if (partitioned) {
+        // the slot's own compute units: the passes go back to back, one synchronization at the end
+        for (int32_t p = 0; p < r.passes && st == GC_OK; p++) {
+            st = gc_recolor(sl.ctx, &g, r.perm, r.seed, p, colors, colors, p == r.passes - 1 ? &s1 : nullptr,
+                            sl.stream);
+            if (st == GC_OK && p == r.passes - 1) d.colors_final = s1.num_colors;
+        }
+    } else {
+        for (int32_t p = 0; p < r.passes && st == GC_OK; p++) {
+            enter_excl();
+            st = gc_recolor(sl.ctx, &g, r.perm, r.seed, p, colors, colors, p == r.passes - 1 ? &s1 : nullptr,
+                            sl.stream);
+            if (st == GC_OK && p == r.passes - 1) d.colors_final = s1.num_colors;
+            hip_ok(hipStreamSynchronize(sl.stream));
+            leave_excl();
+        }
     }
+    hip_ok(hipEventRecord(sl.evp1, sl.stream));
     if (st == GC_OK && r.n > 0)
         hip_ok(hipMemcpyAsync(r.colors, colors, 4 * (size_t)r.n, hipMemcpyDeviceToHost, sl.stream));
     hip_ok(hipEventRecord(sl.ev1, sl.stream));
     hip_ok(hipStreamSynchronize(sl.stream));
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, sl.ev0, sl.ev1) == hipSuccess) d.device_ms = ms;
+    if (hipEventElapsedTime(&ms, ref, sl.evp0) == hipSuccess) d.pass_start_ms = ms;
+    if (hipEventElapsedTime(&ms, ref, sl.evp1) == hipSuccess) d.pass_end_ms = ms;
     d.status = st;
     return d;
 }
@@ -280,9 +317,12 @@ static gc_status warm_walks(gc_server *s) {
 }
 
 static void server_free(gc_server *s) {
+    if (s->ref) (void)hipEventDestroy(s->ref);
     for (Slot &sl : s->slots) {
         if (sl.ev0) (void)hipEventDestroy(sl.ev0);
         if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+        if (sl.evp0) (void)hipEventDestroy(sl.evp0);
+        if (sl.evp1) (void)hipEventDestroy(sl.evp1);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ctx) gc_ctx_destroy(sl.ctx);
     }
@@ -311,6 +351,12 @@ extern "C" gc_status gc_server_create(const gc_server_config *cfg, gc_server **o
     }
     s->arena.reset(cfg->hbm_budget);
     s->slots.resize(cfg->slots);
+    int dev_cus = 0;
+    if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess) {
+        server_free(s);
+        return GC_ERR_DEVICE;
+    }
+    s->slot_cus = dev_cus;
     for (Slot &sl : s->slots) {
         gc_status st = gc_ctx_create(cfg->device, cfg->max_n, cfg->max_nnz, &sl.ctx);
         if (st != GC_OK) {
@@ -318,10 +364,50 @@ extern "C" gc_status gc_server_create(const gc_server_config *cfg, gc_server **o
             server_free(s);
             return st;
         }
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreate(&sl.ev0) != hipSuccess || hipEventCreate(&sl.ev1) != hipSuccess) {
+        if (hipEventCreate(&sl.ev0) != hipSuccess || hipEventCreate(&sl.ev1) != hipSuccess ||
+            hipEventCreate(&sl.evp0) != hipSuccess || hipEventCreate(&sl.evp1) != hipSuccess) {
             server_free(s);
             return GC_ERR_DEVICE;
+        }
+    }
+    // compute-unit partitions: at least one unit of every XCD per slot
+    s->partitioned = cfg->cu_partition != 0 && dev_cus / cfg->slots >= 8;
+    if (s->partitioned) {
+        for (int i = 0; i < cfg->slots && s->partitioned; i++) {
+            Slot &sl = s->slots[i];
+            int cnt = 0;
+            std::vector<uint32_t> mask = slot_cu_mask(dev_cus, cfg->slots, i, &cnt);
+            if (hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+                sl.stream = nullptr;
+                (void)hipGetLastError();
+                s->partitioned = false;  // the runtime refused the mask: the slots share the device
+                break;
+            }
+            gc_tuning t;
+            gc_ctx_get_tuning(sl.ctx, &t);
+            t.cu_count = cnt;
+            gc_ctx_set_tuning(sl.ctx, &t);
+            s->slot_cus = cnt;
+        }
+        if (!s->partitioned) {
+            for (Slot &sl : s->slots) {
+                if (sl.stream) (void)hipStreamDestroy(sl.stream);
+                sl.stream = nullptr;
+                gc_tuning t;
+                gc_ctx_get_tuning(sl.ctx, &t);
+                t.cu_count = 0;
+                gc_ctx_set_tuning(sl.ctx, &t);
+            }
+            s->slot_cus = dev_cus;
+        }
+    }
+    if (!s->partitioned) {
+        for (Slot &sl : s->slots) {
+            if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+                sl.stream = nullptr;
+                server_free(s);
+                return GC_ERR_DEVICE;
+            }
         }
     }
     // Size every slot's persistent walk on the idle device (the walk measures
@@ -333,6 +419,11 @@ extern "C" gc_status gc_server_create(const gc_server_config *cfg, gc_server **o
             server_free(s);
             return st;
         }
+    }
+    if (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, s->slots[0].stream) != hipSuccess ||
+        hipEventSynchronize(s->ref) != hipSuccess) {
+        server_free(s);
+        return GC_ERR_DEVICE;
     }
     for (int i = 0; i < cfg->slots; i++) s->workers.emplace_back(&gc_server::worker, s, i);
     *out = s;
@@ -387,6 +478,8 @@ extern "C" gc_status gc_server_get_stats(gc_server *s, gc_server_stats *o) {
     o->arena_size = s->arena.size();
     o->arena_used = s->arena.used();
     o->arena_peak = s->arena.peak();
+    o->cu_partition = s->partitioned ? 1 : 0;
+    o->slot_cus = s->slot_cus;
     return GC_OK;
 }
 

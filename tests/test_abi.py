@@ -92,10 +92,10 @@ def test_server_struct_layouts():
     """The binding's ctypes mirrors of the server structs have the C sizes."""
     import paper_1407_6745_amd as gc
 
-    assert ctypes.sizeof(gc.ServerConfigArgs) == 32
+    assert ctypes.sizeof(gc.ServerConfigArgs) == 40
     assert ctypes.sizeof(gc.RequestArgs) == 72
-    assert ctypes.sizeof(gc.RequestDoneArgs) == 72
-    assert ctypes.sizeof(gc.ServerStatsArgs) == 64
+    assert ctypes.sizeof(gc.RequestDoneArgs) == 88
+    assert ctypes.sizeof(gc.ServerStatsArgs) == 80
     assert gc.request_footprint(0, 0) == 256 + 0 + 0
     assert gc.request_footprint(100, 1000) == 512 + 4096 + 512
 

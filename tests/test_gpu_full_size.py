@@ -198,3 +198,40 @@ def test_full_batch_4096(gc):
             assert per[gi, 2] == ref["passes_out"][-1]["num_colors"], gi
         del colors
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["rmat22", "mesh128"])
+def test_full_size_no_stats_path(gc, name):
+    """The benchmark's call sequence: whole steps without statistics (the
+    timed path: no synchronization inside a pass), a traced pass, then the
+    initial coloring and every pass again without statistics, each compared
+    with the oracle's digest."""
+    ref = GOLD["workloads"][name]
+    g = eval(ref["graph"])
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(d)
+    col = torch.from_numpy(g.col).to(d)
+    sel = gc.FIRST_FIT if ref["select"] == "FIRST_FIT" else gc.RANDOM_X
+    perm = PERM[ref["perm"]]
+    ctx = gc.Context(g.n, g.nnz)
+    c = torch.empty(g.n, dtype=torch.int32, device=d)
+    for step in range(2):
+        gc.init_color(rp, col, sel, ref["X"], ref["seed"], out=c, stats=False, ctx=ctx)
+        for p in range(len(ref["passes_out"])):
+            gc.recolor(rp, col, c, perm, ref["seed"], p, out=c, stats=False, ctx=ctx)
+        ctx.raise_status()
+        assert digest(c) == ref["passes_out"][-1]["sha256"], f"step {step}: differs from the oracle"
+    ctx.set_tuning(trace=1)
+    t = c.clone()
+    gc.recolor(rp, col, t, perm, ref["seed"], 0, out=t, stats=False, ctx=ctx)
+    tr = ctx.walk_trace()
+    assert len(tr["class_done"]) == ref["passes_out"][-1]["num_colors"] and tr["end"] > 0
+    assert all(0 < x <= tr["end"] for x in tr["class_done"])
+    ctx.set_tuning(trace=0)
+    gc.init_color(rp, col, sel, ref["X"], ref["seed"], out=c, stats=False, ctx=ctx)
+    assert digest(c) == ref["init"]["sha256"], "initial coloring without statistics"
+    for p, rp_ in enumerate(ref["passes_out"]):
+        gc.recolor(rp, col, c, perm, ref["seed"], p, out=c, stats=False, ctx=ctx)
+        assert digest(c) == rp_["sha256"], f"pass {p} without statistics"
+    ctx.raise_status()
+    ctx.close()

@@ -105,6 +105,34 @@ def test_validate_count_parity(gc):
             assert gc.count_colors(ct) == oracle.count(c)
 
 
+def test_validate_long_rows(gc):
+    """Rows past 4,096 entries are checked as (row, chunk) pairs, one wavefront
+    per chunk; a full chunk list falls back to the 64-row scan.  Counts equal
+    the oracle's (duplicate entries count once per copy)."""
+    rng = np.random.default_rng(3)
+    for g in (gen.star(10000), gen.rmat(14, 16, seed=2), gen.complete(5000)):
+        rp, col = dev(g)
+        base = oracle.greedy_seq(g)
+        for trial in range(3):
+            c = base.copy()
+            idx = rng.integers(0, g.n, 50)
+            c[idx] = rng.integers(-1, 4, 50)
+            if trial == 2:
+                c[:] = 1
+                c[rng.integers(0, g.n, 5)] = 0
+            assert gc.validate(rp, col, torch.from_numpy(c).cuda()) == oracle.validate(g, c), (g.name, trial)
+    # two vertices joined by 20,000 duplicate entries each way, on a context of two vertices:
+    # 6 chunks do not fit the 2-entry chunk list
+    d = torch.device("cuda:0")
+    rp = torch.tensor([0, 20000, 40000], dtype=torch.int32, device=d)
+    col = torch.cat([torch.ones(20000, dtype=torch.int32), torch.zeros(20000, dtype=torch.int32)]).to(d)
+    ctx = gc.Context(2, 40000)
+    assert gc.validate(rp, col, torch.tensor([3, 3], dtype=torch.int32, device=d), ctx=ctx) == (20000, 0)
+    assert gc.validate(rp, col, torch.tensor([3, 4], dtype=torch.int32, device=d), ctx=ctx) == (0, 0)
+    assert gc.validate(rp, col, torch.tensor([0, 4], dtype=torch.int32, device=d), ctx=ctx) == (0, 1)
+    ctx.close()
+
+
 def test_count_large_colors(gc):
     c = np.array([5, 2_000_000_000, 5, 7, -3, 0, 2_000_000_000, 123456789], np.int32)
     assert gc.count_colors(torch.from_numpy(c).cuda()) == oracle.count(c)
@@ -222,6 +250,9 @@ TUNINGS = [
     dict(deg_split=0), dict(deg_wave=4, deg_split=16, split_len=64),
     dict(deg_wave=8, deg_split=64, split_len=64, group=8, xcd_chunks=1),
     dict(deg_wave=4, deg_split=16, split_len=64, hub_words=1),
+    dict(tail_max=-1), dict(tail_max=1 << 30), dict(tail_max=1 << 30, deg_wave=4),
+    dict(walk_flags=1), dict(walk_flags=2), dict(walk_flags=3, deg_wave=4, deg_split=16, split_len=64),
+    dict(compact_init=0), dict(compact_init=0, tail_max=1 << 30),
 ]
 
 
@@ -269,6 +300,9 @@ MANY_CLASS_TUNINGS = [
     dict(group=4, deg_wave=512),
     dict(deg_wave=16, deg_split=128, split_len=64),  # split rows, multi-word hub bitmaps
     dict(deg_wave=16, deg_split=128, split_len=64, hub_words=1),  # ranks >= 64: long rows on one wavefront
+    dict(deg_wave=16, deg_split=128, split_len=64, walk_flags=3),  # split rows first, early merge of sub-chunks
+    dict(deg_wave=16, deg_split=64, split_len=64, walk_flags=2),
+    dict(walk_flags=1),
     dict(walk_mode=1),
 ]
 
@@ -312,6 +346,8 @@ SPLIT_TUNINGS = [
     dict(deg_wave=8, deg_split=64, split_len=64),
     dict(deg_wave=8, deg_split=64, split_len=64, hub_words=1),  # colors above 64: the row is rescanned
     dict(deg_wave=0, deg_split=1, split_len=64, group=1),        # every row of 2+ entries split
+    dict(deg_wave=8, deg_split=64, split_len=64, walk_flags=3),  # split rows first, early merge
+    dict(deg_wave=0, deg_split=1, split_len=64, group=1, walk_flags=2),
 ]
 
 
@@ -435,3 +471,57 @@ def test_recolor_unaligned_col(gc, name):
         c, _ = gc.recolor(rp, col, c, perm, 5, p, out=c)
         ref = oracle.recolor(g, ref, perm, 5, p).colors
         assert np.array_equal(c.cpu().numpy(), ref), f"{name} pass {p}"
+
+
+TAIL = [dict(tail_max=-1), dict(tail_max=0), dict(tail_max=1 << 30), dict(tail_max=1 << 30, deg_wave=8),
+        dict(tail_max=1 << 30, deg_split=0), dict(tail_max=50), dict(tail_max=-1, compact_init=0),
+        dict(tail_max=1 << 30, compact_init=0)]
+
+
+@pytest.mark.parametrize("name", ["er", "rmat", "mesh", "star", "complete100", "path", "rgg", "crown"])
+@pytest.mark.parametrize("t", TAIL, ids=str)
+def test_init_tail_rounds(gc, name, t):
+    """The persistent launch that runs the last rounds of the initial coloring
+    (from round 1 with tail_max = 2^30) gives the oracle's colors, rounds,
+    round sizes and degree sums, for every selection and conflict priority."""
+    g = GRAPHS[name]()
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(**t)
+    for sel, X, flags in ((gc.FIRST_FIT, 1, 0), (gc.RANDOM_X, 4, 0), (gc.RANDOM_X, 3, gc.FLAG_FIXED_PRIORITY),
+                          (gc.FIRST_FIT, 1, gc.FLAG_PRIO_LF), (gc.RANDOM_X, 2, gc.FLAG_PRIO_NATURAL)):
+        _init_equal(gc, g, sel, X, 5, flags=flags, ctx=ctx)
+    ctx.close()
+
+
+@pytest.mark.parametrize("max_rounds", [1, 2, 3, 5, 8, 13])
+def test_init_tail_round_cap(gc, max_rounds):
+    """A round cap that falls inside the persistent tail launch stops it there
+    (GC_ERR_NOT_CONVERGED, the same colors and statistics as the oracle)."""
+    g = GRAPHS["complete"]()
+    rp, col = dev(g)
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(tail_max=1 << 30)
+    c, st = gc.init_color(rp, col, gc.FIRST_FIT, 1, 3, max_rounds=max_rounds, ctx=ctx, allow_not_converged=True)
+    ref = oracle.init_color(g, oracle.FIRST_FIT, 1, 3, max_rounds=max_rounds)
+    assert st["status"] == gc.ERR_NOT_CONVERGED and ref.status == oracle.ERR_NOT_CONVERGED
+    got = c.cpu().numpy()
+    assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
+    assert st["rounds"] == ref.stats["rounds"] == max_rounds
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    ctx.close()
+
+
+def test_arc_tail_rounds(gc):
+    """Asynchronous recoloring's rounds (class-rank priorities) through the tail launch."""
+    g = GRAPHS["rmat"]()
+    rp, col = dev(g)
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(tail_max=1 << 30)
+    c, _ = gc.init_color(rp, col, gc.RANDOM_X, 4, 2, ctx=ctx)
+    for p, perm in enumerate((gc.PERM_NONINC, gc.PERM_RANDOM)):
+        ref = oracle.arc_recolor(g, c.cpu().numpy(), perm, 2, p)
+        c, st = gc.arc_recolor(rp, col, c, perm, 2, p, out=c, ctx=ctx)
+        assert np.array_equal(c.cpu().numpy(), ref.colors)
+        assert st["rounds"] == ref.stats["rounds"]
+    ctx.close()
