@@ -148,18 +148,22 @@ typedef struct gc_tuning {
                               return GC_ERR_COLORING otherwise (one validation sweep; synchronizes) */
     int32_t trace;         /* 1 = the persistent walk records when each class finishes (profiling aid, see
                               gc_ctx_get_trace; device atomics per wavefront and class) */
-    int32_t tail_max;      /* initial coloring: once a round has at most tail_max vertices (0 = 16384) and no
-                              row needs the split kernels, the remaining rounds run in one persistent launch
-                              with grid barriers (no host read-back per round); -1 = never */
+    int32_t tail_max;      /* initial coloring: > 0 = once a round has at most tail_max vertices and no row
+                              needs the split kernels, the remaining rounds run in one persistent launch with
+                              grid barriers (no host read-back per round); 0 (default) or -1 = never (the
+                              per-round launches measured faster on every workload tried) */
     int32_t walk_flags;    /* persistent walk, bit mask: 1 = inside a class, split rows are taken first, then
                               wavefront rows, then group rows; 2 = a split-row sub-chunk still waiting when all
                               the row's other sub-chunks are done takes their mask words and publishes the color
-                              itself */
+                              itself; 4 = a row waits for a pending lower-rank neighbor where its scan meets
+                              it (default: the scan of the whole row goes on, and the pending words are
+                              waited for together at its end) */
     int32_t cu_count;      /* compute units the context's streams may use (0 = all of the device): sizes the
                               grids, and the persistent launches measure their co-resident grid on it; for
                               streams created with a compute-unit mask (as the request server does) */
-    int32_t compact_init;  /* initial coloring: 1 (default) = neighbor colors are read from a one-byte copy when
-                              no color can exceed 127 (longest row + X <= 127); 0 = always from colors */
+    int32_t compact_init;  /* initial coloring: 1 = neighbor colors are read from a one-byte copy when no color
+                              can exceed 127 (longest row + X <= 127); 0 (default) = always from colors (the
+                              copy's extra stores cost more than its narrower gathers saved) */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);
@@ -275,6 +279,24 @@ gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X,
  */
 gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                      const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream);
+
+/*
+ * `passes` recoloring passes in a row (section 3: recoloring iterated, each
+ * pass on the previous one's result): pass p (0-based) is exactly
+ * gc_recolor(ctx, g, perms[p], seed, pass0 + p, ...) with colors_in the
+ * previous pass's colors_out (colors_in itself for p = 0); colors_out ends
+ * with the last pass's colors.  perms (host, passes entries) each in [0, 3];
+ * st (host, NULL or `passes` records) gets each pass's statistics, as
+ * gc_recolor's.  passes = 0 copies colors_in to colors_out.
+ *
+ * The passes are queued on `stream` back to back (one call for a whole
+ * schedule, as the hybrid schedules of gc_schedule_perm give it); with st
+ * NULL nothing synchronizes.  Error behavior as gc_recolor, for the first
+ * pass that fails (later passes are then not queued).
+ */
+gc_status gc_recolor_passes(gc_ctx *ctx, const gc_csr *g, const int32_t *perms, int32_t passes, uint64_t seed,
+                            int32_t pass0, const int32_t *colors_in, int32_t *colors_out, gc_stats *st,
+                            void *stream);
 
 /*
  * gc_recolor for a distance-2 coloring: the same class order, and every

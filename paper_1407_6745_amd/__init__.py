@@ -86,6 +86,9 @@ _SIGS = {
     "gc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
                                   ctypes.c_void_p]),
+    "gc_recolor_passes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(StatsArgs), ctypes.c_void_p]),
     "gc_recolor_d2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
                                      ctypes.c_void_p]),
@@ -380,6 +383,27 @@ def recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=No
                           _stream_ptr(stream))
     ctx.check(rc, "gc_recolor")
     return out, (_stats_dict(st) if st is not None else None)
+
+
+def recolor_passes(row_ptr, col_idx, colors, perms, seed=1, pass0=0, out=None, stats=True,
+                   ctx: Context | None = None, stream=None):
+    """len(perms) recoloring passes in one call (pass p uses perms[p] and pass
+    index pass0 + p); `out` may be `colors`.  Returns (colors, list of stats
+    dicts or None)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    _check_i32_dev(colors, "colors", g.n)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty_like(colors)
+    _check_i32_dev(out, "out", g.n)
+    pa = (ctypes.c_int32 * max(len(perms), 1))(*[int(p) for p in perms])
+    st = (StatsArgs * max(len(perms), 1))() if stats else None
+    rc = lib().gc_recolor_passes(ctx.handle, ctypes.byref(g), pa, len(perms), seed, pass0,
+                                 colors.data_ptr() if g.n else None, out.data_ptr() if g.n else None,
+                                 st, _stream_ptr(stream))
+    ctx.check(rc, "gc_recolor_passes")
+    return out, ([_stats_dict(st[i]) for i in range(len(perms))] if st is not None else None)
 
 
 def recolor_d2(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,

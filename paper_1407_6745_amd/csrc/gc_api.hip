@@ -85,7 +85,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.walk_group = 0;
     ctx->tune.d2_star = 0;
     ctx->tune.walk_flags = 0;
-    ctx->tune.compact_init = 1;
+    ctx->tune.compact_init = 0;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -258,7 +258,7 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->check_input < 0 || t->check_input > 1) return gc_fail(ctx, GC_ERR_ARG, "check_input must be 0 or 1");
     if (t->trace < 0 || t->trace > 1) return gc_fail(ctx, GC_ERR_ARG, "trace must be 0 or 1");
     if (t->tail_max < -1) return gc_fail(ctx, GC_ERR_ARG, "tail_max must be >= -1");
-    if (t->walk_flags < 0 || t->walk_flags > 3) return gc_fail(ctx, GC_ERR_ARG, "walk_flags must be in [0, 3]");
+    if (t->walk_flags < 0 || t->walk_flags > 7) return gc_fail(ctx, GC_ERR_ARG, "walk_flags must be in [0, 7]");
     if (t->cu_count < 0) return gc_fail(ctx, GC_ERR_ARG, "cu_count must be >= 0");
     if (t->compact_init < 0 || t->compact_init > 1) return gc_fail(ctx, GC_ERR_ARG, "compact_init must be 0 or 1");
     const int cus = t->cu_count > 0 && t->cu_count < ctx->dev_cu ? t->cu_count : ctx->dev_cu;

@@ -38,9 +38,9 @@ __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, 
 // Does v (tentative color tv, priority pv) lose against a neighbor?  Group of
 // G lanes, result uniform over the group.  ROUND0: neighbor colors come from
 // the hash; otherwise |C[w]|.
-template <int G, bool ROUND0, int UNR = GC_UNROLL, typename T = int32_t>
+template <int G, bool ROUND0, int UNR = GC_UNROLL, typename CA = const int32_t *>
 __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ col,
-                                   const T *C, int32_t n, const Prio &pr, uint32_t s_color, uint32_t X,
+                                   CA C, int32_t n, const Prio &pr, uint32_t s_color, uint32_t X,
                                    bool randx) {
     const int l = __lane_id() & (G - 1);
     bool lose = false;
@@ -76,9 +76,9 @@ __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t 
 // reservation per batch: *cursor (wavefront-private, len == NULL) or an
 // atomic add on *len (several wavefronts append to one list).  EARLY stops
 // at the first batch that finds a conflict (no kept entries then).
-template <int UNR, bool EARLY, typename T = int32_t>
+template <int UNR, bool EARLY, typename CA = const int32_t *>
 __device__ inline bool wave_loses_keep(int32_t tv, uint64_t pv, int32_t e0, int32_t e1, const int32_t *__restrict__ src,
-                                       const T *C, int32_t n, const Prio &pr, int32_t *out, int32_t *cursor,
+                                       CA C, int32_t n, const Prio &pr, int32_t *out, int32_t *cursor,
                                        int32_t *len) {
     const int lane = __lane_id();
     bool lose = false;
@@ -161,11 +161,14 @@ __device__ inline void publish_long(const LongMasks &lm, const int32_t *__restri
 
 // (j+1)-th smallest color free in a long row's mask, else past FM_COLORS by a
 // scan of the row (a wavefront per row).
+template <bool COH = false, typename CA = const int32_t *>
 __device__ inline int32_t fm_select(const unsigned long long *__restrict__ m, uint32_t j,
-                                    const int32_t *__restrict__ col, int32_t e0, int32_t e1, const int32_t *C,
+                                    const int32_t *__restrict__ col, int32_t e0, int32_t e1, CA C,
                                     int32_t n) {
     const int lane = __lane_id();
-    const uint64_t word = lane < FM_WORDS ? m[lane] : ~0ull;
+    uint64_t word = ~0ull;
+    if (lane < FM_WORDS)
+        word = COH ? __hip_atomic_load(&m[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : m[lane];
     const uint32_t t = wave_nth_free(word, j);
     if (t) return (int32_t)t;
     const uint32_t freec = (uint32_t)wave_sum_u64((unsigned long long)__popcll(~word));
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
         int32_t t;
         const int32_t li = (G == 64 && lm.idx && v >= 0) ? lm.idx[v] : -1;  // one row per wavefront: uniform
         if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
-        else t = group_select_wide<G, ROW_UNROLL(G), CT>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n,
+        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n,
                                                            j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
@@ -363,7 +366,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
             lose = wave_loses_keep<ROW_UNROLL(G), false>(t, pv, e0, e1, src, C, n, pr, al.next + e0, &kept, nullptr);
             if (__lane_id() == 0) al.len_next[li] = kept;
         } else {
-            lose = group_loses<G, false, ROW_UNROLL(G), CT>(t, pv, e0, e1, src,
+            lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src,
                                                            sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, pr, 0u, 1u,
                                                            false);
         }
@@ -651,6 +654,10 @@ __global__ void k_long_index(const int32_t *__restrict__ rp, int32_t n, int64_t 
 
 #define TAIL_CHECKIN_LIMIT (1u << 14)
 
+__device__ inline int32_t coherent_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Grid barrier over every (resident) workgroup; false when a bounded wait ran
 // out (recorded as a sticky device error; the launch then stops).  Two
 // levels, so that no counter sees more than a few dozen arrivals: workgroup b
@@ -661,18 +668,21 @@ __global__ void k_long_index(const int32_t *__restrict__ rp, int32_t n, int64_t 
 #define TAIL_LINE 16  // 64-bit words per 128-byte line
 __device__ inline bool tail_barrier(unsigned long long *T, unsigned long long *bar, uint32_t &gen, uint32_t limit,
                                     unsigned long long *scal, int32_t *lds_flag) {
+    // Everything the workgroups exchange inside the launch is written with
+    // agent-scope atomics and read with agent-scope atomic loads, so the
+    // barrier needs no cache maintenance: each wave waits until its own
+    // stores are done, then the workgroup arrives.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         bool ok = true;
         const uint32_t groups = gridDim.x < TAIL_GROUPS ? gridDim.x : TAIL_GROUPS;
         const uint32_t grp = blockIdx.x % groups;
         const uint32_t gsize = (gridDim.x - grp + groups - 1) / groups;  // workgroups b with b % groups == grp
-        __threadfence();  // this workgroup's writes before the arrival
         if (atomicAdd(&bar[grp * TAIL_LINE], 1ull) == gsize - 1) {
             atomicExch(&bar[grp * TAIL_LINE], 0ull);
             if (atomicAdd(&bar[TAIL_GROUPS * TAIL_LINE], 1ull) == groups - 1) {
                 atomicExch(&bar[TAIL_GROUPS * TAIL_LINE], 0ull);
-                __threadfence();
                 atomicExch(&T[3], (unsigned long long)(gen + 1));
             }
         }
@@ -684,9 +694,8 @@ __device__ inline bool tail_barrier(unsigned long long *T, unsigned long long *b
                 atomicOr(&scal[S_STICKY], 2ull);
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(2);
         }
-        __threadfence();  // the other workgroups' writes after it
         *lds_flag = ok ? 1 : 0;
     }
     gen++;
@@ -768,18 +777,18 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
         // assign: the (j+1)-th color free among the neighbors' committed colors
         const uint32_t sc = gc_stream_value(seed, GC_TAG_COLOR, (uint32_t)R);
         unsigned long long degs = 0;
+        const CoherentColors cc{C};
         for (int64_t i = wave; i < cnt; i += waves) {
-            const int32_t v = i < cnt_a ? A[i] : B[i - cnt_a];
+            const int32_t v = i < cnt_a ? coherent_load(&A[i]) : coherent_load(&B[i - cnt_a]);
             int32_t e0, e1;
             row_range(rp, v, nnz, e0, e1);
             const uint32_t j = randx ? gc_pick(sc, v, X) : 0u;
             const int32_t li = lm.idx ? lm.idx[v] : -1;
             int32_t t;
-            if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
-            else t = group_select_wide<64, UNR, CT>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, j, lw);
+            if (li >= 0) t = fm_select<true>(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, cc, n);
+            else t = group_select_wide<64, UNR>(col, e0, e1, cc, n, j, lw);
             if (lane == 0) {
-                C[v] = -t;
-                compact_put<CT>(S, v, -t);
+                __hip_atomic_store(&C[v], -t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 degs += (unsigned long long)(e1 - e0);
             }
         }
@@ -793,7 +802,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
         pr.s_prio = gc_stream_value(seed, GC_TAG_PRIO, fixed_prio ? 0u : (uint32_t)R);
         int32_t *out = q & 1 ? buf1 : buf0;
         for (int64_t i = wave; i < cnt; i += waves) {
-            const int32_t v = i < cnt_a ? A[i] : B[i - cnt_a];
+            const int32_t v = i < cnt_a ? coherent_load(&A[i]) : coherent_load(&B[i - cnt_a]);
             int32_t e0, e1;
             row_range(rp, v, nnz, e0, e1);
             const int32_t full = e1 - e0;
@@ -806,19 +815,17 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
                     e1 = e0 + min(al.len[li], full);
                 }
             }
-            const int32_t t = -C[v];
+            const int32_t t = -cc[v];
             const int32_t *src = act ? al.cur : col;
-            const bool lose = wave_loses_keep<UNR, true, CT>(t, round_prio(pr, v), e0, e1, src,
-                                                            sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, pr,
-                                                            nullptr, nullptr, nullptr);
+            const bool lose =
+                wave_loses_keep<UNR, true>(t, round_prio(pr, v), e0, e1, src, cc, n, pr, nullptr, nullptr, nullptr);
             if (!lose) {
-                if (lane == 0) {
-                    C[v] = t;
-                    compact_put<CT>(S, v, t);
-                }
+                if (lane == 0) __hip_atomic_store(&C[v], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 publish_long<64>(lm, src, e0, e1, n, t);
             }
-            if (lose && lane == 0) out[atomicAdd(&T[4 + (q & 1)], 1ull)] = v;
+            if (lose && lane == 0)
+                __hip_atomic_store(&out[atomicAdd(&T[4 + (q & 1)], 1ull)], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!tail_barrier(T, bar, gen, limit, scal, &sh[1])) return;
     }
@@ -1023,8 +1030,8 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
     int32_t batch = 0;  // rounds queued since the last read-back
     // Rounds of at most tail_max vertices run in one persistent launch
     // (k_tail_rounds) once no row needs the split kernels.
-    bool tail_on = ctx->tune.tail_max >= 0;
-    const int64_t tail_max = ctx->tune.tail_max > 0 ? ctx->tune.tail_max : 16384;
+    bool tail_on = ctx->tune.tail_max > 0;
+    const int64_t tail_max = ctx->tune.tail_max;
     int tail_per_cu = 0;  // one workgroup per compute unit, when the kernel fits at all
     GC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &tail_per_cu, reinterpret_cast<const void *>(k_tail_rounds<ROW_UNROLL(64), CT>), INIT_BLOCK, 0));

@@ -573,8 +573,19 @@ __device__ inline void bq_flush(int32_t *lbuf, int32_t *lcnt, int32_t *lbase, in
 
 // (j+1)-th smallest positive color absent from {C[w] > 0 : w in row}, by a
 // group of G lanes (group-uniform result).  Colors <= 0 are "no color".
-template <int G, typename T = int32_t>
-__device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const T *C,
+// Colors read by agent-scope atomic loads: values written by other
+// workgroups of the same launch, with no cache maintenance in between.
+struct CoherentColors {
+    const int32_t *p;
+    __device__ int32_t operator[](int64_t i) const {
+        return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// In the helpers below, C is any color accessor: a pointer to int32 or int8
+// colors, or CoherentColors.
+template <int G, typename CA>
+__device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t e0, int32_t e1, CA C,
                                        int32_t n, uint32_t j, uint32_t base = 0) {
     const int l = __lane_id() & (G - 1);
     for (;;) {
@@ -590,7 +601,7 @@ __device__ inline int32_t group_select(const int32_t *__restrict__ col, int32_t 
 #pragma unroll
             for (int u = 0; u < GC_UNROLL; u++) {
                 const bool ok = (uint32_t)w[u] < (uint32_t)n;
-                const int32_t xl = C[ok ? w[u] : 0];
+                const int32_t xl = (int32_t)C[ok ? w[u] : 0];
                 x[u] = ok ? xl : 0;
             }
 #pragma unroll
@@ -658,8 +669,8 @@ __device__ inline uint32_t wave_nth_free(uint64_t word, uint32_t j) {
 // 65 .. 64 * G in the group's LDS words (lw: the wavefront's 64 words, lane L
 // owns lw[L]); colors beyond rescan the row in 64-color windows.  Result
 // uniform over the group.
-template <int G, int UNR = GC_UNROLL, typename T = int32_t>
-__device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int32_t e0, int32_t e1, const T *C,
+template <int G, int UNR = GC_UNROLL, typename CA>
+__device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int32_t e0, int32_t e1, CA C,
                                             int32_t n, uint32_t j, unsigned long long *lw) {
     const int lane = __lane_id();
     const int o = lane & (G - 1);
@@ -679,7 +690,7 @@ __device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
             const bool ok = (uint32_t)w[u] < (uint32_t)n;
-            const int32_t xl = C[ok ? w[u] : 0];
+            const int32_t xl = (int32_t)C[ok ? w[u] : 0];
             x[u] = ok ? xl : 0;
         }
 #pragma unroll
@@ -707,5 +718,5 @@ __device__ inline int32_t group_select_wide(const int32_t *__restrict__ col, int
         return (int32_t)__shfl(r, fl);
     }
     const uint32_t total = __shfl(inc, gfirst + G - 1);
-    return group_select<G, T>(col, e0, e1, C, n, j - total, 64u * G);
+    return group_select<G>(col, e0, e1, C, n, j - total, 64u * G);
 }

@@ -440,6 +440,7 @@ __device__ inline void compact_store(void *S, int32_t v, int32_t color) {
 // walk_flags knob bits
 #define WALK_LONG_FIRST 1u   // inside a rank: split rows, then wavefront rows, then group rows
 #define WALK_EARLY_MERGE 2u  // a waiting split-row sub-chunk takes the others' words once they are all in
+#define WALK_WAIT_IN_PLACE 4u  // a pending word is waited for where the scan meets it (else after the scan)
 
 struct WaitCtl {
     unsigned long long *scal;
@@ -544,6 +545,72 @@ __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t
     for (int u = 0; u < U; u++) mask_mark<WIDE>(xv[u], base, m, lw, gfirst, gw);
 }
 
+// Deferred waits.  A lane's entries whose words were pending (lower rank, not
+// final yet) are remembered as bits of their index j in the lane's share of
+// the range (entry e + j * gsz, j < 64), and settled together after the whole
+// range has been scanned: the scan of the rest of a long row then overlaps
+// the wait instead of following it, so a vertex publishes one round trip
+// after its last lower-rank neighbor, not one per batch of the row left.
+// Batches past index 64 wait in place (absorb).
+template <int U, bool WIDE>
+__device__ inline void absorb_defer(const int32_t *w, int32_t *xv, int32_t s, uint64_t &m, unsigned long long *lw,
+                                    int gfirst, int gw, int32_t *C, const WaitCtl &wc, uint64_t &pm, int j0) {
+    if (j0 + U > 64) {
+        absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gw, C, wc);
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        if (xv[u] < 0) {
+            if (-xv[u] - 1 < s) pm |= 1ull << (j0 + u);
+            xv[u] = 0;  // pending: marked when settled; a rank >= s: no constraint
+        }
+        mask_mark<WIDE>(xv[u], 0u, m, lw, gfirst, gw);
+    }
+}
+
+// Waits (bounded, as absorb) until every deferred entry's word is final and
+// marks its color.  Whole wavefront; e is this lane's first entry.
+template <bool WIDE>
+__device__ inline void settle(uint64_t pm, int32_t e, int gsz, const int32_t *__restrict__ col, uint64_t &m,
+                              unsigned long long *lw, int gfirst, int gw, int32_t *C, const WaitCtl &wc) {
+    for (uint32_t it = 0;; it++) {
+        uint64_t rest = pm;
+        while (__ballot(rest != 0ull)) {
+            // up to four of the lane's entries per sweep, their loads issued together
+            int32_t jj[4], y[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                jj[q] = rest ? __ffsll((long long)rest) - 1 : -1;
+                rest &= rest - 1;
+            }
+            int32_t wq[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) wq[q] = jj[q] >= 0 ? col[e + jj[q] * gsz] : 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                y[q] = jj[q] >= 0 ? __hip_atomic_load(&C[wq[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (jj[q] >= 0 && y[q] > 0) {
+                    mask_mark<WIDE>(y[q], 0u, m, lw, gfirst, gw);
+                    pm &= ~(1ull << jj[q]);
+                }
+        }
+        if (!__ballot(pm != 0ull)) break;
+        if (it >= wc.limit ||
+            ((it & 1023u) == 1023u &&
+             (__hip_atomic_load(&wc.scal[S_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 6ull))) {
+            if (it >= wc.limit) {  // gives up: wrong result, but the kernel ends; the error is sticky
+                atomicOr(&wc.scal[S_ERR], 2ull);
+                atomicOr(&wc.scal[S_STICKY], 2ull);
+            }
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 // Gathers the colors of the neighbor ids w (invalid ids read as 0).
 template <int U>
 __device__ inline void gather(const int32_t *w, int32_t *xv, const int32_t *C, int32_t n) {
@@ -559,8 +626,9 @@ __device__ inline void gather(const int32_t *w, int32_t *xv, const int32_t *C, i
 template <int U, bool WIDE>
 __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t *__restrict__ col, int32_t n,
                                   int32_t s, uint32_t base, uint64_t &m, unsigned long long *lw, int gfirst, int gw,
-                                  int32_t *C, const WaitCtl &wc, HubWait *hw = nullptr) {
-    for (int32_t eb = e; __ballot(eb < e1); eb += U * gsz) {
+                                  int32_t *C, const WaitCtl &wc, HubWait *hw = nullptr, uint64_t *pm = nullptr,
+                                  int j0 = 0) {
+    for (int32_t eb = e; __ballot(eb < e1); eb += U * gsz, j0 += U) {
         int32_t ww[U], xx[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -570,7 +638,8 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
             ww[u] = ok ? wl : -1;
         }
         gather<U>(ww, xx, C, n);
-        absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, wc, hw);
+        if (pm) absorb_defer<U, WIDE>(ww, xx, s, m, lw, gfirst, gw, C, wc, *pm, j0);
+        else absorb<U, WIDE>(ww, xx, s, base, m, lw, gfirst, gw, C, wc, hw);
     }
 }
 
@@ -580,7 +649,7 @@ __device__ inline void scan_range(int32_t e, int32_t e1, int gsz, const int32_t 
 // the group: this lane's word is lw[lane]) for colors 65 .. 64 * (gsz + 1).
 // Colors beyond (a free color is at most the row length + 1) rescan the row
 // in 64-color windows.  The first window takes the prefetched ids w.
-template <int U, bool WIDE, int CT>
+template <int U, bool WIDE, int CT, bool DEFER>
 __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const int32_t *x, int gsz,
                                   const int32_t *__restrict__ col, int32_t n, int32_t *C, void *S,
                                   unsigned long long *lw, const WaitCtl &wc) {
@@ -597,8 +666,13 @@ __device__ inline void finish_row(const WalkChunk &t, const int32_t *w, const in
     int32_t xv[U];
 #pragma unroll
     for (int u = 0; u < U; u++) xv[u] = x[u];
-    absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, wc);
-    scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, wc);
+    const bool defer = DEFER && !(wc.flags & WALK_WAIT_IN_PLACE);
+    uint64_t pm = 0;  // deferred entries of this lane
+    if (defer) absorb_defer<U, WIDE>(w, xv, s, m, lw, gfirst, gsz, C, wc, pm, 0);
+    else absorb<U, WIDE>(w, xv, s, 0u, m, lw, gfirst, gsz, C, wc);
+    scan_range<U, WIDE>(t.e0 + l + U * gsz, t.e1, gsz, col, n, s, 0u, m, lw, gfirst, gsz, C, wc, nullptr,
+                        defer ? &pm : nullptr, U);
+    if (DEFER && __ballot(pm != 0ull)) settle<WIDE>(pm, t.e0 + l, gsz, col, m, lw, gfirst, gsz, C, wc);
     m = group_or_rt(m, gsz);
     uint32_t r = ~m ? (uint32_t)__ffsll((long long)~m) : 0u;
     uint32_t base = 0;
@@ -654,8 +728,13 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
     for (int u = 0; u < U; u++) xv[u] = x[u];
     HubWait hw{hub_cnt + t.slot, bits, t.nsub, words, false};
     HubWait *hwp = (wc.flags & WALK_EARLY_MERGE) ? &hw : nullptr;
-    absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp);
-    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp);
+    const bool defer = !hwp && !(wc.flags & WALK_WAIT_IN_PLACE);
+    uint64_t pm = 0;  // deferred entries of this lane
+    if (defer) absorb_defer<U, true>(w, xv, s, m, lw, 0, HUB_WORDS - 1, C, wc, pm, 0);
+    else absorb<U, true>(w, xv, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp);
+    scan_range<U, true>(t.e0 + lane + U * 64, t.e1, 64, col, n, s, 0u, m, lw, 0, HUB_WORDS - 1, C, wc, hwp,
+                        defer ? &pm : nullptr, U);
+    if (__ballot(pm != 0ull)) settle<true>(pm, t.e0 + lane, 64, col, m, lw, 0, HUB_WORDS - 1, C, wc);
     m = group_or_rt(m, 64);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -821,10 +900,12 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     auto finish = [&](const WalkChunk &t, const int32_t *w, const int32_t *x) {
         const int b = t.seg % NSEG_PER_RANK;
         const int32_t s = t.seg / NSEG_PER_RANK;
-        if (!FULL) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        // (rows under 64 entries, the narrow variant's, span one or two batches:
+        // deferring their waits gains nothing and costs registers)
+        if (!FULL) finish_row<U, false, CT, false>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
         else if (b == 2) finish_split<U, CT>(t, w, x, col, n, C, S, lw, hub_bits, hub_cnt, wc);
-        else if (s < 64) finish_row<U, false, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
-        else finish_row<U, true, CT>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        else if (s < 64) finish_row<U, false, CT, true>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        else finish_row<U, true, CT, true>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
     };
 
     // Software pipeline, one stage per iteration: chunk i+3's vertex and row
@@ -989,7 +1070,10 @@ static int hist_grid_for(const gc_ctx *ctx, int32_t n, int block) {
     return (int)(tiles <= cap ? tiles : cap);
 }
 
-static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
+// Co-resident grid of the walk variant for this graph, measured on its first
+// use.  Runs before a pass's own kernels: the probe clears the error slot,
+// which would otherwise lose what the pass's histogram recorded there.
+static gc_status measure_walk(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
     const int G = gc_walk_group(ctx, full);
     walk_fn f = walk_kernel(G, full);
     const int variant = 2 * G + (full ? 1 : 0);
@@ -1026,6 +1110,19 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
         GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
         ctx->walk_blocks_v[variant] = blocks;
     }
+    return GC_OK;
+}
+
+static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
+    const int G = gc_walk_group(ctx, full);
+    walk_fn f = walk_kernel(G, full);
+    const int variant = 2 * G + (full ? 1 : 0);
+    if (ctx->walk_blocks_v[variant] == 0) return gc_fail(ctx, GC_ERR_DEVICE, "walk grid not measured");
+    const int32_t *col = g->nnz > 0 ? g->col_idx : (const int32_t *)ctx->scal;
+    int32_t *hub_cnt = ctx->hub_cnt ? ctx->hub_cnt : (int32_t *)ctx->scal;
+    unsigned long long *hub_bits = ctx->hub_bits ? ctx->hub_bits : ctx->scal;
+    const int32_t split_len = ctx->tune.split_len;
+    const uint32_t spin_limit = ctx->tune.spin_limit > 0 ? (uint32_t)ctx->tune.spin_limit : SPIN_LIMIT;
     ctx->walk_blocks = ctx->walk_blocks_v[variant];
     // An ordinary stream-ordered launch whose grid is what the device holds at
     // once (measured above): the kernel starts after the previous kernel of the
@@ -1100,6 +1197,10 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
         if (status) return status;
     }
     const int hist_grid = hist_grid_for(ctx, n, block);
+    if (flow) {
+        status = measure_walk(ctx, g, colors_out, full, s);
+        if (status) return status;
+    }
     // max, min, error flags (and the conflict count, which its users clear
     // anyway): 32 aligned bytes, one fill launch
     static_assert(S_MAXC == 2 && S_ERR == 4 && S_CONFLICTS == 5, "scalar slots cleared per pass");
@@ -1256,6 +1357,37 @@ static gc_status gc_arc_recolor_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm,
 extern "C" gc_status gc_recolor(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,
                                 const int32_t *colors_in, int32_t *colors_out, gc_stats *st, void *stream) {
     return gc_report(ctx, gc_recolor_impl(ctx, g, perm, seed, pass, colors_in, colors_out, st, stream));
+}
+
+static gc_status gc_recolor_passes_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *perms, int32_t passes,
+                                        uint64_t seed, int32_t pass0, const int32_t *colors_in, int32_t *colors_out,
+                                        gc_stats *st, void *stream) {
+    gc_status status = gc_check_graph_args(ctx, g);
+    if (status) return status;
+    if (passes < 0 || pass0 < 0 || (int64_t)pass0 + passes > INT32_MAX) return gc_fail(ctx, GC_ERR_ARG, "bad pass range");
+    if (passes > 0 && !perms) return gc_fail(ctx, GC_ERR_ARG, "perms is NULL");
+    for (int32_t p = 0; p < passes; p++)
+        if (perms[p] < 0 || perms[p] > 3) return gc_fail(ctx, GC_ERR_ARG, "perms[%d] must be in [0, 3]", p);
+    if (g->n > 0 && (!colors_in || !colors_out)) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    GC_HIP(hipSetDevice(ctx->device));
+    if (passes == 0) {
+        if (g->n > 0 && colors_out != colors_in)
+            GC_HIP(hipMemcpyAsync(colors_out, colors_in, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s));
+        return GC_OK;
+    }
+    for (int32_t p = 0; p < passes; p++) {
+        status = recolor_pass(ctx, g, perms[p], seed, pass0 + p, p == 0 ? colors_in : colors_out, colors_out,
+                              st ? &st[p] : nullptr, stream, 1);
+        if (status) return status;
+    }
+    return GC_OK;
+}
+
+extern "C" gc_status gc_recolor_passes(gc_ctx *ctx, const gc_csr *g, const int32_t *perms, int32_t passes, uint64_t seed,
+                                       int32_t pass0, const int32_t *colors_in, int32_t *colors_out, gc_stats *st,
+                                       void *stream) {
+    return gc_report(ctx, gc_recolor_passes_impl(ctx, g, perms, passes, seed, pass0, colors_in, colors_out, st, stream));
 }
 
 extern "C" gc_status gc_recolor_d2(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64_t seed, int32_t pass,

@@ -235,3 +235,30 @@ def test_full_size_no_stats_path(gc, name):
         assert digest(c) == rp_["sha256"], f"pass {p} without statistics"
     ctx.raise_status()
     ctx.close()
+
+
+@pytest.mark.parametrize("name", sorted(GOLD["workloads"]))
+def test_full_size_recolor_passes(gc, name):
+    """All of a workload's passes in one gc_recolor_passes call (the
+    benchmark's step), with and without statistics: the oracle's final colors
+    and per-pass color counts."""
+    ref = GOLD["workloads"][name]
+    print(f"[full-size passes] {name}", flush=True)
+    g = eval(ref["graph"])
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(d)
+    col = torch.from_numpy(g.col).to(d)
+    sel = gc.FIRST_FIT if ref["select"] == "FIRST_FIT" else gc.RANDOM_X
+    perms = [PERM[ref["perm"]]] * len(ref["passes_out"])
+    ctx = gc.Context(g.n, g.nnz)
+    c = torch.empty(g.n, dtype=torch.int32, device=d)
+    for stats in (True, False, True):
+        gc.init_color(rp, col, sel, ref["X"], ref["seed"], out=c, stats=False, ctx=ctx)
+        c, st = gc.recolor_passes(rp, col, c, perms, ref["seed"], 0, out=c, stats=stats, ctx=ctx)
+        ctx.raise_status()
+        assert digest(c) == ref["passes_out"][-1]["sha256"], f"stats={stats}: differs from the oracle"
+        if stats:
+            assert [s["num_colors"] for s in st] == [p["num_colors"] for p in ref["passes_out"]]
+            assert [s["k_classes"] for s in st] == [p["k"] for p in ref["passes_out"]]
+    assert gc.validate(rp, col, c, ctx=ctx) == (0, 0)
+    ctx.close()

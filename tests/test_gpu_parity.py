@@ -252,7 +252,9 @@ TUNINGS = [
     dict(deg_wave=4, deg_split=16, split_len=64, hub_words=1),
     dict(tail_max=-1), dict(tail_max=1 << 30), dict(tail_max=1 << 30, deg_wave=4),
     dict(walk_flags=1), dict(walk_flags=2), dict(walk_flags=3, deg_wave=4, deg_split=16, split_len=64),
-    dict(compact_init=0), dict(compact_init=0, tail_max=1 << 30),
+    dict(walk_flags=4), dict(walk_flags=4, deg_wave=4, deg_split=16, split_len=64),
+    dict(deg_wave=1024, walk_group=2, deg_split=0),  # 512 entries per lane: late batches wait in place
+    dict(compact_init=1), dict(compact_init=1, tail_max=1 << 30),
 ]
 
 
@@ -303,6 +305,8 @@ MANY_CLASS_TUNINGS = [
     dict(deg_wave=16, deg_split=128, split_len=64, walk_flags=3),  # split rows first, early merge of sub-chunks
     dict(deg_wave=16, deg_split=64, split_len=64, walk_flags=2),
     dict(walk_flags=1),
+    dict(walk_flags=4),
+    dict(deg_wave=16, deg_split=128, split_len=64, walk_flags=4),
     dict(walk_mode=1),
 ]
 
@@ -348,6 +352,7 @@ SPLIT_TUNINGS = [
     dict(deg_wave=0, deg_split=1, split_len=64, group=1),        # every row of 2+ entries split
     dict(deg_wave=8, deg_split=64, split_len=64, walk_flags=3),  # split rows first, early merge
     dict(deg_wave=0, deg_split=1, split_len=64, group=1, walk_flags=2),
+    dict(deg_wave=8, deg_split=64, split_len=64, walk_flags=4),
 ]
 
 
@@ -474,8 +479,8 @@ def test_recolor_unaligned_col(gc, name):
 
 
 TAIL = [dict(tail_max=-1), dict(tail_max=0), dict(tail_max=1 << 30), dict(tail_max=1 << 30, deg_wave=8),
-        dict(tail_max=1 << 30, deg_split=0), dict(tail_max=50), dict(tail_max=-1, compact_init=0),
-        dict(tail_max=1 << 30, compact_init=0)]
+        dict(tail_max=1 << 30, deg_split=0), dict(tail_max=50), dict(tail_max=16384), dict(tail_max=-1, compact_init=1),
+        dict(tail_max=1 << 30, compact_init=1)]
 
 
 @pytest.mark.parametrize("name", ["er", "rmat", "mesh", "star", "complete100", "path", "rgg", "crown"])
