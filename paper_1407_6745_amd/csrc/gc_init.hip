@@ -482,14 +482,16 @@ __device__ inline SplitChunk split_chunk(int32_t c, int32_t nrow, int32_t nch, c
 }
 
 // Counts a finished chunk of slot; true (wavefront-uniform) for the last one.
+// What the chunks exchange through the slot is written and read with device
+// atomics only, so no cache maintenance is needed: the wavefront waits until
+// its own atomics on the slot are done before counting itself, and the last
+// chunk reads the slot after its count came back.
 __device__ inline bool split_last(int32_t *hub_cnt, int32_t slot, int32_t nsub) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     int32_t done = 0;
     if (__lane_id() == 0) done = atomicAdd(&hub_cnt[slot], 1) + 1;
     done = __shfl(done, 0);
-    if (done != nsub) return false;
-    __threadfence();
-    return true;
+    return done == nsub;
 }
 
 // Assign step for long rows (rounds >= 1): committed neighbor colors 1..64

@@ -515,8 +515,8 @@ __device__ inline void absorb(const int32_t *w, int32_t *xv, int32_t s, uint32_t
                 if (__lane_id() == 0) done = __hip_atomic_load(hw->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 done = __shfl(done, 0);
                 if (done == hw->nsub - 1) {
-                    // each other sub-chunk ORed its words and fenced before counting itself
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    // each other sub-chunk's ORs were done before it counted itself;
+                    // the words are read with device atomics
                     const int lane = __lane_id();
                     const uint64_t b =
                         lane < hw->words ? __hip_atomic_load(&hw->bits[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -762,13 +762,14 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
         return;
     }
     if (lane < words && mine) atomicOr(&bits[lane], mine);
-    __threadfence();
+    // the slot is exchanged through device atomics only: wait until this
+    // wavefront's ORs are done, then count it in (no cache maintenance)
+    __builtin_amdgcn_s_waitcnt(0);
     int32_t done = 0;
     if (lane == 0) done = atomicAdd(&hub_cnt[t.slot], 1) + 1;
     done = __shfl(done, 0);
     if (done == t.nsub) {
-        __threadfence();
-        // every sub-chunk's bits are in: first free color of the row
+        // every sub-chunk's bits are in (read atomically below): first free color of the row
         const uint64_t word = lane < words ? atomicOr(&bits[lane], 0ull) : ~0ull;
         const uint64_t fr = __ballot(~word != 0ull);
         uint32_t r = 64u * (uint32_t)words + 1u;  // unreachable: at most s colors are taken
