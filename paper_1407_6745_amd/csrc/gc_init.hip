@@ -25,7 +25,7 @@
 #include <vector>
 
 #define INIT_BLOCK 256
-#define GC_RUN_AHEAD 4  // rounds queued per host read-back when no launch needs one
+#define GC_RUN_AHEAD 8  // rounds queued per host read-back when no launch needs one
 static_assert(S_REC + 2 * GC_RUN_AHEAD <= S_COUNT, "round records");
 // loads in flight per lane: whole-wavefront rows are long, so they keep more
 #define ROW_UNROLL(G) ((G) >= 32 ? 16 : GC_UNROLL)
@@ -1021,14 +1021,15 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
     // the threshold; lists only shrink, so once a round plans no split row the
     // later rounds skip the split kernels.
     bool split_live = split, planned = split;
-    // Without split rows and active lists no launch of a round depends on a
+    // Once no row needs the split kernels, no launch of a round depends on a
     // value the host must read: the kernels take the worklist counts from the
-    // device, each bin's list only shrinks (so the last counts read bound the
-    // grids), and a round whose list is empty does nothing.  The host then
-    // queues up to GC_RUN_AHEAD rounds per read-back; every queued round
-    // after the first records its input size and the previous round's degree
-    // sum in scal[S_REC + 2q ..], so the statistics stay exact.
-    const bool ahead = !split && !lists;
+    // device, each bin's list only shrinks (a vertex keeps its bin, so the
+    // last counts read bound the grids, and a bin read empty stays empty), a
+    // round whose list is empty does nothing, and the active lists swap
+    // buffers every round that has long rows.  The host then queues up to
+    // GC_RUN_AHEAD rounds per read-back; every queued round after the first
+    // records its input size and the previous round's degree sum in
+    // scal[S_REC + 2q ..], so the statistics stay exact.
     int32_t batch = 0;  // rounds queued since the last read-back
     // Rounds of at most tail_max vertices run in one persistent launch
     // (k_tail_rounds) once no row needs the split kernels.
@@ -1096,7 +1097,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
         }
         sizes.push_back(tot);
         batch = 1;
-        if (ahead) {
+        if (!split_live) {
             batch = GC_RUN_AHEAD;
             if (max_rounds > 0 && max_rounds - r < batch) batch = max_rounds - r;
         }

@@ -45,7 +45,7 @@ enum {
     S_WL = 16,       // initial coloring: 4 worklist counts + two degree-sum slots (16..21)
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
-    S_REC = 26,      // rounds queued ahead (26..33): input size, previous round's degree sum
+    S_REC = 46,      // rounds queued ahead (46..61): input size, previous round's degree sum
     S_VLONG = 35,    // validation: (row, chunk) pairs of long rows listed
     S_TAIL = 36,     // initial coloring's persistent tail launch (36..45): check-in, decision, barrier count and
                      // generation, two list counts, two degree sums, rounds run, status

@@ -187,6 +187,53 @@ def test_round_cap_at_every_queue_position(gc, max_rounds):
     assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
 
 
+def _cap_equal(gc, g, max_rounds, ctx=None):
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, gc.FIRST_FIT, 1, 4, max_rounds=max_rounds, allow_not_converged=True, ctx=ctx)
+    ref = oracle.init_color(g, oracle.FIRST_FIT, 1, 4, max_rounds=max_rounds)
+    assert st["status"] == ref.status
+    assert st["rounds"] == ref.stats["rounds"]
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    got = c.cpu().numpy()
+    assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
+
+
+@pytest.mark.parametrize("max_rounds", list(range(1, 20)) + [150, 151, 152, 153, 154, 155, 156, 157, 298, 299, 300, 301])
+def test_round_cap_queued_with_lists(gc, max_rounds):
+    """K_300: every row is long (masks and active lists, no split rows), and
+    rounds are queued per read-back; a cap anywhere in a queue, and the
+    natural end (300 rounds), match the oracle."""
+    _cap_equal(gc, gen.complete(300), max_rounds)
+
+
+@pytest.mark.parametrize("max_rounds", list(range(228, 252)) + [1, 2, 3])
+def test_round_cap_split_then_queued(gc, max_rounds):
+    """K_300 with rows split at 64 entries: the split path runs round by round
+    until the rows' active lists fall under the threshold, then rounds are
+    queued; caps around that switch match the oracle."""
+    g = gen.complete(300)
+    ctx = gc.Context(g.n, g.nnz)
+    ctx.set_tuning(deg_wave=32, deg_split=64, split_len=64)
+    _cap_equal(gc, g, max_rounds, ctx)
+    ctx.close()
+
+
+@pytest.mark.parametrize("extra", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
+def test_queued_rounds_end_anywhere_lists(gc, extra):
+    """An RMAT graph with long rows (masks and lists): caps from the round
+    count R to R + 9 all converge with the oracle's colors and statistics."""
+    g = gen.rmat(12, 16, seed=5)
+    ref = oracle.init_color(g, oracle.RANDOM_X, 4, 9)
+    R = ref.stats["rounds"]
+    rp, col = dev(g)
+    c, st = gc.init_color(rp, col, gc.RANDOM_X, 4, 9, max_rounds=R + extra)
+    assert st["rounds"] == R
+    assert st["round_sizes"] == ref.w_sizes.tolist()
+    assert st["round_degsum"] == ref.w_degsum.tolist()
+    assert np.array_equal(c.cpu().numpy(), ref.colors)
+
+
 @pytest.mark.parametrize("extra", [0, 1, 2, 3, 4, 5])
 def test_queued_rounds_end_anywhere(gc, extra):
     """The coloring ends at every offset inside a queue of rounds: caps from
