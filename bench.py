@@ -51,7 +51,9 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_traffic_k_walk_flow_mesh27_128.txt")
+# committed rocprofv3 counter summaries of the walk, per workload
+TRAFFIC_RECORDS = {"mesh128": os.path.join(ROOT, "profiles", "pmc_traffic_k_walk_flow_mesh27_128.txt"),
+                   "rmat22": os.path.join(ROOT, "profiles", "pmc_traffic_k_walk_flow_rmat22.txt")}
 
 
 def recorded_traffic(workload, tuning):
@@ -60,8 +62,10 @@ def recorded_traffic(workload, tuning):
     now (different workload, tuning or kernel source)."""
     import hashlib
 
+    if workload not in TRAFFIC_RECORDS:
+        return None
     try:
-        rec = dict(line.split(": ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
+        rec = dict(line.split(": ", 1) for line in open(TRAFFIC_RECORDS[workload]).read().splitlines()
                    if ": " in line and not line.startswith("#"))
     except OSError:
         return None
@@ -134,7 +138,8 @@ def cpu_baseline(g, select, X, perms, passes, seed, method="rc", budget_s=20.0, 
                 c = recolor(g, c, perms[p], seed, p).colors
                 t_pass.append(time.perf_counter() - t0)
                 if r == 0 and p + 1 < k and time.perf_counter() - t_start > budget_s / repeats:
-                    k = p + 1
+                    k = p + 1  # the budget is spent: later repetitions time these k passes
+                    break
             runs.append((t_init, t_pass))
             if r == 0 and time.perf_counter() - t_start > budget_s / repeats:
                 break
