@@ -161,9 +161,16 @@ typedef struct gc_tuning {
     int32_t cu_count;      /* compute units the context's streams may use (0 = all of the device): sizes the
                               grids, and the persistent launches measure their co-resident grid on it; for
                               streams created with a compute-unit mask (as the request server does) */
-    int32_t compact_init;  /* initial coloring: 1 = neighbor colors are read from a one-byte copy when no color
-                              can exceed 127 (longest row + X <= 127); 0 (default) = always from colors (the
-                              copy's extra stores cost more than its narrower gathers saved) */
+    int32_t compact_init;  /* initial coloring: neighbor colors read from a compact copy of the colors, one byte
+                              when no color can exceed 127 (longest row + X <= 127), else two bytes saturated at
+                              compact_sat; 1 = always, 0 = never (read the int32 colors), -1 (default) = the
+                              one-byte copy when it fits and more than half of the adjacency entries (u, w) have
+                              |u - w| >= 32768 (neighbors far apart in the vertex order, where the narrower copy
+                              keeps more of the colors in the L2; with near neighbors its extra stores cost more
+                              than it saves) */
+    int32_t compact_sat;   /* two-byte copy: words saturate at +-compact_sat (1..32767, 0 = 32767), and a
+                              saturated word is read from the colors instead; a small value only serves to test
+                              that path */
 } gc_tuning;
 
 const char *gc_status_string(gc_status s);

@@ -53,11 +53,11 @@ class Tuning(ctypes.Structure):
                 ("d2_star", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32), ("batch_order", ctypes.c_int32),
                 ("spin_limit", ctypes.c_int32), ("check_input", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("tail_max", ctypes.c_int32), ("walk_flags", ctypes.c_int32), ("cu_count", ctypes.c_int32),
-                ("compact_init", ctypes.c_int32)]
+                ("compact_init", ctypes.c_int32), ("compact_sat", ctypes.c_int32)]
 
 TUNING_FIELDS = ("block", "deg_wave", "group", "grid_per_cu", "walk_mode", "xcd_chunks", "check_resident", "deg_split",
                  "split_len", "hub_words", "walk_group", "d2_star", "batch_wg_per_cu", "batch_order", "spin_limit",
-                 "check_input", "trace", "tail_max", "walk_flags", "cu_count", "compact_init")
+                 "check_input", "trace", "tail_max", "walk_flags", "cu_count", "compact_init", "compact_sat")
 
 
 class BatchArgs(ctypes.Structure):

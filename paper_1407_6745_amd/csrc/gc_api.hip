@@ -85,7 +85,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.walk_group = 0;
     ctx->tune.d2_star = 0;
     ctx->tune.walk_flags = 0;
-    ctx->tune.compact_init = 0;
+    ctx->tune.compact_init = -1;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) { free(ctx); return GC_ERR_DEVICE; }
     hipDeviceProp_t prop;
@@ -260,7 +260,8 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->tail_max < -1) return gc_fail(ctx, GC_ERR_ARG, "tail_max must be >= -1");
     if (t->walk_flags < 0 || t->walk_flags > 7) return gc_fail(ctx, GC_ERR_ARG, "walk_flags must be in [0, 7]");
     if (t->cu_count < 0) return gc_fail(ctx, GC_ERR_ARG, "cu_count must be >= 0");
-    if (t->compact_init < 0 || t->compact_init > 1) return gc_fail(ctx, GC_ERR_ARG, "compact_init must be 0 or 1");
+    if (t->compact_init < -1 || t->compact_init > 1) return gc_fail(ctx, GC_ERR_ARG, "compact_init must be -1, 0 or 1");
+    if (t->compact_sat < 0 || t->compact_sat > 32767) return gc_fail(ctx, GC_ERR_ARG, "compact_sat must be in [0, 32767]");
     const int cus = t->cu_count > 0 && t->cu_count < ctx->dev_cu ? t->cu_count : ctx->dev_cu;
     if (cus != ctx->num_cu) {
         // launch sizes follow the compute units; the persistent walk's grid is measured again
@@ -821,8 +822,30 @@ __global__ void k_max_degree(const int32_t *__restrict__ rp, int32_t n, int64_t 
     if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXDEG], bm);
 }
 
-// Longest row of g, computed once per graph (keyed by its arrays and sizes;
-// it only picks the walk variant, every variant colors any graph correctly).
+// Far entries (|u - w| >= GC_NEAR): a wavefront per 64 rows, their entries
+// spread over the lanes in 64-entry steps per row.
+__global__ void __launch_bounds__(256) k_far_entries(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     int32_t n, int64_t nnz, unsigned long long *scal) {
+    __shared__ unsigned long long lds[16];
+    unsigned long long far = 0;
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = wave; u < n; u += waves) {
+        int32_t e0, e1;
+        row_range(rp, (int32_t)u, nnz, e0, e1);
+        for (int32_t e = e0 + lane; e < e1; e += 64) {
+            const int64_t d = (int64_t)col[e] - u;
+            far += (d >= GC_NEAR || d <= -GC_NEAR) ? 1ull : 0ull;
+        }
+    }
+    far = block_sum_u64(far, lds);
+    if (threadIdx.x == 0 && far) atomicAdd(&scal[S_FAR], far);
+}
+
+// Longest row of g and the fraction of far entries, computed once per graph
+// (keyed by its arrays and sizes; they only pick kernel variants, every
+// variant colors any graph correctly).
 gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out) {
     if (ctx->deg_key_rp == g->row_ptr && ctx->deg_key_col == g->col_idx && ctx->deg_key_n == g->n &&
         ctx->deg_key_nnz == g->nnz) {
@@ -830,17 +853,31 @@ gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32
         return GC_OK;
     }
     GC_HIP(hipMemsetAsync(ctx->scal + S_MAXDEG, 0, 8, s));
+    GC_HIP(hipMemsetAsync(ctx->scal + S_FAR, 0, 8, s));
     const int grid = gc_grid(ctx, g->n, 256) < 2 * ctx->num_cu ? gc_grid(ctx, g->n, 256) : 2 * ctx->num_cu;
     k_max_degree<<<grid, 256, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
     GC_LAUNCHED();
+    if (g->nnz > 0) {
+        k_far_entries<<<4 * ctx->num_cu, 256, 0, s>>>(g->row_ptr, g->col_idx, g->n, g->nnz, ctx->scal);
+        GC_LAUNCHED();
+    }
     gc_status st = gc_sync_scalars(ctx, s);
     if (st) return st;
     ctx->deg_max = (int32_t)ctx->hscal[S_MAXDEG];
+    ctx->deg_far = g->nnz > 0 ? (double)ctx->hscal[S_FAR] / (double)g->nnz : 0.0;
     ctx->deg_key_rp = g->row_ptr;
     ctx->deg_key_col = g->col_idx;
     ctx->deg_key_n = g->n;
     ctx->deg_key_nnz = g->nnz;
     *out = ctx->deg_max;
+    return GC_OK;
+}
+
+gc_status gc_graph_far_fraction(gc_ctx *ctx, const gc_csr *g, hipStream_t s, double *out) {
+    int32_t maxdeg = 0;
+    gc_status st = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (st) return st;
+    *out = ctx->deg_far;
     return GC_OK;
 }
 

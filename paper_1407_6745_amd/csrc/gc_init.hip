@@ -215,17 +215,67 @@ __device__ inline void queues_flush(InitQueues &q, int32_t *wl_lo, unsigned long
 // second queue (they get their own launch, one wavefront each); over a list,
 // rows longer than skip_len are left to the split kernels.  Writes
 // C[v] = +T (kept) or -T (lost) and appends losers by bin.
-// Compact copy of the colors for the neighbor reads of the rounds (T = int8_t,
-// when every color the coloring can take fits: the longest row plus X is at
-// most 127), written beside C at every change; T = int32_t: C itself.
+// Compact copy of the colors for the neighbor reads of the rounds, written
+// beside C at every change.  CT = int8_t when every color the coloring can
+// take fits (the longest row plus X is at most 127); CT = int16_t otherwise,
+// saturated at +-C16_SAT (a saturated word sends the reader to C, which
+// stays exact); CT = int32_t: no copy, C itself.  Half or a quarter of the
+// bytes keep more of the colors in the L2 for graphs whose neighbors lie far
+// apart in the vertex order.
+// The two-byte copy saturates at +-sat (the compact_sat knob, 32767 by
+// default; tests lower it to reach the saturated path on small graphs).
 template <typename CT>
-__device__ inline void compact_put(CT *S, int32_t v, int32_t x) {
-    if (sizeof(CT) < sizeof(int32_t)) S[v] = (CT)x;
+struct CompactCopy {
+    CT *p;
+    int32_t sat;
+    __device__ void put(int32_t v, int32_t x) const {
+        if (sizeof(CT) == 1) p[v] = (CT)x;
+        if (sizeof(CT) == 2) p[v] = (CT)(x > sat ? sat : (x < -sat ? -sat : x));
+    }
+};
+
+// The copy as the split-row kernels (not instantiated per copy width) see it:
+// bytes = 0 (no copy), 1 or 2.
+struct CopyRef {
+    void *p;
+    int32_t bytes, sat;
+    __device__ void put(int32_t v, int32_t x) const {
+        if (bytes == 1) ((int8_t *)p)[v] = (int8_t)x;
+        else if (bytes == 2) ((int16_t *)p)[v] = (int16_t)(x > sat ? sat : (x < -sat ? -sat : x));
+    }
+};
+template <typename CT>
+inline CopyRef copy_ref(const CompactCopy<CT> &S) {
+    return CopyRef{(void *)S.p, sizeof(CT) < 4 ? (int32_t)sizeof(CT) : 0, S.sat};
 }
+
+struct Sat16 {
+    const int16_t *s;
+    const int32_t *c;
+    int32_t sat;
+    __device__ int32_t operator[](int64_t i) const {
+        const int32_t x = s[i];
+        return (x == sat || x == -sat) ? c[i] : x;
+    }
+};
+
+// The neighbor-color reader of a kernel instantiated for CT.
+template <typename CT>
+struct CompactRead {
+    using R = const CT *;
+    __device__ static R of(const CompactCopy<CT> &S, const int32_t *C) {
+        return sizeof(CT) < 4 ? S.p : (const CT *)C;
+    }
+};
+template <>
+struct CompactRead<int16_t> {
+    using R = Sat16;
+    __device__ static R of(const CompactCopy<int16_t> &S, const int32_t *C) { return Sat16{S.p, C, S.sat}; }
+};
 
 template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C, CT *S, int32_t deg_wave,
+                                                       int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S, int32_t deg_wave,
                                                        int32_t skip_len, const int32_t *__restrict__ in_list,
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
@@ -254,7 +304,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) {
             C[v] = lose ? -tv : tv;
-            compact_put<CT>(S, v, lose ? -tv : tv);
+            S.put(v, lose ? -tv : tv);
         }
         if (v >= 0 && !forward && !lose) publish_long<G>(lm, col, e0, e1, n, tv);
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
@@ -267,7 +317,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
 // Assign step of round r >= 1: C[v] = -T for every v of the list.
 template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C, CT *S,
+                                                       int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S,
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, uint32_t s_color,
                                                        uint32_t X, int randx, unsigned long long *degsum,
@@ -308,11 +358,11 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
         int32_t t;
         const int32_t li = (G == 64 && lm.idx && v >= 0) ? lm.idx[v] : -1;  // one row per wavefront: uniform
         if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
-        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n,
+        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, CompactRead<CT>::of(S, C), n,
                                                            j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
-            compact_put<CT>(S, v, -t);
+            S.put(v, -t);
             degs += (unsigned long long)(e1 - e0);
         }
     }
@@ -327,7 +377,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
 // the next worklist of their bin.
 template <int G, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       int64_t nnz, int32_t n, int32_t *C, CT *S, int32_t deg_wave,
+                                                       int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S, int32_t deg_wave,
                                                        const int32_t *__restrict__ wl,
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
@@ -363,17 +413,17 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
             // one scan decides the conflict and keeps the entries still uncolored:
             // the row's list for the next round (one wavefront, in order)
             int32_t kept = 0;
-            lose = wave_loses_keep<ROW_UNROLL(G), false>(t, pv, e0, e1, src, C, n, pr, al.next + e0, &kept, nullptr);
+            lose = wave_loses_keep<ROW_UNROLL(G), false>(t, pv, e0, e1, src, CompactRead<CT>::of(S, C), n, pr,
+                                                         al.next + e0, &kept, nullptr);
             if (__lane_id() == 0) al.len_next[li] = kept;
         } else {
-            lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src,
-                                                           sizeof(CT) < 4 ? (const CT *)S : (const CT *)C, n, pr, 0u, 1u,
-                                                           false);
+            lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src, CompactRead<CT>::of(S, C), n, pr, 0u,
+                                                           1u, false);
         }
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !lose) {
             C[v] = t;
-            compact_put<CT>(S, v, t);
+            S.put(v, t);
         }
         if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
         const bool hub = full > deg_wave;  // worklist bins by the full row length
@@ -505,7 +555,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_assign(const int32_t *__re
                                                              const unsigned long long *__restrict__ plan,
                                                              int32_t split_len, int32_t hub_words, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
-                                                             int32_t *hub_cnt, unsigned long long *degsum) {
+                                                             int32_t *hub_cnt, unsigned long long *degsum, CopyRef cr) {
     __shared__ unsigned long long lmask[INIT_BLOCK];
     const ActiveLists al{nullptr, nullptr, nullptr, nullptr, nullptr};  // whole rows (no masks on this path)
     const int lane = __lane_id();
@@ -552,6 +602,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_assign(const int32_t *__re
             if (lane == 0) {
                 atomicExch(&hub_cnt[k.slot], 0);
                 C[k.v] = -(int32_t)t;
+                cr.put(k.v, -(int32_t)t);
                 atomicAdd(degsum, (unsigned long long)(k.e1 - k.e0));
             }
         }
@@ -572,7 +623,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              int32_t split_len, Prio pr, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
                                                              int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
-                                                             ActiveLists al) {
+                                                             ActiveLists al, CopyRef cr) {
     const int lane = __lane_id();
     const int32_t nrow = plan_rows(plan), nch = plan_chunks(plan);
     const int wpb = INIT_BLOCK / 64;
@@ -594,8 +645,13 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
             if (lane == 0) {
                 const bool lost = atomicExch(flag, 0ull) != 0ull;
                 atomicExch(&hub_cnt[k.slot], 0);
-                if (ROUND0) C[k.v] = lost ? -t : t;
-                else if (!lost) C[k.v] = t;
+                if (ROUND0) {
+                    C[k.v] = lost ? -t : t;
+                    cr.put(k.v, lost ? -t : t);
+                } else if (!lost) {
+                    C[k.v] = t;
+                    cr.put(k.v, t);
+                }
                 if (lost) wl_hub[atomicAdd(c_hub, 1ull)] = k.v;
             }
         }
@@ -707,7 +763,7 @@ __device__ inline bool tail_barrier(unsigned long long *T, unsigned long long *b
 
 template <int UNR, typename CT>
 __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n, int32_t *C, CT *S,
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S,
     const int32_t *__restrict__ lo_in, const int32_t *__restrict__ hub_in, const unsigned long long *c_lo_in,
     const unsigned long long *c_hub_in, int32_t *buf0, int32_t *buf1, int32_t r0, int32_t max_rounds, uint64_t seed,
     int fixed_prio, Prio pbase, int randx, uint32_t X, LongMasks lm, ActiveLists al, long long *round_stats,
@@ -842,7 +898,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
 // ---------------------------------------------------------------------------
 
 template <int G, typename CT>
-static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, int32_t deg_wave, int32_t skip_len,
+static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CompactCopy<CT> S, int32_t deg_wave, int32_t skip_len,
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
                           int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx,
@@ -852,7 +908,7 @@ static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 }
 
 template <int G, typename CT>
-static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, const int32_t *wl,
+static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CompactCopy<CT> S, const int32_t *wl,
                           const unsigned long long *wc, uint32_t sc, uint32_t X, int randx, unsigned long long *degsum,
                           int32_t skip_len, LongMasks lm, unsigned long long *zero2, unsigned long long *zero1,
                           unsigned long long *rec, const unsigned long long *rec_in) {
@@ -861,7 +917,7 @@ static void launch_assign(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 }
 
 template <int G, typename CT>
-static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CT *S, int32_t deg_wave, const int32_t *wl,
+static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CompactCopy<CT> S, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                           unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
                           ActiveLists al) {
@@ -886,7 +942,7 @@ static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
 template <typename CT>
 static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
                                int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s,
-                               const int32_t *prank, CT *S) {
+                               const int32_t *prank, CompactCopy<CT> S) {
     gc_status status = GC_OK;
     if (select == GC_FIRST_FIT) X = 1;
     const int randx = select == GC_RANDOM_X ? 1 : 0;
@@ -1007,7 +1063,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
-                                     cnt + 1, al0));
+                                     cnt + 1, al0, copy_ref(S)));
         GC_LAUNCHED();
         if (masks) {
             GC_TIMED(GC_K_ROUND0, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
@@ -1138,7 +1194,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
                 GC_TIMED(GC_K_ASSIGN, s, k_split_assign<<<cap, INIT_BLOCK, 0, s>>>(
                                              g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                              split_len, ctx->tune.hub_words, sc, (uint32_t)X, randx, ctx->hub_bits,
-                                             ctx->hub_cnt, dsum));
+                                             ctx->hub_cnt, dsum, copy_ref(S)));
                 GC_LAUNCHED();
             }
             if (nlo) {
@@ -1156,7 +1212,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
                 GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
                                              g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                              split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
-                                             al));
+                                             al, copy_ref(S)));
                 GC_LAUNCHED();
                 if (masks) {
                     GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
@@ -1193,16 +1249,33 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
 
 gc_status gc_spec_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed, int32_t max_rounds,
                          uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s, const int32_t *prank) {
-    // neighbor reads through a one-byte copy of the colors when no color can
-    // exceed 127: a color is at most the row length plus X
+    // Neighbor reads through a compact copy of the colors: one byte when no
+    // color can exceed 127 (a color is at most the row length plus X), else
+    // two.  compact_init 1: always; -1: the one-byte copy when most adjacency
+    // entries point far away in the vertex order (there the int32 colors'
+    // cache lines are rarely shared by neighbors, and a quarter of the bytes
+    // keeps more of them in the L2: a random graph of 4 M vertices, 8.5 ->
+    // 4.8 ms).  With near neighbors the copy's stores cost more than it
+    // saves (the 27-point mesh), and the two-byte copy measured slower on
+    // RMAT-22 (46.2 against 42.6 ms), so neither is taken by default.
     int32_t maxdeg = 0;
     gc_status status = gc_graph_max_degree(ctx, g, s, &maxdeg);
     if (status) return status;
+    double far = 0.0;
+    status = gc_graph_far_fraction(ctx, g, s, &far);
+    if (status) return status;
     const int32_t xw = select == GC_FIRST_FIT ? 1 : X;
-    if (ctx->tune.compact_init != 0 && (int64_t)maxdeg + xw <= 127)
+    const bool fits8 = (int64_t)maxdeg + xw <= 127;
+    const bool compact = ctx->tune.compact_init == 1 || (ctx->tune.compact_init == -1 && far > 0.5 && fits8);
+    const int32_t sat = ctx->tune.compact_sat > 0 ? ctx->tune.compact_sat : 32767;
+    if (compact && fits8)
         return spec_rounds_t<int8_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank,
-                                     (int8_t *)ctx->shadow);
-    return spec_rounds_t<int32_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank, colors);
+                                     CompactCopy<int8_t>{(int8_t *)ctx->shadow, 127});
+    if (compact)
+        return spec_rounds_t<int16_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank,
+                                      CompactCopy<int16_t>{(int16_t *)ctx->shadow, sat});
+    return spec_rounds_t<int32_t>(ctx, g, select, X, seed, max_rounds, flags, colors, st, s, prank,
+                                  CompactCopy<int32_t>{colors, 0});
 }
 
 static gc_status gc_init_color_impl(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,

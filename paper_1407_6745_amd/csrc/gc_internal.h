@@ -45,6 +45,7 @@ enum {
     S_WL = 16,       // initial coloring: 4 worklist counts + two degree-sum slots (16..21)
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
+    S_FAR = 26,      // adjacency entries (u, w) with |u - w| >= GC_NEAR (locality of a graph)
     S_REC = 46,      // rounds queued ahead (46..61): input size, previous round's degree sum
     S_VLONG = 35,    // validation: (row, chunk) pairs of long rows listed
     S_TAIL = 36,     // initial coloring's persistent tail launch (36..45): check-in, decision, barrier count and
@@ -86,6 +87,7 @@ struct gc_ctx {
     const void *deg_key_rp, *deg_key_col;
     int64_t deg_key_n, deg_key_nnz;
     int32_t deg_max;
+    double deg_far;          // fraction of its entries with |u - w| >= GC_NEAR
     int32_t *rank;           // rank of a color in the class order (ccap + 2)
     int32_t *pi;             // class order (ccap + 2)
     int32_t *off;            // list offsets per (rank, bin) segment (3 * ccap + 4)
@@ -172,6 +174,11 @@ gc_status gc_check_input_coloring(gc_ctx *ctx, const gc_csr *g, const int32_t *c
 // it only picks kernel variants, never results).  Synchronizes the stream on
 // a new graph.
 gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32_t *out);
+// Neighbor ids at least this far from the row's own id count as far: their
+// colors lie outside the int32 window of 256 KB around the row's.
+#define GC_NEAR 32768
+// Fraction of g's adjacency entries that are far (computed with the longest row).
+gc_status gc_graph_far_fraction(gc_ctx *ctx, const gc_csr *g, hipStream_t s, double *out);
 
 // Speculative rounds over every vertex of g (arguments checked, n > 0):
 // prank == NULL gives the initial coloring (hash priorities); a per-vertex

@@ -57,6 +57,23 @@ def _init_equal(gc, g, sel, X, seed, flags=0, ctx=None):
     return c, ref
 
 
+@pytest.mark.parametrize("t", [dict(compact_init=1), dict(compact_init=1, compact_sat=3), dict(compact_init=0)],
+                         ids=str)
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_init_compact_copies(gc, name, t):
+    """The initial coloring through each compact copy of the colors (one
+    byte when the colors fit, else two bytes; a tiny saturation value sends
+    most reads to the int32 colors) and without one: the oracle's colors and
+    round statistics for both selections and the three priority orders."""
+    g = GRAPHS[name]()
+    ctx = gc.Context(max(g.n, 1), max(g.nnz, 1))
+    ctx.set_tuning(**t)
+    for sel, X, flags in ((gc.FIRST_FIT, 1, 0), (gc.RANDOM_X, 5, 0), (gc.RANDOM_X, 2, gc.FLAG_FIXED_PRIORITY),
+                          (gc.FIRST_FIT, 1, gc.FLAG_PRIO_LF), (gc.RANDOM_X, 3, gc.FLAG_PRIO_NATURAL)):
+        _init_equal(gc, g, sel, X, 13, flags=flags, ctx=ctx)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", sorted(GRAPHS))
 def test_init_parity(gc, name):
     g = GRAPHS[name]()
@@ -301,7 +318,8 @@ TUNINGS = [
     dict(walk_flags=1), dict(walk_flags=2), dict(walk_flags=3, deg_wave=4, deg_split=16, split_len=64),
     dict(walk_flags=4), dict(walk_flags=4, deg_wave=4, deg_split=16, split_len=64),
     dict(deg_wave=1024, walk_group=2, deg_split=0),  # 512 entries per lane: late batches wait in place
-    dict(compact_init=1), dict(compact_init=1, tail_max=1 << 30),
+    dict(compact_init=1), dict(compact_init=1, tail_max=1 << 30), dict(compact_init=0),
+    dict(compact_init=1, compact_sat=5), dict(compact_init=1, compact_sat=1, deg_wave=4),
 ]
 
 
@@ -400,6 +418,9 @@ SPLIT_TUNINGS = [
     dict(deg_wave=8, deg_split=64, split_len=64, walk_flags=3),  # split rows first, early merge
     dict(deg_wave=0, deg_split=1, split_len=64, group=1, walk_flags=2),
     dict(deg_wave=8, deg_split=64, split_len=64, walk_flags=4),
+    dict(deg_wave=8, deg_split=64, split_len=64, compact_init=1),  # split rows write the compact copy too
+    dict(deg_wave=8, deg_split=64, split_len=64, compact_init=1, compact_sat=3),
+    dict(deg_wave=0, deg_split=1, split_len=64, group=1, compact_init=1, compact_sat=2),
 ]
 
 
@@ -527,7 +548,7 @@ def test_recolor_unaligned_col(gc, name):
 
 TAIL = [dict(tail_max=-1), dict(tail_max=0), dict(tail_max=1 << 30), dict(tail_max=1 << 30, deg_wave=8),
         dict(tail_max=1 << 30, deg_split=0), dict(tail_max=50), dict(tail_max=16384), dict(tail_max=-1, compact_init=1),
-        dict(tail_max=1 << 30, compact_init=1)]
+        dict(tail_max=1 << 30, compact_init=1), dict(tail_max=1 << 30, compact_init=1, compact_sat=4)]
 
 
 @pytest.mark.parametrize("name", ["er", "rmat", "mesh", "star", "complete100", "path", "rgg", "crown"])
