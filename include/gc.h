@@ -111,7 +111,7 @@ typedef struct gc_stats {
    reported as a device error). */
 typedef struct gc_tuning {
     int32_t block;         /* threads per workgroup of the streaming kernels (64..1024, multiple of 64) */
-    int32_t deg_wave;      /* rows with more than deg_wave entries get a whole wavefront per vertex */
+    int32_t deg_wave;      /* rows with more than deg_wave entries get a whole wavefront per vertex (default 64) */
     int32_t group;         /* lanes per vertex for rows of at most deg_wave entries in the initial coloring
                               (and in the walk when walk_group says so; power of two, 1..64) */
     int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
@@ -131,7 +131,7 @@ typedef struct gc_tuning {
                               across wavefronts; larger colors rescan the row, and recoloring ranks of
                               64 * hub_words and above keep their long rows on one wavefront */
     int32_t walk_group;    /* lanes per vertex in the recoloring walk (power of two, 1..64); 0 = automatic:
-                              8 when every row is shorter than 64 entries, else `group` */
+                              8 when every row is shorter than 64 entries, else 2 */
     int32_t d2_star;       /* distance-2 detect step: 0 = automatic (per-neighborhood marking for rounds
                               of more than n / 8 vertices when no row exceeds 64 entries, else a scan of
                               each vertex's distance-2 neighborhood), 1 = marking in every round, -1 = the

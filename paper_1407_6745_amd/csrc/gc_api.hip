@@ -74,7 +74,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->max_nnz = max_nnz;
     ctx->ccap = (int32_t)(max_n + GC_MAX_X + 64);
     ctx->tune.block = 256;
-    ctx->tune.deg_wave = 256;
+    ctx->tune.deg_wave = 64;
     ctx->tune.group = 4;
     ctx->tune.grid_per_cu = 8;
     ctx->tune.walk_mode = 0;

@@ -200,8 +200,12 @@ gc_status gc_d2_classes(gc_ctx *ctx, const gc_csr *g, int32_t *C, int32_t k, con
 // Lanes per vertex of the recoloring walk: the walk_group knob, or when it is
 // 0, 8 for graphs whose rows are all shorter than 64 entries (full = false)
 // and the group knob otherwise.
+// Automatic: 8 lanes per vertex for graphs whose rows are all under 64
+// entries; 2 in the variant with split rows, whose graphs (skewed degrees)
+// hold many rows of a few entries (more vertices per chunk; rows past
+// deg_wave take a whole wavefront anyway).
 inline int gc_walk_group(const gc_ctx *ctx, bool full) {
-    return ctx->tune.walk_group ? ctx->tune.walk_group : (full ? ctx->tune.group : 8);
+    return ctx->tune.walk_group ? ctx->tune.walk_group : (full ? 2 : 8);
 }
 
 // Mask words of one split row (colors 1 .. 64 * GC_HUB_WORDS).

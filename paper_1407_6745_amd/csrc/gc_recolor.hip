@@ -797,7 +797,9 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
                                           const int32_t *__restrict__ hsub, const int32_t *__restrict__ sbase,
                                           int32_t split_len, unsigned long long *hub_bits, int32_t *hub_cnt,
                                           WaitCtl wc, int32_t xcd, unsigned long long *lw, void *S) {
-    constexpr int U = 32 / G > 4 ? 32 / G : 4;
+    // entries per lane and batch: 32 per group, between 4 and 8 (narrow groups
+    // keep the registers, and so the occupancy, of four-lane groups)
+    constexpr int U = 32 / G > 8 ? 8 : (32 / G > 4 ? 32 / G : 4);
     const int lane = __lane_id();
     const int wpb = WALK_BLOCK / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
