@@ -272,6 +272,21 @@ gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X,
                         int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream);
 
 /*
+ * gc_init_color that also records, for every vertex, the round in which its
+ * color became final (section 2.2's rounds, 0-based: round 0 is the first
+ * speculative round; a vertex commits in the round in which it wins its
+ * conflicts).  vertex_round (device, n, output): the commit round, or -1 for
+ * a vertex still uncolored when max_rounds stopped the coloring.  The
+ * vertices with a commit round >= r are those of W_r, so st->round_sizes[r]
+ * counts them.  A debugging aid, to find where two colorings part: the
+ * colors and statistics are gc_init_color's.  Not available with
+ * GC_FLAG_DISTANCE2 (GC_ERR_ARG); vertex_round NULL with n > 0: GC_ERR_ARG.
+ */
+gc_status gc_init_color_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                               int32_t max_rounds, uint32_t flags, int32_t *colors, int32_t *vertex_round,
+                               gc_stats *st, void *stream);
+
+/*
  * One iterated-greedy recoloring pass (section 2.1, Culberson's Iterated
  * Greedy; section 3, synchronous recoloring RC).  The classes of colors_in
  * are visited in the order `perm` picks; every vertex of the current class

@@ -108,6 +108,8 @@ def _load():
         "orc_check_csr": (ctypes.c_int, [i32, i32p, i32p]),
         "orc_init_color": (ctypes.c_int, [i32, i32p, i32p, i32, i32, u64, i32, u32, i32p,
                                           ctypes.POINTER(Stats), i64p, i64p, i32]),
+        "orc_init_color_rounds": (ctypes.c_int, [i32, i32p, i32p, i32, i32, u64, i32, u32, i32p,
+                                                 ctypes.POINTER(Stats), i64p, i64p, i32, i32p]),
         "orc_class_order": (i32, [i32, i64p, i32, u64, i32, i32p]),
         "orc_recolor": (ctypes.c_int, [i32, i32p, i32p, i32, u64, i32, i32p, i32p, i32p, i32p,
                                        ctypes.POINTER(Stats)]),
@@ -238,6 +240,24 @@ def init_color(g, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0, w_cap=No
         raise RuntimeError(f"orc_init_color: {rc}")
     r = min(st.rounds, cap)
     return InitResult(rc, c[:g.n], st.as_dict(), ws[:r].copy(), wd[:r].copy())
+
+
+def init_color_rounds(g, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0):
+    """init_color, plus the round in which each vertex kept its colour (-1:
+    still uncoloured when max_rounds stopped it).  Returns (InitResult, rounds)."""
+    rp, col = _csr(g)
+    c = np.zeros(max(g.n, 1), np.int32)
+    cr = np.zeros(max(g.n, 1), np.int32)
+    cap = g.n + 2
+    ws = np.zeros(max(cap, 1), np.int64)
+    wd = np.zeros(max(cap, 1), np.int64)
+    st = Stats()
+    rc = _load().orc_init_color_rounds(g.n, _p32(rp), _p32(col), select, X, seed, max_rounds, flags, _p32(c),
+                                       ctypes.byref(st), _p64(ws), _p64(wd), cap, _p32(cr))
+    if rc not in (OK, ERR_NOT_CONVERGED):
+        raise RuntimeError(f"orc_init_color_rounds: {rc}")
+    r = min(st.rounds, cap)
+    return InitResult(rc, c[:g.n], st.as_dict(), ws[:r].copy(), wd[:r].copy()), cr[:g.n].copy()
 
 
 class RecolorResult:

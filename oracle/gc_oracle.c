@@ -245,11 +245,12 @@ static uint64_t init_key(uint32_t flags, uint64_t seed, uint32_t r, const int32_
  * (uniform among the first X permissible colours).
  *
  * w_sizes[r] = |W_r| and w_degsum[r] = sum of degrees over W_r for the first
- * w_cap rounds (either pointer may be NULL).
+ * w_cap rounds (either pointer may be NULL).  commit_round (may be NULL):
+ * for every vertex, the round in which it kept its colour, -1 if none.
  */
-int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel, int32_t X, uint64_t seed,
-                   int32_t max_rounds, uint32_t flags, int32_t *C, orc_stats *st,
-                   int64_t *w_sizes, int64_t *w_degsum, int32_t w_cap) {
+int orc_init_color_rounds(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel, int32_t X, uint64_t seed,
+                          int32_t max_rounds, uint32_t flags, int32_t *C, orc_stats *st,
+                          int64_t *w_sizes, int64_t *w_degsum, int32_t w_cap, int32_t *commit_round) {
     if (n < 0 || (sel != ORC_FIRST_FIT && sel != ORC_RANDOM_X) || (sel == ORC_RANDOM_X && X < 1) || max_rounds < 0)
         return ORC_ERR_ARG;
     if ((flags & ORC_FLAG_PRIO_LF) && (flags & ORC_FLAG_PRIO_NATURAL)) return ORC_ERR_ARG;
@@ -270,6 +271,8 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
     }
     for (int64_t i = 0; i < fcap; i++) forbidden[i] = -1;
     for (int32_t v = 0; v < n; v++) { C[v] = 0; inW[v] = -1; W[v] = v; }
+    if (commit_round)
+        for (int32_t v = 0; v < n; v++) commit_round[v] = -1;
     int64_t stamp = 0, visited = 0;
     int32_t nW = n, r = 0, status = ORC_OK;
     while (nW > 0) {
@@ -314,7 +317,10 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
         for (int32_t i = 0; i < nW; i++) {
             int32_t v = W[i];
             if (lost[i]) L[nL++] = v;
-            else C[v] = T[v];
+            else {
+                C[v] = T[v];
+                if (commit_round) commit_round[v] = r;
+            }
         }
         int32_t *tmp = W; W = L; L = tmp;
         nW = nL;
@@ -327,6 +333,12 @@ int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel
     }
     free(forbidden); free(T); free(inW); free(W); free(L); free(lost);
     return status;
+}
+
+int orc_init_color(int32_t n, const int32_t *rp, const int32_t *col, int32_t sel, int32_t X, uint64_t seed,
+                   int32_t max_rounds, uint32_t flags, int32_t *C, orc_stats *st,
+                   int64_t *w_sizes, int64_t *w_degsum, int32_t w_cap) {
+    return orc_init_color_rounds(n, rp, col, sel, X, seed, max_rounds, flags, C, st, w_sizes, w_degsum, w_cap, NULL);
 }
 
 /* ------------------------------------------------------------------ */

@@ -83,6 +83,9 @@ _SIGS = {
     "gc_init_color": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p,
                                      ctypes.POINTER(StatsArgs), ctypes.c_void_p]),
+    "gc_init_color_rounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.POINTER(StatsArgs), ctypes.c_void_p]),
     "gc_recolor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CSRArgs), ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(StatsArgs),
                                   ctypes.c_void_p]),
@@ -365,6 +368,28 @@ def init_color(row_ptr, col_idx, select=FIRST_FIT, X=1, seed=1, max_rounds=0, fl
     if d is not None:
         d["status"] = rc
     return out, d
+
+
+def init_color_rounds(row_ptr, col_idx, select=FIRST_FIT, X=1, seed=1, max_rounds=0, flags=0, out=None,
+                      ctx: Context | None = None, stream=None, allow_not_converged=False):
+    """Initial coloring that also returns each vertex's commit round (-1:
+    still uncolored).  Returns (colors, rounds int32 tensor, stats dict)."""
+    torch = _torch()
+    g = _csr_args(row_ptr, col_idx)
+    ctx = ctx or default_context(g.n, g.nnz)
+    if out is None:
+        out = torch.empty(max(g.n, 0), dtype=torch.int32, device=row_ptr.device)
+    _check_i32_dev(out, "out", g.n)
+    vr = torch.empty(max(g.n, 0), dtype=torch.int32, device=row_ptr.device)
+    st = StatsArgs()
+    rc = lib().gc_init_color_rounds(ctx.handle, ctypes.byref(g), select, X, seed, max_rounds, flags,
+                                    out.data_ptr() if g.n else None, vr.data_ptr() if g.n else None,
+                                    ctypes.byref(st), _stream_ptr(stream))
+    if not (rc == ERR_NOT_CONVERGED and allow_not_converged):
+        ctx.check(rc, "gc_init_color_rounds")
+    d = _stats_dict(st)
+    d["status"] = rc
+    return out, vr, d
 
 
 def recolor(row_ptr, col_idx, colors, perm=PERM_REVERSE, seed=1, pass_=0, out=None, stats=True,

@@ -249,6 +249,15 @@ inline CopyRef copy_ref(const CompactCopy<CT> &S) {
     return CopyRef{(void *)S.p, sizeof(CT) < 4 ? (int32_t)sizeof(CT) : 0, S.sat};
 }
 
+// Optional per-vertex output: the round in which a vertex's color became final.
+struct RoundOut {
+    int32_t *p;  // NULL: off
+    int32_t r;
+    __device__ void put(int32_t v) const {
+        if (p) p[v] = r;
+    }
+};
+
 struct Sat16 {
     const int16_t *s;
     const int32_t *c;
@@ -280,7 +289,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ in_count,
                                                        int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, Prio pr, uint32_t s_color,
-                                                       uint32_t X, int randx, LongMasks lm) {
+                                                       uint32_t X, int randx, LongMasks lm, RoundOut ro) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = in_list ? (int64_t)*in_count : (int64_t)n;
@@ -305,6 +314,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         if (leader && !forward) {
             C[v] = lose ? -tv : tv;
             S.put(v, lose ? -tv : tv);
+            if (!lose) ro.put(v);
         }
         if (v >= 0 && !forward && !lose) publish_long<G>(lm, col, e0, e1, n, tv);
         bq_push(q.buf[0], &q.cnt[0], leader && !forward && lose && !hub, v);
@@ -382,7 +392,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
                                                        const unsigned long long *__restrict__ wcount, int32_t *wl_lo,
                                                        unsigned long long *c_lo, int32_t *wl_hub,
                                                        unsigned long long *c_hub, Prio pr, int32_t skip_len,
-                                                       LongMasks lm, ActiveLists al) {
+                                                       LongMasks lm, ActiveLists al, RoundOut ro) {
     __shared__ InitQueues q;
     queues_init(q);
     const int64_t cnt = (int64_t)*wcount;
@@ -424,6 +434,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         if (leader && !lose) {
             C[v] = t;
             S.put(v, t);
+            ro.put(v);
         }
         if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
         const bool hub = full > deg_wave;  // worklist bins by the full row length
@@ -623,7 +634,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                                                              int32_t split_len, Prio pr, uint32_t s_color,
                                                              uint32_t X, int randx, unsigned long long *hub_bits,
                                                              int32_t *hub_cnt, int32_t *wl_hub, unsigned long long *c_hub,
-                                                             ActiveLists al, CopyRef cr) {
+                                                             ActiveLists al, CopyRef cr, RoundOut ro) {
     const int lane = __lane_id();
     const int32_t nrow = plan_rows(plan), nch = plan_chunks(plan);
     const int wpb = INIT_BLOCK / 64;
@@ -652,6 +663,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_split_detect(const int32_t *__re
                     C[k.v] = t;
                     cr.put(k.v, t);
                 }
+                if (!lost) ro.put(k.v);
                 if (lost) wl_hub[atomicAdd(c_hub, 1ull)] = k.v;
             }
         }
@@ -767,7 +779,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
     const int32_t *__restrict__ lo_in, const int32_t *__restrict__ hub_in, const unsigned long long *c_lo_in,
     const unsigned long long *c_hub_in, int32_t *buf0, int32_t *buf1, int32_t r0, int32_t max_rounds, uint64_t seed,
     int fixed_prio, Prio pbase, int randx, uint32_t X, LongMasks lm, ActiveLists al, long long *round_stats,
-    unsigned long long *T, unsigned long long *bar, unsigned long long *scal, uint32_t limit) {
+    unsigned long long *T, unsigned long long *bar, unsigned long long *scal, uint32_t limit, int32_t *vround) {
     __shared__ unsigned long long lmask[INIT_BLOCK];
     __shared__ int32_t sh[4];
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
@@ -879,6 +891,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_tail_rounds(
                 wave_loses_keep<UNR, true>(t, round_prio(pr, v), e0, e1, src, cc, n, pr, nullptr, nullptr, nullptr);
             if (!lose) {
                 if (lane == 0) __hip_atomic_store(&C[v], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0 && vround) vround[v] = R;
                 publish_long<64>(lm, src, e0, e1, n, t);
             }
             if (lose && lane == 0)
@@ -902,9 +915,9 @@ static void launch_round0(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
                           const int32_t *in_list,
                           const unsigned long long *in_count, int32_t *wl_lo, unsigned long long *c_lo,
                           int32_t *wl_hub, unsigned long long *c_hub, Prio pr, uint32_t sc, uint32_t X, int randx,
-                          LongMasks lm) {
+                          LongMasks lm, RoundOut ro) {
     k_round0<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, skip_len, in_list, in_count, wl_lo,
-                                            c_lo, wl_hub, c_hub, pr, sc, X, randx, lm);
+                                            c_lo, wl_hub, c_hub, pr, sc, X, randx, lm, ro);
 }
 
 template <int G, typename CT>
@@ -920,9 +933,9 @@ template <int G, typename CT>
 static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, CompactCopy<CT> S, int32_t deg_wave, const int32_t *wl,
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                           unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
-                          ActiveLists al) {
+                          ActiveLists al, RoundOut ro) {
     k_detect<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, pr, skip_len, lm, al);
+                                            c_hub, pr, skip_len, lm, al, ro);
 }
 
 #define GC_DISPATCH_G(G, ...)                                   \
@@ -944,6 +957,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
                                int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, hipStream_t s,
                                const int32_t *prank, CompactCopy<CT> S) {
     gc_status status = GC_OK;
+    int32_t *vround = prank ? nullptr : ctx->vround;  // each vertex's commit round, when asked for
     if (select == GC_FIRST_FIT) X = 1;
     const int randx = select == GC_RANDOM_X ? 1 : 0;
     const int32_t n = g->n;
@@ -1051,10 +1065,10 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
     const uint32_t sc0 = gc_stream_value(seed, GC_TAG_COLOR, 0);
     GC_TIMED(GC_K_ROUND0, s, GC_DISPATCH_G(G, launch_round0<GG, CT>(grid_for(n, GG), s, g, colors, S, deg_wave, skip, nullptr,
                                                                 nullptr, ctx->wl[0], cnt + 0, ctx->wl[3], cnt + 3, sp0,
-                                                                sc0, (uint32_t)X, randx, lm)));
+                                                                sc0, (uint32_t)X, randx, lm, RoundOut{vround, 0})));
     GC_LAUNCHED();
     GC_TIMED(GC_K_ROUND0, s, launch_round0<64, CT>(cap, s, g, colors, S, deg_wave, skip, ctx->wl[3], cnt + 3, ctx->wl[0], cnt + 0,
-                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, lm));
+                                               ctx->wl[1], cnt + 1, sp0, sc0, (uint32_t)X, randx, lm, RoundOut{vround, 0}));
     GC_LAUNCHED();
     if (split) {
         const ActiveLists al0 = lists_of(false);  // round 0 reads whole rows and writes no lists
@@ -1063,7 +1077,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
         GC_TIMED(GC_K_ROUND0, s, k_split_detect<true><<<cap, INIT_BLOCK, 0, s>>>(
                                      g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                      split_len, sp0, sc0, (uint32_t)X, randx, ctx->hub_bits, ctx->hub_cnt, ctx->wl[1],
-                                     cnt + 1, al0, copy_ref(S)));
+                                     cnt + 1, al0, copy_ref(S), RoundOut{vround, 0}));
         GC_LAUNCHED();
         if (masks) {
             GC_TIMED(GC_K_ROUND0, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n, colors,
@@ -1128,7 +1142,7 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
                                          ctx->wl[2 * cur + 1],
                                          cnt + 2 * cur, cnt + 2 * cur + 1, ctx->wl[2 * nxt], ctx->wl[2 * cur], r,
                                          max_rounds, seed, fixed ? 1 : 0, prio_of(0), randx, (uint32_t)X, lm, al,
-                                         (long long *)ctx->round_stats, T, ctx->sync, ctx->scal, limit));
+                                         (long long *)ctx->round_stats, T, ctx->sync, ctx->scal, limit, vround));
             GC_LAUNCHED();
             ss = gc_sync_scalars(ctx, s);
             if (ss) return ss;
@@ -1200,19 +1214,19 @@ static gc_status spec_rounds_t(gc_ctx *ctx, const gc_csr *g, int32_t select, int
             if (nlo) {
                 GC_TIMED(GC_K_DETECT, s, GC_DISPATCH_G(G, launch_detect<GG, CT>(grid_for(nlo, GG), s, g, colors, S, deg_wave, lo_in,
                                                                             c_lo_in, lo_out, c_lo_out, hub_out, c_hub_out,
-                                                                            sp, skip, lm, al)));
+                                                                            sp, skip, lm, al, RoundOut{vround, r})));
                 GC_LAUNCHED();
             }
             if (nhub) {
                 GC_TIMED(GC_K_DETECT, s, launch_detect<64, CT>(grid_for(nhub, 64), s, g, colors, S, deg_wave, hub_in, c_hub_in, lo_out,
-                                                           c_lo_out, hub_out, c_hub_out, sp, skip, lm, al));
+                                                           c_lo_out, hub_out, c_hub_out, sp, skip, lm, al, RoundOut{vround, r}));
                 GC_LAUNCHED();
             }
             if (split_round) {
                 GC_TIMED(GC_K_DETECT, s, k_split_detect<false><<<cap, INIT_BLOCK, 0, s>>>(
                                              g->row_ptr, g->col_idx, g->nnz, n, colors, ctx->hub_v, ctx->hub_first, plan,
                                              split_len, sp, 0u, 1u, 0, ctx->hub_bits, ctx->hub_cnt, hub_out, c_hub_out,
-                                             al, copy_ref(S)));
+                                             al, copy_ref(S), RoundOut{vround, r}));
                 GC_LAUNCHED();
                 if (masks) {
                     GC_TIMED(GC_K_DETECT, s, k_split_publish<<<cap, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, n,
@@ -1314,4 +1328,30 @@ static gc_status gc_init_color_impl(gc_ctx *ctx, const gc_csr *g, int32_t select
 extern "C" gc_status gc_init_color(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
                                    int32_t max_rounds, uint32_t flags, int32_t *colors, gc_stats *st, void *stream) {
     return gc_report(ctx, gc_init_color_impl(ctx, g, select, X, seed, max_rounds, flags, colors, st, stream));
+}
+
+static gc_status gc_init_color_rounds_impl(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                                           int32_t max_rounds, uint32_t flags, int32_t *colors,
+                                           int32_t *vertex_round, gc_stats *st, void *stream) {
+    if (!ctx) return GC_ERR_ARG;
+    gc_status status = gc_check_graph_args(ctx, g);
+    if (status) return status;
+    if (g->n > 0 && !vertex_round) return gc_fail(ctx, GC_ERR_ARG, "vertex_round is NULL");
+    if (flags & GC_FLAG_DISTANCE2)
+        return gc_fail(ctx, GC_ERR_ARG, "commit rounds are not recorded for GC_FLAG_DISTANCE2");
+    if (g->n > 0) {
+        GC_HIP(hipSetDevice(ctx->device));
+        GC_HIP(hipMemsetAsync(vertex_round, 0xFF, (size_t)g->n * 4, (hipStream_t)stream));  // -1: not committed
+    }
+    ctx->vround = vertex_round;
+    status = gc_init_color_impl(ctx, g, select, X, seed, max_rounds, flags, colors, st, stream);
+    ctx->vround = nullptr;
+    return status;
+}
+
+extern "C" gc_status gc_init_color_rounds(gc_ctx *ctx, const gc_csr *g, int32_t select, int32_t X, uint64_t seed,
+                                          int32_t max_rounds, uint32_t flags, int32_t *colors, int32_t *vertex_round,
+                                          gc_stats *st, void *stream) {
+    return gc_report(ctx, gc_init_color_rounds_impl(ctx, g, select, X, seed, max_rounds, flags, colors, vertex_round,
+                                                    st, stream));
 }

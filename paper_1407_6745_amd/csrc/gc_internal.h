@@ -115,6 +115,7 @@ struct gc_ctx {
     unsigned long long sticky;  // device failures harvested from S_STICKY, not yet reported
     unsigned long long *trace;  // class-completion trace of the last persistent walk (tuning.trace), on demand
     unsigned long long *sync;   // grid-barrier counters of the initial coloring's tail launch (GC_SYNC_BYTES)
+    int32_t *vround;            // during gc_init_color_rounds: the caller's per-vertex commit rounds, else NULL
     char err[512];
 };
 

@@ -598,3 +598,40 @@ def test_arc_tail_rounds(gc):
         assert np.array_equal(c.cpu().numpy(), ref.colors)
         assert st["rounds"] == ref.stats["rounds"]
     ctx.close()
+
+
+ROUND_TUNINGS = [dict(), dict(deg_wave=8, deg_split=64, split_len=64), dict(tail_max=1 << 30),
+                 dict(compact_init=1, compact_sat=3), dict(group=1, deg_wave=4)]
+
+
+@pytest.mark.parametrize("t", ROUND_TUNINGS, ids=str)
+@pytest.mark.parametrize("name", ["er", "rmat", "mesh", "star", "complete100", "path", "rgg", "crown", "empty"])
+def test_init_commit_rounds(gc, name, t):
+    """Each vertex's commit round (gc_init_color_rounds) equals the oracle's,
+    vertex by vertex, on every launch path: lane groups, wavefront rows,
+    split rows, the persistent tail and the compact copies; a round cap leaves
+    -1 for the vertices still uncolored."""
+    g = GRAPHS[name]()
+    rp, col = dev(g)
+    ctx = gc.Context(max(g.n, 1), max(g.nnz, 1))
+    ctx.set_tuning(**t)
+    for sel, X, flags, cap in ((gc.FIRST_FIT, 1, 0, 0), (gc.RANDOM_X, 4, 0, 0), (gc.RANDOM_X, 2, gc.FLAG_PRIO_LF, 0),
+                               (gc.FIRST_FIT, 1, gc.FLAG_PRIO_NATURAL, 0), (gc.FIRST_FIT, 1, 0, 2)):
+        c, vr, st = gc.init_color_rounds(rp, col, sel, X, 5, max_rounds=cap, flags=flags, ctx=ctx,
+                                         allow_not_converged=True)
+        ref, cr = oracle.init_color_rounds(g, sel, X, 5, max_rounds=cap, flags=flags)
+        got = c.cpu().numpy()
+        assert np.array_equal(np.where(got > 0, got, 0), ref.colors)
+        assert np.array_equal(vr.cpu().numpy(), cr), f"{name} {t} sel={sel} flags={flags} cap={cap}"
+        assert st["rounds"] == ref.stats["rounds"]
+    ctx.close()
+
+
+def test_init_commit_rounds_args(gc):
+    g = GRAPHS["er"]()
+    rp, col = dev(g)
+    with pytest.raises(gc.GCError):
+        gc.init_color_rounds(rp, col, gc.FIRST_FIT, 1, 1, flags=gc.FLAG_DISTANCE2)
+    c, vr, st = gc.init_color_rounds(rp, col, gc.FIRST_FIT, 1, 1)
+    c2, _ = gc.init_color(rp, col, gc.FIRST_FIT, 1, 1)
+    assert torch.equal(c, c2)

@@ -316,6 +316,38 @@ def test_init_not_converged_cap():
     assert int((r.colors > 0).sum()) == 3
 
 
+@pytest.mark.parametrize("fam", range(len(FAMILIES)))
+def test_init_commit_rounds_consistent(fam):
+    """The per-vertex commit rounds: the same colours as init_color, -1 exactly
+    for uncoloured vertices, and the vertices still uncommitted at the start
+    of round r are the |W_r| of the round statistics."""
+    g = FAMILIES[fam]()
+    for sel, X, flags, cap in ((oracle.FIRST_FIT, 1, 0, 0), (oracle.RANDOM_X, 4, 0, 0),
+                               (oracle.FIRST_FIT, 1, oracle.PRIO_LF, 0), (oracle.RANDOM_X, 3, 0, 2)):
+        ref = oracle.init_color(g, sel, X, 7, max_rounds=cap, flags=flags)
+        r, cr = oracle.init_color_rounds(g, sel, X, 7, max_rounds=cap, flags=flags)
+        assert np.array_equal(r.colors, ref.colors) and np.array_equal(r.w_sizes, ref.w_sizes)
+        assert np.array_equal(cr < 0, ref.colors == 0)
+        for rnd, size in enumerate(ref.w_sizes):
+            assert int(((cr >= rnd) | (cr < 0)).sum()) == size
+
+
+def test_init_commit_rounds_closed_forms():
+    # K_n with First Fit: the vertex committing in round r takes colour r + 1
+    g = gen.complete(11)
+    r, cr = oracle.init_color_rounds(g, oracle.FIRST_FIT, 1, 3)
+    assert np.array_equal(cr, r.colors - 1)
+    # round 0 keeps exactly the local maxima of round 0's keys (First Fit)
+    g = gen.er(400, 1200, 9)
+    _, cr = oracle.init_color_rounds(g, oracle.FIRST_FIT, 1, 17)
+    for v in range(g.n):
+        kv = oracle.key(17, 0, v)
+        assert (cr[v] == 0) == all(oracle.key(17, 0, int(w)) < kv for w in g.neighbors(v))
+    # an edgeless graph commits everything in round 0
+    _, cr = oracle.init_color_rounds(gen.empty(30), oracle.RANDOM_X, 5, 2)
+    assert cr.tolist() == [0] * 30
+
+
 # ---------------------------------------------------------------- recolouring
 
 def test_recolor_golden_p4():
