@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
 // Detect step of round r >= 1: v loses when a neighbor has the same tentative
 // color and a larger priority; winners commit (flip the sign), losers go to
 // the next worklist of their bin.
-template <int G, typename CT>
+template <int G, typename CT, bool RO>
 __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S, int32_t deg_wave,
                                                        const int32_t *__restrict__ wl,
@@ -434,7 +434,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         if (leader && !lose) {
             C[v] = t;
             S.put(v, t);
-            ro.put(v);
+            // (a compile-time switch: the run-time test alone slowed this
+            // kernel by a quarter on the mesh)
+            if (RO) ro.put(v);
         }
         if (v >= 0 && !lose) publish_long<G>(lm, src, e0, e1, n, t);
         const bool hub = full > deg_wave;  // worklist bins by the full row length
@@ -934,8 +936,12 @@ static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                           unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
                           ActiveLists al, RoundOut ro) {
-    k_detect<G, CT><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo, c_lo, wl_hub,
-                                            c_hub, pr, skip_len, lm, al, ro);
+    if (ro.p)
+        k_detect<G, CT, true><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo,
+                                                      c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+    else
+        k_detect<G, CT, false><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo,
+                                                       c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
 }
 
 #define GC_DISPATCH_G(G, ...)                                   \
