@@ -82,7 +82,7 @@ struct gc_ctx {
     int32_t *hub_first;      // initial coloring: per hub slot, its first chunk
     int64_t hub_cap;         // hub slots allocated
     int walk_blocks;         // co-resident workgroups of the last persistent walk launched (0 = none yet)
-    int walk_blocks_v[130];  // measured per walk variant (2 * group + full); 0 = not measured
+    int walk_blocks_v[260];  // measured per walk variant (4 * group + 2 * options + full); 0 = not measured
     // longest row of the last graph seen by the recoloring (keyed by its arrays and sizes)
     const void *deg_key_rp, *deg_key_col;
     int64_t deg_key_n, deg_key_nnz;

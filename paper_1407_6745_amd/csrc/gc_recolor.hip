@@ -972,7 +972,10 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
 // Software pipeline (per wavefront): while chunk i gathers its neighbors'
 // colors (the only loads that depend on earlier classes), chunk i+1's first
 // U neighbor ids and chunk i+2's vertex and row are already being loaded.
-template <int G, bool FULL>
+// OPT: the variant that honours walk_flags and the class-completion trace;
+// the other treats both as off (their run-time tests alone cost the mesh's
+// walk 2.4 %).
+template <int G, bool FULL, bool OPT>
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict__ rows, const int32_t *__restrict__ col,
                                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
                                                           const int32_t *__restrict__ off,
@@ -1008,7 +1011,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
     }
     const int32_t k = (int32_t)scal[S_K];
     const int32_t nseg = NSEG_PER_RANK * k;
-    const WaitCtl wc = {scal, spin_limit, walk_flags, trace};
+    if (!OPT) trace = nullptr;
+    const WaitCtl wc = {scal, spin_limit, OPT ? walk_flags : 0u, trace};
     if (trace && threadIdx.x == 0) atomicMin(&trace[0], wall_clock64());
     if (nseg <= WALK_TAB) {
         // segment tables in LDS: their reads are tracked apart from the vector
@@ -1045,20 +1049,32 @@ typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const
                         const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
                         unsigned long long *, int32_t, int32_t, uint32_t, uint32_t, unsigned long long *, void *);
 
-template <bool FULL>
+template <bool FULL, bool OPT>
 static walk_fn walk_kernel_t(int G) {
     switch (G) {
-        case 1: return k_walk_flow<1, FULL>;
-        case 2: return k_walk_flow<2, FULL>;
-        case 4: return k_walk_flow<4, FULL>;
-        case 8: return k_walk_flow<8, FULL>;
-        case 16: return k_walk_flow<16, FULL>;
-        case 32: return k_walk_flow<32, FULL>;
-        default: return k_walk_flow<64, FULL>;
+        case 1: return k_walk_flow<1, FULL, OPT>;
+        case 2: return k_walk_flow<2, FULL, OPT>;
+        case 4: return k_walk_flow<4, FULL, OPT>;
+        case 8: return k_walk_flow<8, FULL, OPT>;
+        case 16: return k_walk_flow<16, FULL, OPT>;
+        case 32: return k_walk_flow<32, FULL, OPT>;
+        default: return k_walk_flow<64, FULL, OPT>;
     }
 }
 
-static walk_fn walk_kernel(int G, bool full) { return full ? walk_kernel_t<true>(G) : walk_kernel_t<false>(G); }
+static walk_fn walk_kernel(int G, bool full, bool opt) {
+    if (opt) return full ? walk_kernel_t<true, true>(G) : walk_kernel_t<false, true>(G);
+    return full ? walk_kernel_t<true, false>(G) : walk_kernel_t<false, false>(G);
+}
+
+// The walk variant of this context's settings.  The variant with split
+// rows takes the options-free kernel unless walk_flags or the trace ask for
+// them (RMAT-22: 2.71 -> 2.39 ms per walk); the narrow variant keeps the
+// run-time tests (measured the other way round there: 151.6 against 155.0 us
+// on the mesh, the same GPU).
+static bool walk_opt(const gc_ctx *ctx, bool full) {
+    return !full || ctx->tune.walk_flags != 0 || ctx->tune.trace != 0;
+}
 
 // full: the variant with split rows and LDS mask words (rows of 64 or more
 // entries); the narrow one keeps only a 64-color register window (further
@@ -1078,8 +1094,9 @@ static int hist_grid_for(const gc_ctx *ctx, int32_t n, int block) {
 // which would otherwise lose what the pass's histogram recorded there.
 static gc_status measure_walk(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
     const int G = gc_walk_group(ctx, full);
-    walk_fn f = walk_kernel(G, full);
-    const int variant = 2 * G + (full ? 1 : 0);
+    const bool opt = walk_opt(ctx, full);
+    walk_fn f = walk_kernel(G, full, opt);
+    const int variant = 4 * G + (opt ? 2 : 0) + (full ? 1 : 0);
     // the walk reads col[0] unconditionally (masked afterwards): give it one valid word when the graph has no edges
     const int32_t *col = g->nnz > 0 ? g->col_idx : (const int32_t *)ctx->scal;
     // without split rows the hub arrays are never touched
@@ -1118,8 +1135,9 @@ static gc_status measure_walk(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool ful
 
 static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool full, hipStream_t s) {
     const int G = gc_walk_group(ctx, full);
-    walk_fn f = walk_kernel(G, full);
-    const int variant = 2 * G + (full ? 1 : 0);
+    const bool opt = walk_opt(ctx, full);
+    walk_fn f = walk_kernel(G, full, opt);
+    const int variant = 4 * G + (opt ? 2 : 0) + (full ? 1 : 0);
     if (ctx->walk_blocks_v[variant] == 0) return gc_fail(ctx, GC_ERR_DEVICE, "walk grid not measured");
     const int32_t *col = g->nnz > 0 ? g->col_idx : (const int32_t *)ctx->scal;
     int32_t *hub_cnt = ctx->hub_cnt ? ctx->hub_cnt : (int32_t *)ctx->scal;
