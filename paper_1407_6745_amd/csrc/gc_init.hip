@@ -385,7 +385,9 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
 // Detect step of round r >= 1: v loses when a neighbor has the same tentative
 // color and a larger priority; winners commit (flip the sign), losers go to
 // the next worklist of their bin.
-template <int G, typename CT, bool RO>
+// LISTS (G = 64 with active lists): every row is scanned by wave_loses_keep
+// (rows without a list keep nothing), so the kernel holds one scan routine.
+template <int G, typename CT, bool RO, bool LISTS>
 __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        int64_t nnz, int32_t n, int32_t *C, CompactCopy<CT> S, int32_t deg_wave,
                                                        const int32_t *__restrict__ wl,
@@ -419,13 +421,14 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         const int32_t *src = act ? al.cur : col;
         const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
         bool lose;
-        if (G == 64 && al.next && v >= 0 && li >= 0) {
+        if (LISTS) {
             // one scan decides the conflict and keeps the entries still uncolored:
             // the row's list for the next round (one wavefront, in order)
+            const bool keep = v >= 0 && li >= 0;
             int32_t kept = 0;
-            lose = wave_loses_keep<ROW_UNROLL(G), false>(t, pv, e0, e1, src, CompactRead<CT>::of(S, C), n, pr,
-                                                         al.next + e0, &kept, nullptr);
-            if (__lane_id() == 0) al.len_next[li] = kept;
+            lose = wave_loses_keep<ROW_UNROLL(64), false>(t, pv, e0, e1, src, CompactRead<CT>::of(S, C), n, pr,
+                                                          keep ? al.next + e0 : nullptr, &kept, nullptr);
+            if (keep && __lane_id() == 0) al.len_next[li] = kept;
         } else {
             lose = group_loses<G, false, ROW_UNROLL(G)>(t, pv, e0, e1, src, CompactRead<CT>::of(S, C), n, pr, 0u,
                                                            1u, false);
@@ -936,12 +939,21 @@ static void launch_detect(int grid, hipStream_t s, const gc_csr *g, int32_t *C, 
                           const unsigned long long *wc, int32_t *wl_lo, unsigned long long *c_lo, int32_t *wl_hub,
                           unsigned long long *c_hub, Prio pr, int32_t skip_len, LongMasks lm,
                           ActiveLists al, RoundOut ro) {
-    if (ro.p)
-        k_detect<G, CT, true><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo,
-                                                      c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
-    else
-        k_detect<G, CT, false><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl, wc, wl_lo,
-                                                       c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+    constexpr bool L = G == 64;  // the list variants exist for wavefront rows only
+    if (L && al.next) {
+        if (ro.p)
+            k_detect<G, CT, true, L><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl,
+                                                             wc, wl_lo, c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+        else
+            k_detect<G, CT, false, L><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl,
+                                                              wc, wl_lo, c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+    } else if (ro.p) {
+        k_detect<G, CT, true, false><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl,
+                                                             wc, wl_lo, c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+    } else {
+        k_detect<G, CT, false, false><<<grid, INIT_BLOCK, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, C, S, deg_wave, wl,
+                                                              wc, wl_lo, c_lo, wl_hub, c_hub, pr, skip_len, lm, al, ro);
+    }
 }
 
 #define GC_DISPATCH_G(G, ...)                                   \
