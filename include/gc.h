@@ -197,8 +197,11 @@ gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t);
 /*
  * Launch facts of a context (host values): info[0] = compute units,
  * info[1] = workgroups of the persistent recoloring walk for the current
- * group size (0 until first used), info[2] = its workgroups per compute unit.
- * Fills min(cap, 3) entries.
+ * group size (0 until first used), info[2] = its workgroups per compute unit,
+ * info[3] = the longest row of the graph a call on this context analysed last
+ * (-1 before any), info[4] = that graph's adjacency entries (u, w) with
+ * |u - w| >= 32768 (-1 before any; the far entries pick the default color
+ * copy of the initial coloring).  Fills min(cap, 5) entries.
  */
 gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap);
 

@@ -285,9 +285,10 @@ class Context:
         return {k: (int(la[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def info(self) -> dict:
-        a = (ctypes.c_int64 * 3)()
-        self.check(lib().gc_ctx_get_info(self.handle, a, 3), "gc_ctx_get_info")
-        return {"num_cu": a[0], "walk_blocks": a[1], "walk_blocks_per_cu": a[2]}
+        a = (ctypes.c_int64 * 5)()
+        self.check(lib().gc_ctx_get_info(self.handle, a, 5), "gc_ctx_get_info")
+        return {"num_cu": a[0], "walk_blocks": a[1], "walk_blocks_per_cu": a[2], "max_degree": a[3],
+                "far_entries": a[4]}
 
     def set_tuning(self, **kw):
         t = Tuning()

@@ -274,8 +274,9 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
 
 extern "C" gc_status gc_ctx_get_info(gc_ctx *ctx, int64_t *info, int cap) {
     if (!ctx || cap < 0 || (cap > 0 && !info)) return GC_ERR_ARG;
-    const int64_t v[3] = {ctx->num_cu, ctx->walk_blocks, ctx->num_cu ? ctx->walk_blocks / ctx->num_cu : 0};
-    for (int i = 0; i < cap && i < 3; i++) info[i] = v[i];
+    const int64_t v[5] = {ctx->num_cu, ctx->walk_blocks, ctx->num_cu ? ctx->walk_blocks / ctx->num_cu : 0,
+                          ctx->deg_known ? ctx->deg_max : -1, ctx->deg_known ? ctx->deg_far_n : -1};
+    for (int i = 0; i < cap && i < 5; i++) info[i] = v[i];
     return GC_OK;
 }
 
@@ -346,85 +347,125 @@ extern "C" gc_status gc_ctx_status(gc_ctx *ctx, void *stream) {
 // validate: conflicting edges and uncolored vertices
 // ---------------------------------------------------------------------------
 
-// Validation by degree: each wavefront takes 64 consecutive vertices and
-// spreads the entries of their rows over its 64 lanes (a lane finds the row
-// of its entry by a binary search over the rows' prefix sums, read across
-// lanes), so short and mid rows keep every lane busy whatever the degree
-// mix.  Rows longer than VAL_LONG entries go, as (row, chunk) pairs of
-// VAL_LONG entries, to a list that k_validate_long scans one wavefront per
-// chunk.  Counts entries (u, w) with u < w and equal positive colors, and
-// vertices with a color <= 0.
-#define VAL_LONG 4096
+// Validation in windows of 64 consecutive vertices: a wavefront loads their
+// rows' bounds and colors, one vertex a lane, and spreads the rows' entries
+// over its 64 lanes in flat order (a lane finds the row of its entry by a
+// binary search over the rows' prefix sums, read across lanes), so that every
+// lane stays busy whatever the degree mix.  A window with more than VAL_WIN
+// entries goes, as (window, chunk) pairs of VAL_WIN entries, to a list that
+// k_validate_long scans one wavefront per chunk: the work of a wavefront is
+// then bounded by VAL_WIN entries however the long rows cluster (a skewed
+// graph with its hubs at low ids has windows of 78,000 entries).  Counts
+// entries (u, w) with u < w and equal positive colors, and vertices with a
+// color <= 0.
+#define VAL_WIN 4096
 #define VAL_U 4
+
+struct ValWindow {
+    int32_t e0, excl, cv, total;
+};
+
+// Bounds, colors and prefix sums of the window's rows (lane = vertex
+// base + lane); an uncolored vertex contributes no entries, since it has no
+// conflicting edge.  unc counts the uncolored vertices when asked.
+__device__ inline ValWindow val_window(const int32_t *__restrict__ rp, int64_t nnz, int32_t n,
+                                       const int32_t *__restrict__ C, int64_t base, int lane,
+                                       unsigned long long *unc) {
+    ValWindow w = {0, 0, 0, 0};
+    const int64_t v = base + lane;
+    int32_t e1 = 0;
+    if (v < n) {
+        row_range(rp, (int32_t)v, nnz, w.e0, e1);
+        w.cv = C[v];
+        if (unc && w.cv <= 0) (*unc)++;
+    }
+    const int32_t len = w.cv > 0 ? e1 - w.e0 : 0;
+    int32_t incl = len;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    w.excl = incl - len;
+    w.total = __shfl(incl, 63);
+    return w;
+}
+
+// Entries [t0, t1) of a window in flat order, VAL_U per lane a step; the
+// next step's neighbor ids are loaded before this step's color gathers, so
+// the two round trips overlap.
+__device__ inline unsigned long long val_scan(const int32_t *__restrict__ col, const int32_t *__restrict__ C, int32_t n,
+                                              int64_t base, const ValWindow &win, int32_t t0, int32_t t1, int lane) {
+    unsigned long long conf = 0;
+    int32_t w[VAL_U], c[VAL_U], uu[VAL_U];
+    auto fetch = [&](int32_t ts) {
+#pragma unroll
+        for (int k = 0; k < VAL_U; k++) {
+            const int32_t t = ts + 64 * k + lane;
+            int32_t lo = 0, hi = 63;  // last lane whose rows start at or before t
+#pragma unroll
+            for (int step = 0; step < 6; step++) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (__shfl(win.excl, mid) <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t a = __shfl(win.e0, lo), x = __shfl(win.excl, lo);
+            c[k] = __shfl(win.cv, lo);
+            uu[k] = (int32_t)base + lo;
+            w[k] = t < t1 ? col[a + (t - x)] : -1;
+        }
+    };
+    if (t0 < t1) fetch(t0);
+    for (int32_t ts = t0; ts < t1; ts += 64 * VAL_U) {
+        int32_t wn[VAL_U], cn[VAL_U], un[VAL_U];
+#pragma unroll
+        for (int k = 0; k < VAL_U; k++) {
+            wn[k] = w[k];
+            cn[k] = c[k];
+            un[k] = uu[k];
+        }
+        if (ts + 64 * VAL_U < t1) fetch(ts + 64 * VAL_U);
+        // each edge is checked from its smaller end only: half the color gathers
+        int32_t cw[VAL_U];
+#pragma unroll
+        for (int k = 0; k < VAL_U; k++) {
+            const bool need = (uint32_t)wn[k] < (uint32_t)n && wn[k] > un[k];
+            cw[k] = need ? C[wn[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < VAL_U; k++)
+            if (cw[k] == cn[k] && (uint32_t)wn[k] < (uint32_t)n && wn[k] > un[k]) conf++;
+    }
+    return conf;
+}
 
 __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                   int64_t nnz, int32_t n, const int32_t *__restrict__ C,
-                                                  int32_t *__restrict__ long_row, int32_t *__restrict__ long_chunk,
+                                                  int32_t *__restrict__ long_win, int32_t *__restrict__ long_chunk,
                                                   int64_t long_cap, unsigned long long *scal) {
     const int wpb = blockDim.x / 64;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = __lane_id();
     unsigned long long conf = 0, unc = 0;
     for (int64_t base = ((int64_t)blockIdx.x * wpb + wib) * 64; base < n; base += (int64_t)gridDim.x * wpb * 64) {
-        const int64_t v = base + lane;
-        const bool valid = v < n;
-        int32_t e0 = 0, e1 = 0, cv = 0;
-        if (valid) {
-            row_range(rp, (int32_t)v, nnz, e0, e1);
-            cv = C[v];
-            if (cv <= 0) unc++;
-        }
-        int32_t len = cv > 0 ? e1 - e0 : 0;  // an uncolored vertex has no conflicting edge
-        if (len > VAL_LONG) {
-            const int32_t nch = (len + VAL_LONG - 1) / VAL_LONG;
-            const int64_t p = (int64_t)atomicAdd(&scal[S_VLONG], (unsigned long long)nch);
+        const ValWindow win = val_window(rp, nnz, n, C, base, lane, &unc);
+        if (win.total > VAL_WIN) {
+            const int32_t nch = (win.total + VAL_WIN - 1) / VAL_WIN;
+            unsigned long long p0 = 0;
+            if (lane == 0) p0 = atomicAdd(&scal[S_VLONG], (unsigned long long)nch);
+            const int64_t p = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(p0 >> 32)) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p0));
             if (p + nch <= long_cap) {
-                for (int32_t j = 0; j < nch; j++) {
-                    long_row[p + j] = (int32_t)v;
+                for (int32_t j = lane; j < nch; j += 64) {
+                    long_win[p + j] = (int32_t)base;
                     long_chunk[p + j] = j;
                 }
-                len = 0;
-            } else {
-                // list full: the row stays here, scanned by the whole wavefront; the
-                // reserved slots that do exist are marked empty
-                for (int64_t j = p; j < p + nch && j < long_cap; j++) long_row[j] = -1;
+                continue;
             }
+            // list full: the window stays here; the reserved slots that do
+            // exist are marked empty
+            for (int64_t j = p + lane; j < p + nch && j < long_cap; j += 64) long_win[j] = -1;
         }
-        int32_t incl = len;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        const int32_t excl = incl - len;
-        const int32_t total = __shfl(incl, 63);
-        for (int32_t t0 = 0; t0 < total; t0 += 64 * VAL_U) {
-            int32_t w[VAL_U], c[VAL_U], uu[VAL_U];
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++) {
-                const int32_t t = t0 + 64 * k + lane;
-                int32_t lo = 0, hi = 63;  // last lane whose rows start at or before t
-#pragma unroll
-                for (int step = 0; step < 6; step++) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (__shfl(excl, mid) <= t) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int32_t a = __shfl(e0, lo), x = __shfl(excl, lo);
-                c[k] = __shfl(cv, lo);
-                uu[k] = (int32_t)base + lo;
-                w[k] = t < total ? col[a + (t - x)] : -1;
-            }
-            // each edge is checked from its smaller end only: half the color gathers
-            int32_t cw[VAL_U];
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++) {
-                const bool need = (uint32_t)w[k] < (uint32_t)n && w[k] > uu[k];
-                cw[k] = need ? C[w[k]] : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++)
-                if (cw[k] == c[k] && (uint32_t)w[k] < (uint32_t)n && w[k] > uu[k]) conf++;
-        }
+        conf += val_scan(col, C, n, base, win, 0, win.total, lane);
     }
     __shared__ unsigned long long lds[16];
     conf = block_sum_u64(conf, lds);
@@ -435,10 +476,10 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp
     }
 }
 
-// The long rows' chunks listed by k_validate: one wavefront per chunk.
+// The heavy windows' chunks listed by k_validate: one wavefront per chunk.
 __global__ void __launch_bounds__(256) k_validate_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        int64_t nnz, int32_t n, const int32_t *__restrict__ C,
-                                                       const int32_t *__restrict__ long_row,
+                                                       const int32_t *__restrict__ long_win,
                                                        const int32_t *__restrict__ long_chunk, int64_t long_cap,
                                                        unsigned long long *scal) {
     const int wpb = blockDim.x / 64;
@@ -448,24 +489,12 @@ __global__ void __launch_bounds__(256) k_validate_long(const int32_t *__restrict
     if (cnt > long_cap) cnt = long_cap;  // reservations past the list were scanned by k_validate
     unsigned long long conf = 0;
     for (int64_t i = (int64_t)blockIdx.x * wpb + wib; i < cnt; i += (int64_t)gridDim.x * wpb) {
-        const int32_t v = long_row[i];
-        if (v < 0) continue;
-        int32_t e0, e1;
-        row_range(rp, v, nnz, e0, e1);
-        const int32_t a = e0 + long_chunk[i] * VAL_LONG;
-        const int32_t b = min(e1, a + VAL_LONG);
-        const int32_t cv = C[v];
-        for (int32_t e = a + lane; e < b; e += 64 * VAL_U) {
-            int32_t w[VAL_U];
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++) w[k] = e + 64 * k < b ? col[e + 64 * k] : -1;
-            int32_t cw[VAL_U];
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++) cw[k] = ((uint32_t)w[k] < (uint32_t)n && w[k] > v) ? C[w[k]] : 0;
-#pragma unroll
-            for (int k = 0; k < VAL_U; k++)
-                if (cw[k] == cv && (uint32_t)w[k] < (uint32_t)n && w[k] > v) conf++;
-        }
+        const int32_t base = __builtin_amdgcn_readfirstlane(long_win[i]);
+        if (base < 0) continue;
+        const int32_t j = __builtin_amdgcn_readfirstlane(long_chunk[i]);
+        const ValWindow win = val_window(rp, nnz, n, C, base, lane, nullptr);
+        const int32_t t0 = j * VAL_WIN, t1 = win.total - t0 > VAL_WIN ? t0 + VAL_WIN : win.total;
+        conf += val_scan(col, C, n, base, win, t0, t1, lane);
     }
     __shared__ unsigned long long lds[16];
     conf = block_sum_u64(conf, lds);
@@ -822,21 +851,52 @@ __global__ void k_max_degree(const int32_t *__restrict__ rp, int32_t n, int64_t 
     if (threadIdx.x == 0) atomicMax((int *)&scal[S_MAXDEG], bm);
 }
 
-// Far entries (|u - w| >= GC_NEAR): a wavefront per 64 rows, their entries
-// spread over the lanes in 64-entry steps per row.
+// Far entries (|u - w| >= GC_NEAR).  The entries are cut into flat chunks of
+// FAR_CHUNK, a wavefront per chunk, so that a long row spreads over many
+// wavefronts.  A chunk finds the row of its first entry by a binary search of
+// the row pointers, then takes its rows 64 at a time: lane l holds the end of
+// row u + l, and the row of an entry is u plus the number of those ends at or
+// before it, found by a binary search across the lanes.  Row pointers that
+// are not monotone give a wrong count, never an access out of bounds.
+constexpr int32_t FAR_CHUNK = 64 * 64;
+
 __global__ void __launch_bounds__(256) k_far_entries(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      int32_t n, int64_t nnz, unsigned long long *scal) {
     __shared__ unsigned long long lds[16];
     unsigned long long far = 0;
     const int lane = __lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t u = wave; u < n; u += waves) {
-        int32_t e0, e1;
-        row_range(rp, (int32_t)u, nnz, e0, e1);
-        for (int32_t e = e0 + lane; e < e1; e += 64) {
-            const int64_t d = (int64_t)col[e] - u;
-            far += (d >= GC_NEAR || d <= -GC_NEAR) ? 1ull : 0ull;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int32_t m = (int32_t)nnz;  // row pointers are int32, so nnz fits
+    for (int64_t c = wave * FAR_CHUNK; c < nnz; c += waves * FAR_CHUNK) {
+        const int32_t c0 = (int32_t)c, c1 = c0 + FAR_CHUNK < m ? c0 + FAR_CHUNK : m;
+        int32_t lo = 0, hi = n;  // the last row whose first entry is at or before c0
+        while (hi - lo > 1) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if (rp[mid] <= c0) lo = mid;
+            else hi = mid;
+        }
+        int32_t e = c0;
+        for (int64_t u = lo; u < n && e < c1; u += 64) {
+            const int64_t r = u + lane;
+            int32_t end = m;
+            if (r < n) {
+                end = rp[r + 1];
+                end = end < 0 ? 0 : (end > m ? m : end);
+            }
+            const int32_t w_end = min(c1, __shfl(end, 63));
+            for (; e < w_end; e += 64) {
+                const int32_t x = e + lane;
+                int32_t k = 0;
+#pragma unroll
+                for (int32_t s = 32; s; s >>= 1)
+                    if (__shfl(end, k + s - 1) <= x) k += s;
+                if (x < w_end) {
+                    const int64_t d = (int64_t)col[x] - (u + k);
+                    far += (d >= GC_NEAR || d <= -GC_NEAR) ? 1ull : 0ull;
+                }
+            }
+            e = e > w_end ? w_end : e;  // the last step may overrun the window by up to 63
         }
     }
     far = block_sum_u64(far, lds);
@@ -858,13 +918,17 @@ gc_status gc_graph_max_degree(gc_ctx *ctx, const gc_csr *g, hipStream_t s, int32
     k_max_degree<<<grid, 256, 0, s>>>(g->row_ptr, g->n, g->nnz, ctx->scal);
     GC_LAUNCHED();
     if (g->nnz > 0) {
-        k_far_entries<<<4 * ctx->num_cu, 256, 0, s>>>(g->row_ptr, g->col_idx, g->n, g->nnz, ctx->scal);
+        const int64_t blocks = (g->nnz + 4 * FAR_CHUNK - 1) / (4 * FAR_CHUNK);  // four wavefronts a block
+        k_far_entries<<<(int)(blocks < 8 * ctx->num_cu ? blocks : 8 * ctx->num_cu), 256, 0, s>>>(
+            g->row_ptr, g->col_idx, g->n, g->nnz, ctx->scal);
         GC_LAUNCHED();
     }
     gc_status st = gc_sync_scalars(ctx, s);
     if (st) return st;
     ctx->deg_max = (int32_t)ctx->hscal[S_MAXDEG];
-    ctx->deg_far = g->nnz > 0 ? (double)ctx->hscal[S_FAR] / (double)g->nnz : 0.0;
+    ctx->deg_far_n = g->nnz > 0 ? (int64_t)ctx->hscal[S_FAR] : 0;
+    ctx->deg_far = g->nnz > 0 ? (double)ctx->deg_far_n / (double)g->nnz : 0.0;
+    ctx->deg_known = 1;
     ctx->deg_key_rp = g->row_ptr;
     ctx->deg_key_col = g->col_idx;
     ctx->deg_key_n = g->n;

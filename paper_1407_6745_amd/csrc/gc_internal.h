@@ -88,6 +88,8 @@ struct gc_ctx {
     int64_t deg_key_n, deg_key_nnz;
     int32_t deg_max;
     double deg_far;          // fraction of its entries with |u - w| >= GC_NEAR
+    int64_t deg_far_n;       // how many entries that is
+    int deg_known;           // set once a graph has been analysed
     int32_t *rank;           // rank of a color in the class order (ccap + 2)
     int32_t *pi;             // class order (ccap + 2)
     int32_t *off;            // list offsets per (rank, bin) segment (3 * ccap + 4)

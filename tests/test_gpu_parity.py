@@ -123,11 +123,12 @@ def test_validate_count_parity(gc):
 
 
 def test_validate_long_rows(gc):
-    """Rows past 4,096 entries are checked as (row, chunk) pairs, one wavefront
-    per chunk; a full chunk list falls back to the 64-row scan.  Counts equal
-    the oracle's (duplicate entries count once per copy)."""
+    """Windows of 64 rows holding more than 4,096 entries are checked as
+    (window, chunk) pairs, one wavefront per chunk; a full chunk list falls
+    back to scanning the window in place.  Counts equal the oracle's
+    (duplicate entries count once per copy)."""
     rng = np.random.default_rng(3)
-    for g in (gen.star(10000), gen.rmat(14, 16, seed=2), gen.complete(5000)):
+    for g in (gen.star(10000), gen.rmat(14, 16, seed=2), gen.rmat(17, 16, seed=4), gen.complete(5000)):
         rp, col = dev(g)
         base = oracle.greedy_seq(g)
         for trial in range(3):
@@ -138,8 +139,17 @@ def test_validate_long_rows(gc):
                 c[:] = 1
                 c[rng.integers(0, g.n, 5)] = 0
             assert gc.validate(rp, col, torch.from_numpy(c).cuda()) == oracle.validate(g, c), (g.name, trial)
+    # K_5000 on a context of 5,000 vertices: its 79 windows need about 6,170 chunks, so
+    # the list fills part way and the later windows are scanned in place
+    g = gen.complete(5000)
+    rp, col = dev(g)
+    ctx = gc.Context(g.n, g.nnz)
+    c = rng.integers(1, 4000, g.n).astype(np.int32)
+    c[rng.integers(0, g.n, 7)] = 0
+    assert gc.validate(rp, col, torch.from_numpy(c).cuda(), ctx=ctx) == oracle.validate(g, c)
+    ctx.close()
     # two vertices joined by 20,000 duplicate entries each way, on a context of two vertices:
-    # 6 chunks do not fit the 2-entry chunk list
+    # 10 chunks do not fit the 2-entry chunk list
     d = torch.device("cuda:0")
     rp = torch.tensor([0, 20000, 40000], dtype=torch.int32, device=d)
     col = torch.cat([torch.ones(20000, dtype=torch.int32), torch.zeros(20000, dtype=torch.int32)]).to(d)
