@@ -28,7 +28,7 @@
 #define GC_RUN_AHEAD 8  // rounds queued per host read-back when no launch needs one
 static_assert(S_REC + 2 * GC_RUN_AHEAD <= S_COUNT, "round records");
 // loads in flight per lane: whole-wavefront rows are long, so they keep more
-#define ROW_UNROLL(G) ((G) >= 32 ? 16 : GC_UNROLL)
+#define ROW_UNROLL(G) ((G) >= 32 ? 8 : GC_UNROLL)
 
 // Tentative color of w in round 0: 1 + its Random-X offset (no color is held yet).
 __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, bool randx) {
@@ -150,12 +150,16 @@ __device__ inline void publish_long(const LongMasks &lm, const int32_t *__restri
     if (!lm.idx || c < 1 || c > FM_COLORS) return;
     const unsigned long long bit = 1ull << ((c - 1) & 63);
     const int w = (c - 1) >> 6;
-    for (int32_t e = e0 + (int32_t)(__lane_id() & (G - 1)); e < e1; e += G) {
-        const int32_t x = col[e];
-        if ((uint32_t)x < (uint32_t)n) {
-            const int32_t li = lm.idx[x];
-            if (li >= 0) atomicOr(&lm.fm[(size_t)li * FM_WORDS + w], bit);
-        }
+    constexpr int PU = G >= 32 ? 4 : 1;  // a wavefront's row: four neighbor ids per lane in flight
+    for (int32_t e = e0 + (int32_t)(__lane_id() & (G - 1)); e < e1; e += G * PU) {
+        int32_t x[PU], li[PU];
+#pragma unroll
+        for (int u = 0; u < PU; u++) x[u] = e + u * G < e1 ? col[e + u * G] : -1;
+#pragma unroll
+        for (int u = 0; u < PU; u++) li[u] = (uint32_t)x[u] < (uint32_t)n ? lm.idx[x[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < PU; u++)
+            if (li[u] >= 0) atomicOr(&lm.fm[(size_t)li[u] * FM_WORDS + w], bit);
     }
 }
 
@@ -400,6 +404,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
     const int64_t cnt = (int64_t)*wcount;
     const int vpi = INIT_BLOCK / G;
     const int gi = threadIdx.x / G;
+    int32_t iter = 0;
     for (int64_t base = (int64_t)blockIdx.x * vpi; base < cnt; base += (int64_t)gridDim.x * vpi) {
         const int64_t i = base + gi;
         int32_t v = -1, e0 = 0, e1 = 0, t = 0, full = 0, li = -1;
@@ -445,7 +450,11 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_detect(const int32_t *__restrict
         const bool hub = full > deg_wave;  // worklist bins by the full row length
         bq_push(q.buf[0], &q.cnt[0], leader && lose && !hub, v);
         bq_push(q.buf[1], &q.cnt[1], leader && lose && hub, v);
-        queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
+        // wavefront rows push at most four entries an iteration: they check
+        // the queues (a block barrier) every 64 iterations only, which still
+        // flushes before the buffer can overflow (the trip count is uniform
+        // across the block)
+        if (G < 64 || ++iter % 64 == 0) queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, false);
     }
     queues_flush(q, wl_lo, c_lo, wl_hub, c_hub, true);
 }
