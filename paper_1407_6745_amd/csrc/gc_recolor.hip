@@ -907,7 +907,11 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
         // deferring their waits gains nothing and costs registers)
         if (!FULL) finish_row<U, false, CT, false>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
         else if (b == 2) finish_split<U, CT>(t, w, x, col, n, C, S, lw, hub_bits, hub_cnt, wc);
-        else if (s < 64) finish_row<U, false, CT, true>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
+        // group rows (at most deg_wave entries, 64 by default) keep to the
+        // register word: a color above 64 needs 64 lower-rank neighbors, and
+        // the rare row that has them rescans in 64-color windows (RMAT-22
+        // walk 2.39 -> 2.36 ms)
+        else if (s < 64 || b == 0) finish_row<U, false, CT, true>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
         else finish_row<U, true, CT, true>(t, w, x, b ? 64 : G, col, n, C, S, lw, wc);
     };
 
