@@ -78,9 +78,11 @@ __device__ inline int64_t hist_tiles_per_wg(int32_t n, int block, int grid) {
 
 // Class sizes by degree bin.  Colors below HIST_LDS: bin-0 and bin-1 counts
 // in LDS, flushed into the workgroup's histogram copy; bin 2 always, and
-// every bin of larger colors, straight into the global arrays.
+// every bin of larger colors, straight into the global arrays.  bins == 0:
+// every row is in bin 0 (no row is longer than deg_wave), and the row
+// pointers are not read.
 __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t *__restrict__ rp, int64_t nnz,
-                       int32_t deg_wave, int32_t deg_split, int32_t split_len, int32_t ccap,
+                       int32_t bins, int32_t deg_wave, int32_t deg_split, int32_t split_len, int32_t ccap,
                        int32_t *__restrict__ hist, int32_t *__restrict__ histw, int32_t *__restrict__ hist_s,
                        int32_t *__restrict__ hist_sc, int32_t *__restrict__ hcopy, unsigned long long *scal) {
     __shared__ int32_t h[2 * HIST_LDS];  // bin 0 at [c], bin 1 at [HIST_LDS + c]
@@ -101,8 +103,8 @@ __global__ void k_hist(int32_t n, const int32_t *__restrict__ Cin, const int32_t
             const bool in = v < n;
             const int64_t vv = in ? v : 0;
             cs[it] = in ? Cin[vv] : 0;
-            a0[it] = rp[vv];
-            a1[it] = rp[vv + 1];
+            a0[it] = bins ? rp[vv] : 0;
+            a1[it] = bins ? rp[vv + 1] : 0;
         }
 #pragma unroll
         for (int it = 0; it < HIST_ITEMS; it++) {
@@ -1230,7 +1232,11 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
     // anyway): 32 aligned bytes, one fill launch
     static_assert(S_MAXC == 2 && S_ERR == 4 && S_CONFLICTS == 5, "scalar slots cleared per pass");
     GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 32, s));
-    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, deg_wave, deg_split,
+    int32_t maxdeg_h = 0;
+    status = gc_graph_max_degree(ctx, g, s, &maxdeg_h);
+    if (status) return status;
+    const int32_t bins = maxdeg_h > deg_wave ? 1 : 0;
+    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, bins, deg_wave, deg_split,
                                                              split_len, ctx->ccap, ctx->hist, ctx->histw, ctx->hist_s,
                                                              ctx->hist_sc, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
@@ -1353,7 +1359,7 @@ static gc_status gc_arc_recolor_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm,
     // anyway): 32 aligned bytes, one fill launch
     static_assert(S_MAXC == 2 && S_ERR == 4 && S_CONFLICTS == 5, "scalar slots cleared per pass");
     GC_HIP(hipMemsetAsync(ctx->scal + S_MAXC, 0, 32, s));
-    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, ctx->tune.deg_wave, 0,
+    GC_TIMED(GC_K_HIST, s, k_hist<<<hist_grid, block, 0, s>>>(n, colors_in, g->row_ptr, g->nnz, 0, ctx->tune.deg_wave, 0,
                                                              ctx->tune.split_len, ctx->ccap, ctx->hist, ctx->histw,
                                                              ctx->hist_s, ctx->hist_sc, ctx->hcopy, ctx->scal));
     GC_LAUNCHED();
