@@ -12,6 +12,7 @@
 #define BT 256            // threads per workgroup
 #define BK 1024           // colors below BK keep their class tables in LDS
 #define BBITS 1024        // LDS bitmap words for distinct counts (colors up to 32768)
+#define BU 16             // neighbor ids in flight per lane in the row scans
 
 // workspace slice layout per workgroup (int32 units)
 struct BatchSlice {
@@ -89,11 +90,16 @@ __device__ int32_t block_init(const int32_t *rp, const int32_t *col, int64_t nnz
                 row_range(rp, v, nnz, e0, e1);
                 uint32_t tv = randx ? gc_pick(sc, v, X) : 0u;
                 uint32_t pv = gc_prio(sp, v);
-                for (int32_t e = e0; e < e1; e++) {
-                    int32_t w = col[e];
-                    if ((uint32_t)w >= (uint32_t)n) continue;
-                    uint32_t tw = randx ? gc_pick(sc, w, X) : 0u;
-                    if (tw == tv && gc_prio(sp, w) > pv) { lose = true; break; }
+                for (int32_t eb = e0; eb < e1 && !lose; eb += BU) {
+                    int32_t w[BU];
+#pragma unroll
+                    for (int u = 0; u < BU; u++) w[u] = eb + u < e1 ? col[eb + u] : -1;
+#pragma unroll
+                    for (int u = 0; u < BU; u++) {
+                        if ((uint32_t)w[u] >= (uint32_t)n) continue;
+                        const uint32_t tw = randx ? gc_pick(sc, w[u], X) : 0u;
+                        if (tw == tv && gc_prio(sp, w[u]) > pv) lose = true;
+                    }
                 }
                 int32_t t = (int32_t)tv + 1;
                 C[v] = lose ? -t : t;
@@ -118,7 +124,7 @@ __device__ int32_t block_init(const int32_t *rp, const int32_t *col, int64_t nnz
             int32_t v = win[i];
             int32_t e0, e1;
             row_range(rp, v, nnz, e0, e1);
-            C[v] = -select_color_lane(col, e0, e1, C, n, randx ? gc_pick(sc, v, X) : 0u);
+            C[v] = -select_color_lane<BU>(col, e0, e1, C, n, randx ? gc_pick(sc, v, X) : 0u);
         }
         __syncthreads();
         for (int32_t base = 0; base < cnt; base += BT) {
@@ -131,11 +137,16 @@ __device__ int32_t block_init(const int32_t *rp, const int32_t *col, int64_t nnz
                 int32_t e0, e1;
                 row_range(rp, v, nnz, e0, e1);
                 uint32_t pv = gc_prio(sp, v);
-                for (int32_t e = e0; e < e1; e++) {
-                    int32_t w = col[e];
-                    if ((uint32_t)w >= (uint32_t)n) continue;
-                    int32_t cw = C[w];
-                    if ((cw == t || cw == -t) && gc_prio(sp, w) > pv) { lose = true; break; }
+                for (int32_t eb = e0; eb < e1 && !lose; eb += BU) {
+                    int32_t w[BU], cw[BU];
+#pragma unroll
+                    for (int u = 0; u < BU; u++) w[u] = eb + u < e1 ? col[eb + u] : -1;
+#pragma unroll
+                    for (int u = 0; u < BU; u++) cw[u] = (uint32_t)w[u] < (uint32_t)n ? C[w[u]] : 0;
+#pragma unroll
+                    for (int u = 0; u < BU; u++)
+                        if ((uint32_t)w[u] < (uint32_t)n && (cw[u] == t || cw[u] == -t) && gc_prio(sp, w[u]) > pv)
+                            lose = true;
                 }
                 if (!lose) C[v] = t;
             }
@@ -186,7 +197,7 @@ __device__ int32_t block_pass(const int32_t *rp, const int32_t *col, int64_t nnz
             int32_t v = ws.list[i];
             int32_t e0, e1;
             row_range(rp, v, nnz, e0, e1);
-            int32_t c = select_color_lane(col, e0, e1, C, n, 0u);
+            int32_t c = select_color_lane<BU>(col, e0, e1, C, n, 0u);
             C[v] = c;
             newmax = max(newmax, c);
         }

@@ -333,16 +333,23 @@ __device__ inline uint32_t nth_set_bit(uint64_t x, uint32_t j) {
 }
 
 // (j+1)-th smallest positive color absent from {C[w] > 0 : w in col[e0..e1)},
-// one lane per vertex, 64 colors per window.
+// one lane per vertex, 64 colors per window; UNR neighbor ids, then their UNR
+// colors, in flight per lane.
+template <int UNR = 8>
 __device__ inline int32_t select_color_lane(const int32_t *__restrict__ col, int32_t e0, int32_t e1,
                                             const int32_t *C, int32_t n, uint32_t j) {
     uint32_t base = 0;
     for (;;) {
         uint64_t mask = 0;
-        for (int32_t e = e0; e < e1; e++) {
-            int32_t w = col[e];
-            if ((uint32_t)w < (uint32_t)n) {
-                uint32_t d = (uint32_t)C[w] - base - 1u;  // colors <= base (incl. <= 0) wrap to >= 64
+        for (int32_t eb = e0; eb < e1; eb += UNR) {
+            int32_t w[UNR], x[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) w[u] = eb + u < e1 ? col[eb + u] : -1;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) x[u] = (uint32_t)w[u] < (uint32_t)n ? C[w[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const uint32_t d = (uint32_t)x[u] - base - 1u;  // colors <= base (incl. <= 0) wrap to >= 64
                 if (d < 64u) mask |= 1ull << d;
             }
         }
