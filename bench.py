@@ -823,7 +823,7 @@ def run_graph(args, workload):
         "walk_trace_one_pass": walk_trace,
         "validate": {"ms": round(validate_ms, 4), "algorithmic_bytes": validate_bytes,
                      "frac_of_peak": round(validate_bytes / (validate_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "note": "gc_validate call incl. its two scalar resets and read-back, events on the stream"},
+                     "note": "gc_validate call incl. its scalar resets and read-back, events on the stream"},
         "roofline": roofline,
     }
     # the initial coloring against its algorithmic bytes (16 per scanned entry

@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp
     unsigned long long conf = 0, unc = 0;
     for (int64_t base = ((int64_t)blockIdx.x * wpb + wib) * 64; base < n; base += (int64_t)gridDim.x * wpb * 64) {
         const ValWindow win = val_window(rp, nnz, n, C, base, lane, &unc);
-        if (win.total > VAL_WIN) {
+        if (win.total > VAL_WIN && long_cap > 0) {
             const int32_t nch = (win.total + VAL_WIN - 1) / VAL_WIN;
             unsigned long long p0 = 0;
             if (lane == 0) p0 = atomicAdd(&scal[S_VLONG], (unsigned long long)nch);
@@ -508,8 +508,16 @@ gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, 
     if (g->n > 0 && !colors) return gc_fail(ctx, GC_ERR_ARG, "colors is NULL");
     hipStream_t s = (hipStream_t)stream;
     GC_HIP(hipSetDevice(ctx->device));
+    // Windows of more than VAL_WIN entries exist only when 64 rows can hold
+    // them; otherwise the long-window launch is left out, and the list is
+    // given no room, so that a window heavier than the cached longest row
+    // promised (a graph changed in place) is still scanned where it is.
+    int32_t maxdeg = 0;
+    st = gc_graph_max_degree(ctx, g, s, &maxdeg);
+    if (st) return st;
+    const bool heavy = (int64_t)maxdeg * 64 > VAL_WIN;
     GC_HIP(hipMemsetAsync(ctx->scal + S_CONFLICTS, 0, 2 * 8, s));
-    GC_HIP(hipMemsetAsync(ctx->scal + S_VLONG, 0, 8, s));
+    if (heavy) GC_HIP(hipMemsetAsync(ctx->scal + S_VLONG, 0, 8, s));
     if (g->n > 0) {
         const int block = 256;
         const int64_t waves = ((int64_t)g->n + 63) / 64;
@@ -517,12 +525,15 @@ gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, 
         const int grid = (int)std::min<int64_t>((waves + 3) / 4, cap);
         // the long-row chunk list lives in two initial-coloring worklists (free here)
         GC_TIMED(GC_K_OTHER, s, k_validate<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors,
-                                                                   ctx->wl[1], ctx->wl[2], ctx->max_n, ctx->scal));
+                                                                   ctx->wl[1], ctx->wl[2], heavy ? ctx->max_n : 0,
+                                                                   ctx->scal));
         GC_LAUNCHED();
-        GC_TIMED(GC_K_OTHER, s, k_validate_long<<<ctx->num_cu * 4, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
-                                                                                   g->n, colors, ctx->wl[1],
-                                                                                   ctx->wl[2], ctx->max_n, ctx->scal));
-        GC_LAUNCHED();
+        if (heavy) {
+            GC_TIMED(GC_K_OTHER, s, k_validate_long<<<ctx->num_cu * 4, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
+                                                                                       g->n, colors, ctx->wl[1],
+                                                                                       ctx->wl[2], ctx->max_n, ctx->scal));
+            GC_LAUNCHED();
+        }
     }
     st = gc_sync_scalars(ctx, s);
     if (st) return st;

@@ -122,6 +122,42 @@ def test_validate_count_parity(gc):
             assert gc.count_colors(ct) == oracle.count(c)
 
 
+def _validate_expected(rp, col, c):
+    """Entries (u, w), u < w, with equal positive colors; vertices with a color <= 0."""
+    n = len(rp) - 1
+    u = np.repeat(np.arange(n), np.diff(rp))
+    w = np.asarray(col, np.int64)
+    ok = (w >= 0) & (w < n) & (u < w)
+    cu, cw = c[u[ok]], c[w[ok]]
+    return int(((cu == cw) & (cu > 0)).sum()), int((c <= 0).sum())
+
+
+def test_validate_graph_changed_in_place(gc):
+    """A graph rewritten in place (same arrays, same sizes) after a validation:
+    the longest row cached for the old contents is stale, and windows heavier
+    than it promised are still checked where they are."""
+    d = torch.device("cuda:0")
+    rng = np.random.default_rng(8)
+    n, deg = 1000, 40
+    rp = (np.arange(n + 1) * deg).astype(np.int32)
+    col = ((np.arange(n)[:, None] + np.arange(1, deg + 1)[None, :]) % n).astype(np.int32).ravel()
+    rp_t, col_t = torch.from_numpy(rp).to(d), torch.from_numpy(col).to(d)
+    ctx = gc.Context(n, n * deg)
+    c = rng.integers(1, 6, n).astype(np.int32)
+    c[rng.integers(0, n, 9)] = 0
+    ct = torch.from_numpy(c).to(d)
+    assert gc.validate(rp_t, col_t, ct, ctx=ctx) == _validate_expected(rp, col, c)
+    # rows 0..63 now hold 600 entries each (one window of 38,400), the others 1 or 2
+    lens = np.concatenate([np.full(64, 600), np.full(272, 1), np.full(664, 2)])
+    assert lens.sum() == n * deg
+    rp2 = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    col2 = rng.integers(0, n, n * deg).astype(np.int32)
+    rp_t.copy_(torch.from_numpy(rp2))
+    col_t.copy_(torch.from_numpy(col2))
+    assert gc.validate(rp_t, col_t, ct, ctx=ctx) == _validate_expected(rp2, col2, c)
+    ctx.close()
+
+
 def test_validate_long_rows(gc):
     """Windows of 64 rows holding more than 4,096 entries are checked as
     (window, chunk) pairs, one wavefront per chunk; a full chunk list falls
