@@ -46,13 +46,13 @@ enum {
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
     S_FAR = 26,      // adjacency entries (u, w) with |u - w| >= GC_NEAR (locality of a graph)
-    S_REC = 46,      // rounds queued ahead (46..61): input size, previous round's degree sum
+    S_REC = 64,      // rounds queued ahead (64..127): input size, previous round's degree sum
     S_VLONG = 35,    // validation: (row, chunk) pairs of long rows listed
     S_TAIL = 36,     // initial coloring's persistent tail launch (36..45): check-in, decision, barrier count and
                      // generation, two list counts, two degree sums, rounds run, status
     S_STICKY = 34,   // device failures kept until a synchronizing call reports them (bit 1: a walk wait
                      // gave up, bit 2: walk workgroups not all resident); never cleared by a pass
-    S_COUNT = 64
+    S_COUNT = 128
 };
 
 struct gc_ctx {
