@@ -38,6 +38,9 @@ GRAPHS = {
     "rmat": lambda: gen.rmat(12, 16, seed=5),
     "rgg": lambda: gen.rgg(2500, 0.05, 7),
     "complete100": lambda: gen.complete(100),
+    # rows of exactly 64 entries (group rows at the default deg_wave) in 65
+    # classes: the last rank's First Fit color is 65, past the register word
+    "complete65": lambda: gen.complete(65),
     "star": lambda: gen.star(5000),
     "path": lambda: gen.path(1000),
     "single": lambda: gen.empty(1),
@@ -117,7 +120,7 @@ PASS_TUNINGS = [
 
 
 @pytest.mark.parametrize("t", PASS_TUNINGS, ids=str)
-@pytest.mark.parametrize("name", ["rmat", "star", "complete100", "mesh"])
+@pytest.mark.parametrize("name", ["rmat", "star", "complete100", "complete65", "mesh"])
 def test_passes_tunings(gc, name, t):
     g = GRAPHS[name]()
     ctx = gc.Context(g.n, g.nnz)
