@@ -393,14 +393,17 @@ __device__ inline ValWindow val_window(const int32_t *__restrict__ rp, int64_t n
 // Entries [t0, t1) of a window in flat order, VAL_U per lane a step; the
 // next step's neighbor ids are loaded before this step's color gathers, so
 // the two round trips overlap.
+// IT: type of the positions in a window (int64_t only for graphs with nearly
+// 2^31 entries, where t + 64 * VAL_U could wrap in 32 bits).
+template <typename IT>
 __device__ inline unsigned long long val_scan(const int32_t *__restrict__ col, const int32_t *__restrict__ C, int32_t n,
                                               int64_t base, const ValWindow &win, int32_t t0, int32_t t1, int lane) {
     unsigned long long conf = 0;
     int32_t w[VAL_U], c[VAL_U], uu[VAL_U];
-    auto fetch = [&](int32_t ts) {
+    auto fetch = [&](IT ts) {
 #pragma unroll
         for (int k = 0; k < VAL_U; k++) {
-            const int32_t t = ts + 64 * k + lane;
+            const IT t = ts + 64 * k + lane;
             int32_t lo = 0, hi = 63;  // last lane whose rows start at or before t
 #pragma unroll
             for (int step = 0; step < 6; step++) {
@@ -415,7 +418,7 @@ __device__ inline unsigned long long val_scan(const int32_t *__restrict__ col, c
         }
     };
     if (t0 < t1) fetch(t0);
-    for (int32_t ts = t0; ts < t1; ts += 64 * VAL_U) {
+    for (IT ts = t0; ts < t1; ts += 64 * VAL_U) {
         int32_t wn[VAL_U], cn[VAL_U], un[VAL_U];
 #pragma unroll
         for (int k = 0; k < VAL_U; k++) {
@@ -438,6 +441,7 @@ __device__ inline unsigned long long val_scan(const int32_t *__restrict__ col, c
     return conf;
 }
 
+template <typename IT>
 __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                   int64_t nnz, int32_t n, const int32_t *__restrict__ C,
                                                   int32_t *__restrict__ long_win, int32_t *__restrict__ long_chunk,
@@ -465,7 +469,7 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp
             // exist are marked empty
             for (int64_t j = p + lane; j < p + nch && j < long_cap; j += 64) long_win[j] = -1;
         }
-        conf += val_scan(col, C, n, base, win, 0, win.total, lane);
+        conf += val_scan<IT>(col, C, n, base, win, 0, win.total, lane);
     }
     __shared__ unsigned long long lds[16];
     conf = block_sum_u64(conf, lds);
@@ -477,6 +481,7 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ rp
 }
 
 // The heavy windows' chunks listed by k_validate: one wavefront per chunk.
+template <typename IT>
 __global__ void __launch_bounds__(256) k_validate_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        int64_t nnz, int32_t n, const int32_t *__restrict__ C,
                                                        const int32_t *__restrict__ long_win,
@@ -494,7 +499,7 @@ __global__ void __launch_bounds__(256) k_validate_long(const int32_t *__restrict
         const int32_t j = __builtin_amdgcn_readfirstlane(long_chunk[i]);
         const ValWindow win = val_window(rp, nnz, n, C, base, lane, nullptr);
         const int32_t t0 = j * VAL_WIN, t1 = win.total - t0 > VAL_WIN ? t0 + VAL_WIN : win.total;
-        conf += val_scan(col, C, n, base, win, t0, t1, lane);
+        conf += val_scan<IT>(col, C, n, base, win, t0, t1, lane);
     }
     __shared__ unsigned long long lds[16];
     conf = block_sum_u64(conf, lds);
@@ -524,14 +529,17 @@ gc_status gc_validate_impl(gc_ctx *ctx, const gc_csr *g, const int32_t *colors, 
         const int64_t cap = (int64_t)ctx->num_cu * 16;
         const int grid = (int)std::min<int64_t>((waves + 3) / 4, cap);
         // the long-row chunk list lives in two initial-coloring worklists (free here)
-        GC_TIMED(GC_K_OTHER, s, k_validate<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors,
-                                                                   ctx->wl[1], ctx->wl[2], heavy ? ctx->max_n : 0,
-                                                                   ctx->scal));
+        // positions within a window in 64 bits only where 32 could wrap
+        const bool wide = g->nnz > (int64_t)INT32_MAX - 65536;
+        auto kv = wide ? k_validate<int64_t> : k_validate<int32_t>;
+        auto kl = wide ? k_validate_long<int64_t> : k_validate_long<int32_t>;
+        GC_TIMED(GC_K_OTHER, s, kv<<<grid, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors, ctx->wl[1],
+                                                           ctx->wl[2], heavy ? ctx->max_n : 0, ctx->scal));
         GC_LAUNCHED();
         if (heavy) {
-            GC_TIMED(GC_K_OTHER, s, k_validate_long<<<ctx->num_cu * 4, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz,
-                                                                                       g->n, colors, ctx->wl[1],
-                                                                                       ctx->wl[2], ctx->max_n, ctx->scal));
+            GC_TIMED(GC_K_OTHER, s, kl<<<ctx->num_cu * 4, block, 0, s>>>(g->row_ptr, g->col_idx, g->nnz, g->n, colors,
+                                                                          ctx->wl[1], ctx->wl[2], ctx->max_n,
+                                                                          ctx->scal));
             GC_LAUNCHED();
         }
     }
@@ -880,14 +888,14 @@ __global__ void __launch_bounds__(256) k_far_entries(const int32_t *__restrict__
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int32_t m = (int32_t)nnz;  // row pointers are int32, so nnz fits
     for (int64_t c = wave * FAR_CHUNK; c < nnz; c += waves * FAR_CHUNK) {
-        const int32_t c0 = (int32_t)c, c1 = c0 + FAR_CHUNK < m ? c0 + FAR_CHUNK : m;
-        int32_t lo = 0, hi = n;  // the last row whose first entry is at or before c0
+        const int64_t c1 = c + FAR_CHUNK < nnz ? c + FAR_CHUNK : nnz;  // (64-bit: no wrap near 2^31 entries)
+        int32_t lo = 0, hi = n;  // the last row whose first entry is at or before c
         while (hi - lo > 1) {
             const int32_t mid = lo + ((hi - lo) >> 1);
-            if (rp[mid] <= c0) lo = mid;
+            if (rp[mid] <= c) lo = mid;
             else hi = mid;
         }
-        int32_t e = c0;
+        int64_t e = c;
         for (int64_t u = lo; u < n && e < c1; u += 64) {
             const int64_t r = u + lane;
             int32_t end = m;
@@ -895,9 +903,9 @@ __global__ void __launch_bounds__(256) k_far_entries(const int32_t *__restrict__
                 end = rp[r + 1];
                 end = end < 0 ? 0 : (end > m ? m : end);
             }
-            const int32_t w_end = min(c1, __shfl(end, 63));
+            const int64_t w_end = min(c1, (int64_t)__shfl(end, 63));
             for (; e < w_end; e += 64) {
-                const int32_t x = e + lane;
+                const int64_t x = e + lane;
                 int32_t k = 0;
 #pragma unroll
                 for (int32_t s = 32; s; s >>= 1)
