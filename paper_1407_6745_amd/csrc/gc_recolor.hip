@@ -831,6 +831,10 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
             const uint32_t s0 = (uint32_t)CO[seg], len = (uint32_t)CO[seg + 1] - s0;
             const uint32_t lo = s0 + (uint32_t)(((uint64_t)len * x) >> xl);
             hi = s0 + (uint32_t)(((uint64_t)len * (x + 1)) >> xl);
+            if (hi <= lo) {  // no chunk of this segment in this part (mesh walk 150.8 -> 146.6 us)
+                c = hi;
+                continue;
+            }
             // rotate so that short segments do not all land on the first
             // wavefronts: c - lo = (me - s0) mod Wx, with s0 mod Wx by a
             // multiply-high with floor((2^32 - 1) / Wx) (the quotient is at
