@@ -55,7 +55,7 @@ gc_status gc_check_graph_args(gc_ctx *ctx, const gc_csr *g) {
 
 static void free_all(gc_ctx *c) {
     void *ptrs[] = {c->wl[0], c->wl[1], c->wl[2], c->wl[3], c->list, c->rows, c->hist, c->rank, c->pi, c->off, c->cursor,
-                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->histw, c->hist_s,
+                    c->keys, c->bitmap, c->round_stats, c->scal, c->bws, c->coff, c->segnz, c->histw, c->hist_s,
                     c->hist_sc, c->sbase, c->hsub, c->hub_bits, c->hub_cnt, c->hub_v, c->hub_first, c->shadow,
                     c->d2mask, c->border, c->longidx, c->fm, c->act, c->alen, c->hcopy, c->trace, c->sync};
     for (void *p : ptrs)
@@ -104,6 +104,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
         {(void **)&ctx->hist, CC * 4},       {(void **)&ctx->rank, CC * 4},
         {(void **)&ctx->pi, CC * 4},         {(void **)&ctx->off, (3 * CC + 4) * 4},
         {(void **)&ctx->coff, (3 * CC + 4) * 4},
+        {(void **)&ctx->segnz, (3 * CC + 4) * 4},
         {(void **)&ctx->histw, CC * 4},      {(void **)&ctx->hist_s, CC * 4},
         {(void **)&ctx->hist_sc, CC * 4},    {(void **)&ctx->sbase, (CC + 2) * 4},
         {(void **)&ctx->hcopy, (size_t)GC_HCOPY_INTS * 4},

@@ -46,6 +46,7 @@ enum {
     S_SUM = 24,      // checksum of a color array (autotuning)
     S_NLONG = 25,    // long rows of the initial coloring's masks
     S_FAR = 26,      // adjacency entries (u, w) with |u - w| >= GC_NEAR (locality of a graph)
+    S_NZSEG = 27,    // recoloring: segments with at least one work chunk (their list is ctx->segnz)
     S_REC = 64,      // rounds queued ahead (64..127): input size, previous round's degree sum
     S_VLONG = 35,    // validation: (row, chunk) pairs of long rows listed
     S_TAIL = 36,     // initial coloring's persistent tail launch (36..45): check-in, decision, barrier count and
@@ -70,6 +71,7 @@ struct gc_ctx {
     int32_t *hist;           // class sizes by color (ccap + 2), all zero between calls
     int32_t *histw;          // per color: vertices in the wavefront-per-vertex degree bin; zero between calls
     int32_t *coff;           // recolor: work-chunk offsets per (rank, bin) segment (3 * ccap + 4)
+    int32_t *segnz;          // recolor: the segments with work chunks, in order (3 * ccap + 4)
     int32_t *hist_s;         // per color: vertices of the split bin; zero between calls
     int32_t *hist_sc;        // per color: work chunks of those vertices; zero between calls
     int32_t *hcopy;          // recoloring's histogram copies and per-copy scatter cursors (GC_HCOPY_INTS)

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(THREADS) k_class_order(int32_t ccap, int32_t p
                                                                int32_t *hist_sc, int32_t *cls, int32_t *pi,
                                                                int32_t *rank, int32_t *off, int32_t *coff,
                                                                int32_t *cursor, int32_t *sbase, int32_t *hcopy,
-                                                               unsigned long long *scal) {
+                                                               int32_t *segnz, unsigned long long *scal) {
     __shared__ int32_t lds[32];
     // up to ORDER_LDS colors every step below runs on LDS copies of the class
     // counts (one workgroup: global round trips would dominate)
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(THREADS) k_class_order(int32_t ccap, int32_t p
     }
     const int32_t k = block_class_order(maxc, perm, s_perm, H, CL, PI, rank, nullptr, nullptr, lds);
     const int32_t nseg = NSEG_PER_RANK * k;
-    int32_t acc = 0, cacc = 0;
+    int32_t acc = 0, cacc = 0, zacc = 0;
     for (int32_t base = 0; base < nseg; base += blockDim.x) {
         const int32_t g = base + (int32_t)threadIdx.x;
         int32_t sz = 0, ch = 0;
@@ -236,16 +236,20 @@ __global__ void __launch_bounds__(THREADS) k_class_order(int32_t ccap, int32_t p
                 ch = HSC[c];
             }
         }
-        int32_t tot, ctot;
+        int32_t tot, ctot, ztot;
         const int32_t ex = block_exclusive_scan(sz, &tot, lds);
         const int32_t cex = block_exclusive_scan(ch, &ctot, lds);
+        // the segments that hold work chunks, in order: the walk visits only these
+        const int32_t zex = block_exclusive_scan(ch > 0 ? 1 : 0, &ztot, lds);
         if (g < nseg) {
             off[g] = acc + ex;
             cursor[g] = acc + ex;
             coff[g] = cacc + cex;
+            if (ch > 0) segnz[zacc + zex] = g;
         }
         acc += tot;
         cacc += ctot;
+        zacc += ztot;
     }
     // hub slot bases: prefix of the split-segment sizes over ranks
     int32_t hacc = 0;
@@ -262,6 +266,7 @@ __global__ void __launch_bounds__(THREADS) k_class_order(int32_t ccap, int32_t p
         off[nseg] = acc;
         coff[nseg] = cacc;
         scal[S_K] = (unsigned long long)k;
+        scal[S_NZSEG] = (unsigned long long)zacc;
     }
     if (local)
         for (int32_t i = threadIdx.x; i < k; i += blockDim.x) pi[i] = l_pi[i];
@@ -793,7 +798,8 @@ __device__ inline void finish_split(const WalkChunk &t, const int32_t *w, const 
 #define WALK_TAB 1536  // segment tables of up to WALK_TAB segments (512 classes) live in LDS
 
 template <int G, bool LDS_TAB, bool FULL, int CT>
-__device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, int32_t nseg,
+__device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, const int32_t *NZ, int32_t nnz_seg,
+                                          int32_t nseg,
                                           const int2 *__restrict__ rows, const int32_t *__restrict__ col,
                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
                                           const int32_t *__restrict__ hsub, const int32_t *__restrict__ sbase,
@@ -816,18 +822,22 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, i
     // then the group rows: the longest scans of a class start earliest, and a
     // split row's sub-chunks are already waiting when the previous class ends.
     int32_t idx = -1, seg = -1;
+    // visit order: every segment with WALK_LONG_FIRST, else only those with
+    // work chunks when their list is given (a wavefront passes every segment
+    // it visits, while it takes only a few dozen chunks of the pass)
+    const bool lfirst = (wc.flags & WALK_LONG_FIRST) != 0;
+    const int32_t nvisit = (lfirst || !NZ) ? nseg : nnz_seg;
     uint32_t c = 0, hi = 0;
     bool first = true;
     auto advance = [&]() {
         if (!first) c += Wx;
         first = false;
         while (c >= hi) {
-            if (++idx >= nseg) {
+            if (++idx >= nvisit) {
                 seg = nseg;
                 return;
             }
-            seg = (wc.flags & WALK_LONG_FIRST) ? idx - idx % NSEG_PER_RANK + (NSEG_PER_RANK - 1 - idx % NSEG_PER_RANK)
-                                               : idx;
+            seg = lfirst ? idx - idx % NSEG_PER_RANK + (NSEG_PER_RANK - 1 - idx % NSEG_PER_RANK) : (NZ ? NZ[idx] : idx);
             const uint32_t s0 = (uint32_t)CO[seg], len = (uint32_t)CO[seg + 1] - s0;
             if (len == 0) continue;  // an empty segment: c >= hi still holds (mesh walk 147.7 -> 143.3 us)
             const uint32_t lo = s0 + (uint32_t)(((uint64_t)len * x) >> xl);
@@ -1000,13 +1010,14 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
                                                           int32_t n, int32_t *C, const int32_t *__restrict__ list,
                                                           const int32_t *__restrict__ off,
                                                           const int32_t *__restrict__ coff,
+                                                          const int32_t *__restrict__ segnz,
                                                           const int32_t *__restrict__ hsub,
                                                           const int32_t *__restrict__ sbase, int32_t split_len,
                                                           unsigned long long *hub_bits, int32_t *hub_cnt,
                                                           unsigned long long *scal, int32_t xcd, int32_t check_resident,
                                                           uint32_t spin_limit, uint32_t walk_flags,
                                                           unsigned long long *trace, void *S) {
-    __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1];
+    __shared__ int32_t t_off[WALK_TAB + 1], t_coff[WALK_TAB + 1], t_nz[WALK_TAB];
     __shared__ unsigned long long lmask[WALK_BLOCK];  // per wavefront: 64 mask words for colors above 64
     unsigned long long *lw = lmask + (threadIdx.x & ~63u);
     if (check_resident) {
@@ -1031,6 +1042,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
     }
     const int32_t k = (int32_t)scal[S_K];
     const int32_t nseg = NSEG_PER_RANK * k;
+    int32_t nnz_seg = (int32_t)scal[S_NZSEG];
+    nnz_seg = nnz_seg < 0 ? 0 : (nnz_seg > nseg ? nseg : nnz_seg);
     if (!OPT) trace = nullptr;
     const WaitCtl wc = {scal, spin_limit, OPT ? walk_flags : 0u, trace};
     if (trace && threadIdx.x == 0) atomicMin(&trace[0], wall_clock64());
@@ -1038,15 +1051,16 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_flow(const int2 *__restrict
         // segment tables in LDS: their reads are tracked apart from the vector
         // loads in flight, so looking up the next chunk never drains the pipeline
         for (int32_t i = threadIdx.x; i <= nseg; i += WALK_BLOCK) { t_off[i] = off[i]; t_coff[i] = coff[i]; }
+        for (int32_t i = threadIdx.x; i < nnz_seg; i += WALK_BLOCK) t_nz[i] = segnz[i];
         __syncthreads();
         if (k <= CT_MAX_K1)
-            walk_body<G, true, FULL, 1>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
+            walk_body<G, true, FULL, 1>(t_off, t_coff, t_nz, nnz_seg, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
                                         hub_cnt, wc, xcd, lw, S);
         else
-            walk_body<G, true, FULL, 2>(t_off, t_coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
+            walk_body<G, true, FULL, 2>(t_off, t_coff, t_nz, nnz_seg, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits,
                                         hub_cnt, wc, xcd, lw, S);
     } else {
-        walk_body<G, false, FULL, 0>(off, coff, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt,
+        walk_body<G, false, FULL, 0>(off, coff, nullptr, nseg, nseg, rows, col, n, C, list, hsub, sbase, split_len, hub_bits, hub_cnt,
                                      wc, xcd, lw, S);
     }
     if (trace && __lane_id() == 0) atomicMax(&trace[1], wall_clock64());
@@ -1066,7 +1080,8 @@ __global__ void k_walk_class(const int32_t *__restrict__ rp, const int32_t *__re
 }
 
 typedef void (*walk_fn)(const int2 *, const int32_t *, int32_t, int32_t *, const int32_t *, const int32_t *,
-                        const int32_t *, const int32_t *, const int32_t *, int32_t, unsigned long long *, int32_t *,
+                        const int32_t *, const int32_t *, const int32_t *, const int32_t *, int32_t,
+                        unsigned long long *, int32_t *,
                         unsigned long long *, int32_t, int32_t, uint32_t, uint32_t, unsigned long long *, void *);
 
 template <bool FULL, bool OPT>
@@ -1139,7 +1154,7 @@ static gc_status measure_walk(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool ful
             GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
             GC_HIP(hipMemsetAsync(ctx->scal + S_ERR, 0, 8, s));
             hipLaunchKernelGGL(f, dim3(blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C, ctx->list, ctx->off,
-                               ctx->coff, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2,
+                               ctx->coff, ctx->segnz, ctx->hsub, ctx->sbase, split_len, hub_bits, hub_cnt, ctx->scal, 0, 2,
                                spin_limit, 0u, nullptr, ctx->shadow);
             GC_LAUNCHED();
             gc_status st = gc_sync_scalars(ctx, s);
@@ -1186,7 +1201,8 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
         trace = ctx->trace;
     }
     GC_TIMED(GC_K_WALK, s, hipLaunchKernelGGL(f, dim3(ctx->walk_blocks), dim3(WALK_BLOCK), 0, s, ctx->rows, col, g->n, C,
-                                              ctx->list, ctx->off, ctx->coff, ctx->hsub, ctx->sbase, split_len,
+                                              ctx->list, ctx->off, ctx->coff, ctx->segnz, ctx->hsub, ctx->sbase,
+                                              split_len,
                                               hub_bits, hub_cnt, ctx->scal, xcd, ctx->tune.check_resident,
                                               spin_limit, (uint32_t)ctx->tune.walk_flags, trace, ctx->shadow));
     GC_LAUNCHED();
@@ -1267,7 +1283,7 @@ static gc_status recolor_pass(gc_ctx *ctx, const gc_csr *g, int32_t perm, uint64
     GC_TIMED(GC_K_ORDER, s, order_kernel<<<1, order_threads, 0, s>>>(
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 64 / G, hub_max_rank, ctx->hist,
                                 ctx->histw, ctx->hist_s, ctx->hist_sc, (int32_t *)ctx->keys, ctx->pi, ctx->rank,
-                                ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->hcopy, ctx->scal));
+                                ctx->off, ctx->coff, ctx->cursor, ctx->sbase, ctx->hcopy, ctx->segnz, ctx->scal));
     GC_LAUNCHED();
     static_assert(SCATTER_BLOCK == 256, "scatter tiles share the histogram's block size");
     const int64_t tiles = ((int64_t)n + SCATTER_BLOCK * SCATTER_ITEMS - 1) / (SCATTER_BLOCK * SCATTER_ITEMS);
@@ -1381,7 +1397,7 @@ static gc_status gc_arc_recolor_impl(gc_ctx *ctx, const gc_csr *g, int32_t perm,
                                 ctx->ccap, perm, gc_stream_value(seed, GC_TAG_PERM, (uint32_t)pass), 1,
                                 64 * ctx->tune.hub_words - 1, ctx->hist, ctx->histw, ctx->hist_s, ctx->hist_sc,
                                 (int32_t *)ctx->keys, ctx->pi, ctx->rank, ctx->off, ctx->coff, ctx->cursor, ctx->sbase,
-                                ctx->hcopy, ctx->scal));
+                                ctx->hcopy, ctx->segnz, ctx->scal));
     GC_LAUNCHED();
     int32_t *prank = ctx->list;  // free outside the recoloring walk
     GC_TIMED(GC_K_OTHER, s, k_vertex_rank<<<gc_grid(ctx, n, block), block, 0, s>>>(n, colors_in, ctx->rank, ctx->ccap,
