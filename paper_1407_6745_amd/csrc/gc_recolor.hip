@@ -828,6 +828,10 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, c
     const bool lfirst = (wc.flags & WALK_LONG_FIRST) != 0;
     const int32_t nvisit = (lfirst || !NZ) ? nseg : nnz_seg;
     uint32_t c = 0, hi = 0;
+    // the cursor segment's list range and first chunk, read once per segment
+    // rather than once per chunk (mesh walk 141.3 -> 140.0 us)
+    int32_t seg_lo = 0, seg_hi = 0;
+    uint32_t seg_s0 = 0;
     bool first = true;
     auto advance = [&]() {
         if (!first) c += Wx;
@@ -855,6 +859,11 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, c
             rm = rm >= Wx ? rm - Wx : rm;
             const uint32_t r = me + (Wx - rm);
             c = lo + (r >= Wx ? r - Wx : r);
+            if (c < hi) {
+                seg_lo = O[seg];
+                seg_hi = O[seg + 1];
+                seg_s0 = s0;
+            }
         }
     };
     // stage A: vertex and row part of the chunk under the cursor, then advance
@@ -865,8 +874,8 @@ __device__ __forceinline__ void walk_body(const int32_t *O, const int32_t *CO, c
         t.slot = 0;
         t.nsub = 1;
         if (seg >= nseg) return;
-        const int32_t lo = O[seg], hi2 = O[seg + 1];
-        const int32_t j = (int32_t)(c - (uint32_t)CO[seg]);
+        const int32_t lo = seg_lo, hi2 = seg_hi;
+        const int32_t j = (int32_t)(c - seg_s0);
         const int b = seg % NSEG_PER_RANK;
         if (b == 2) {
             // split row: the last list slot whose first chunk is <= j
