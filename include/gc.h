@@ -117,9 +117,11 @@ typedef struct gc_tuning {
     int32_t grid_per_cu;   /* workgroups per compute unit for grid-stride kernels (1..64) */
     int32_t walk_mode;     /* recoloring class walk: 0 = one persistent launch, waits per dependency;
                               1 = one launch per class (host reads the class count) */
-    int32_t xcd_chunks;    /* persistent walk: 1 (default) = every class's chunks cut into 8 consecutive parts,
-                              part x taken by the workgroups the hardware places on XCD x, so a region of the
-                              vertex order stays in one XCD's L2 across classes; 0 = round robin */
+    int32_t xcd_chunks;    /* persistent walk: 1 = every class's chunks cut into 8 consecutive parts, part x
+                              taken by the workgroups the hardware places on XCD x, so a region of the vertex
+                              order stays in one XCD's L2 across classes; 0 = round robin; -1 (default) = the
+                              parts when at most half the adjacency entries join vertices 32,768 or more apart
+                              in the vertex order (their neighbors share an XCD's L2), else round robin */
     int32_t check_resident;/* persistent walk: verify at start that every workgroup is resident (diagnostic;
                               a failed check makes the call return GC_ERR_DEVICE when it synchronizes) */
     int32_t deg_split;     /* rows longer than both deg_wave and deg_split (0 = never) are scanned by

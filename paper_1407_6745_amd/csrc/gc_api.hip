@@ -78,7 +78,7 @@ extern "C" gc_status gc_ctx_create(int device, int64_t max_n, int64_t max_nnz, g
     ctx->tune.group = 4;
     ctx->tune.grid_per_cu = 8;
     ctx->tune.walk_mode = 0;
-    ctx->tune.xcd_chunks = 1;
+    ctx->tune.xcd_chunks = -1;
     ctx->tune.deg_split = 4096;
     ctx->tune.split_len = 1024;
     ctx->tune.hub_words = GC_HUB_WORDS;
@@ -242,7 +242,7 @@ extern "C" gc_status gc_ctx_set_tuning(gc_ctx *ctx, const gc_tuning *t) {
     if (t->group < 1 || t->group > 64 || (t->group & (t->group - 1))) return gc_fail(ctx, GC_ERR_ARG, "group must be a power of two in [1, 64]");
     if (t->deg_wave < 0) return gc_fail(ctx, GC_ERR_ARG, "deg_wave must be >= 0");
     if (t->walk_mode < 0 || t->walk_mode > 1) return gc_fail(ctx, GC_ERR_ARG, "walk_mode must be 0 or 1");
-    if (t->xcd_chunks < 0) return gc_fail(ctx, GC_ERR_ARG, "xcd_chunks must be >= 0");
+    if (t->xcd_chunks < -1) return gc_fail(ctx, GC_ERR_ARG, "xcd_chunks must be >= -1");
     if (t->check_resident < 0 || t->check_resident > 1) return gc_fail(ctx, GC_ERR_ARG, "check_resident must be 0 or 1");
     if (t->deg_split < 0) return gc_fail(ctx, GC_ERR_ARG, "deg_split must be >= 0");
     if (t->split_len < 64) return gc_fail(ctx, GC_ERR_ARG, "split_len must be >= 64");

@@ -1195,7 +1195,12 @@ static gc_status launch_walk_flow(gc_ctx *ctx, const gc_csr *g, int32_t *C, bool
     // otherwise idle device (kernels of other streams can only delay some
     // workgroups until they finish; the bounded waits keep even that case from
     // hanging).
-    const int32_t xcd = ctx->tune.xcd_chunks > 0 ? 1 : 0;
+    // XCD parts keep a region of the vertex order in one XCD's L2 when
+    // neighbors are near in that order (the mesh: traffic 2.04 -> 1.39x the
+    // algorithmic bytes); with mostly far neighbors there is no such region,
+    // and the parts only unbalance the wavefronts (RMAT-22 walk 2.25 -> 1.93 ms
+    // round robin).  The far fraction comes with the graph's longest row.
+    const int32_t xcd = ctx->tune.xcd_chunks > 0 ? 1 : (ctx->tune.xcd_chunks == 0 ? 0 : (ctx->deg_far <= 0.5 ? 1 : 0));
     if (ctx->tune.check_resident) GC_HIP(hipMemsetAsync(ctx->scal + S_TICKET, 0, 8, s));
     unsigned long long *trace = nullptr;
     if (ctx->tune.trace) {
