@@ -30,6 +30,11 @@
 static_assert(S_REC + 2 * GC_RUN_AHEAD_MAX <= S_COUNT, "round records");
 // loads in flight per lane: whole-wavefront rows are long, so they keep more
 #define ROW_UNROLL(G) ((G) >= 32 ? 8 : GC_UNROLL)
+// The round-0 and assign scans keep eight in flight at every group size: a
+// 27-point mesh row (26 entries on 4 lanes) then takes one batch of loads
+// (mesh initial coloring 0.89 -> 0.85 ms); the detect scan stays at
+// ROW_UNROLL, where eight cost more than they save (detect 0.39 -> 0.48 ms).
+#define SELECT_UNROLL 8
 
 // Tentative color of w in round 0: 1 + its Random-X offset (no color is held yet).
 __device__ inline int32_t round0_color(uint32_t s_color, int32_t w, uint32_t X, bool randx) {
@@ -314,7 +319,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_round0(const int32_t *__restrict
         if (forward) e1 = e0;
         const int32_t tv = v >= 0 ? round0_color(s_color, v, X, randx != 0) : 0;
         const uint64_t pv = v >= 0 ? round_prio(pr, v) : 0u;
-        const bool lose = group_loses<G, true, ROW_UNROLL(G)>(tv, pv, e0, e1, col, C, n, pr, s_color, X, randx != 0);
+        const bool lose = group_loses<G, true, SELECT_UNROLL>(tv, pv, e0, e1, col, C, n, pr, s_color, X, randx != 0);
         const bool leader = (__lane_id() & (G - 1)) == 0 && v >= 0;
         if (leader && !forward) {
             C[v] = lose ? -tv : tv;
@@ -373,7 +378,7 @@ __global__ void __launch_bounds__(INIT_BLOCK) k_assign(const int32_t *__restrict
         int32_t t;
         const int32_t li = (G == 64 && lm.idx && v >= 0) ? lm.idx[v] : -1;  // one row per wavefront: uniform
         if (li >= 0) t = fm_select(lm.fm + (size_t)li * FM_WORDS, j, col, e0, e1, C, n);
-        else t = group_select_wide<G, ROW_UNROLL(G)>(col, e0, e1, CompactRead<CT>::of(S, C), n,
+        else t = group_select_wide<G, SELECT_UNROLL>(col, e0, e1, CompactRead<CT>::of(S, C), n,
                                                            j, lw);
         if (v >= 0 && (__lane_id() & (G - 1)) == 0) {
             C[v] = -t;
