@@ -71,6 +71,10 @@ __device__ inline bool group_loses(int32_t tv, uint64_t pv, int32_t e0, int32_t 
 #pragma unroll
         for (int u = 0; u < UNR; u++)
             if (t[u] == tv && round_prio(pr, w[u]) > pv) lose = true;
+        // one conflict decides: the group reads no more of a loser's row (the
+        // ballot sees only the lanes with entries left, which can only delay
+        // the exit; a row that fits one batch skips it)
+        if (eb + G * UNR < e1 && group_any<G>(lose)) break;
     }
     return group_any<G>(lose);
 }
