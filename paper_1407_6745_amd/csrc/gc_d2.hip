@@ -407,17 +407,26 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_mark(const int32_t *__restrict_
             continue;
         }
         const int32_t sz = e1 - e0 + 1;
-        for (int32_t i = gl; i < sz; i += G) {
-            const int32_t x = i == 0 ? u : col[e0 + i - 1];
-            uint32_t T = 0, key = 0;  // T = 0: not tentative (never matches)
-            if ((uint32_t)x < (uint32_t)n) {
-                const int32_t c = C[x];
-                if (c < 0) {
-                    T = (uint32_t)(-c);
-                    key = (uint32_t)round_prio(pr, x);
-                }
+        // a batch of member ids, then all their colors, then the stage
+        for (int32_t ib = gl; ib < sz; ib += G * D2_ROW_UNROLL) {
+            int32_t x[D2_ROW_UNROLL], c[D2_ROW_UNROLL];
+#pragma unroll
+            for (int k = 0; k < D2_ROW_UNROLL; k++) {
+                const int32_t i = ib + k * G < sz ? ib + k * G : ib;
+                const int32_t y = i == 0 ? u : col[e0 + i - 1];
+                x[k] = ib + k * G < sz && (uint32_t)y < (uint32_t)n ? y : -1;
             }
-            t[i] = ((unsigned long long)T << 32) | key;
+#pragma unroll
+            for (int k = 0; k < D2_ROW_UNROLL; k++) c[k] = C[x[k] >= 0 ? x[k] : u];
+#pragma unroll
+            for (int k = 0; k < D2_ROW_UNROLL; k++) {
+                uint32_t T = 0, key = 0;  // T = 0: not tentative (never matches)
+                if (x[k] >= 0 && c[k] < 0) {
+                    T = (uint32_t)(-c[k]);
+                    key = (uint32_t)round_prio(pr, x[k]);
+                }
+                if (ib + k * G < sz) t[ib + k * G] = ((unsigned long long)T << 32) | key;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
