@@ -436,6 +436,8 @@ __global__ void __launch_bounds__(D2_BLOCK) k_d2_mark(const int32_t *__restrict_
             const uint32_t T = (uint32_t)(me >> 32);
             if (T == 0) continue;
             bool dom = false;
+            // unrolled: the stage reads pipeline (mesh 128^3 step 22.6 -> 21.8 ms)
+#pragma unroll 8
             for (int32_t q = 0; q < sz; q++) {
                 const unsigned long long o = t[q];
                 dom |= (uint32_t)(o >> 32) == T && (uint32_t)o > (uint32_t)me;
